@@ -1,0 +1,227 @@
+"""FP64 CPU oracle of the DIGS deformation-informed Gaussian X-ray renderer.
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package. It shares no code with the HIP library in
+``paper_2506_22280_amd``: the arithmetic lives in ``digs_oracle.c`` (plain C, double precision,
+written from the paper's Eq. 1-11), and this module only marshals numpy arrays into it.
+
+Functions mirror the product's entry points in argument meaning (not in precision):
+  ffd_eval        Eq. 10-11   per-rank u_r(x) and grad u_r(x)
+  deform          Eq. 7-9     mu' and Sigma' for every (t, n)
+  project         Eq. 1,3,6   the closed-form line-integral sum at every pixel, no cut-off
+  project_pixels              the same at a list of sampled pixels
+  project_bwd                 reverse mode of ``project`` for a sparse dL/dI
+  line_integral               one Gaussian along one line
+  dvf, phi        Eq. 9, 6    displacement field and dynamic attenuation at query points
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "digs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("origin", ctypes.c_double * 3),
+                ("spacing", ctypes.c_double * 3)]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("sid", ctypes.c_double), ("sdd", ctypes.c_double), ("nu", ctypes.c_int),
+                ("nv", ctypes.c_int), ("pitch_u", ctypes.c_double),
+                ("pitch_v", ctypes.c_double), ("off_u", ctypes.c_double),
+                ("off_v", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_bspline.argtypes = [ctypes.c_double, _P, _P, _P]
+        lib.oracle_ffd_eval.argtypes = [ctypes.POINTER(Grid), _P, ctypes.c_int, _P, _P, _P]
+        lib.oracle_deform.argtypes = [ctypes.POINTER(Grid), _P, ctypes.c_int, _P, _P, _P,
+                                      ctypes.c_int, _P, _P, _P]
+        lib.oracle_project.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _P,
+                                       ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P]
+        lib.oracle_project.restype = ctypes.c_int
+        lib.oracle_project_pixels.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _P,
+                                              ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P, _P,
+                                              ctypes.c_int, _IP, _IP, _IP, _P]
+        lib.oracle_project_pixels.restype = ctypes.c_int
+        lib.oracle_project_bwd.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _P,
+                                           ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P, _P,
+                                           ctypes.c_int, _IP, _IP, _IP, _P,
+                                           _P, _P, _P, _P, _P, _P]
+        lib.oracle_project_bwd.restype = ctypes.c_int
+        lib.oracle_line_integral.argtypes = [_P, _P, ctypes.c_double, _P, _P]
+        lib.oracle_line_integral.restype = ctypes.c_double
+        lib.oracle_dvf.argtypes = [ctypes.POINTER(Grid), _P, _P, ctypes.c_int, _P, _P]
+        lib.oracle_phi.argtypes = [ctypes.c_int, _P, _P, _P, ctypes.c_int, _P, _P]
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_P)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_IP)
+
+
+def make_grid(grid: dict) -> Grid:
+    g = Grid()
+    g.R, g.nx, g.ny, g.nz = int(grid["R"]), int(grid["nx"]), int(grid["ny"]), int(grid["nz"])
+    for a in range(3):
+        g.origin[a] = float(grid["origin"][a])
+        g.spacing[a] = float(grid["spacing"][a])
+    return g
+
+
+def make_geom(geom: dict) -> Geom:
+    G = Geom()
+    G.sid, G.sdd = float(geom["sid"]), float(geom["sdd"])
+    G.nu, G.nv = int(geom["nu"]), int(geom["nv"])
+    G.pitch_u, G.pitch_v = float(geom["pitch_u"]), float(geom["pitch_v"])
+    G.off_u, G.off_v = float(geom.get("off_u", 0.0)), float(geom.get("off_v", 0.0))
+    return G
+
+
+def bspline(u: float):
+    """B_l(u), B_l'(u), B_l''(u) for l = 0..3 (Eq. 10)."""
+    B = np.zeros(4); dB = np.zeros(4); d2B = np.zeros(4)
+    _load().oracle_bspline(float(u), B.ctypes.data_as(_P), dB.ctypes.data_as(_P),
+                           d2B.ctypes.data_as(_P))
+    return B, dB, d2B
+
+
+def ffd_eval(grid: dict, coef, x):
+    """Per-rank U[R][3][n] = u_r(x) and V[R][9][n] = grad u_r(x) (Eq. 10-11). x is [3][n]."""
+    g = make_grid(grid)
+    coef, pc = _d(coef)
+    x, px = _d(x)
+    n = x.shape[1]
+    U = np.zeros((g.R, 3, n)); V = np.zeros((g.R, 9, n))
+    _load().oracle_ffd_eval(ctypes.byref(g), pc, n, px, U.ctypes.data_as(_P),
+                            V.ctypes.data_as(_P))
+    return U, V
+
+
+def deform(grid: dict, coef, mu, scale, quat, w):
+    """mu_t[T][3][n], cov_t[T][6][n] (xx,xy,xz,yy,yz,zz) after Eq. 7-9; w is [T][R]."""
+    g = make_grid(grid)
+    coef, pc = _d(coef); mu, pm = _d(mu); scale, ps = _d(scale); quat, pq = _d(quat)
+    w, pw = _d(np.atleast_2d(w))
+    n, T = mu.shape[1], w.shape[0]
+    mu_t = np.zeros((T, 3, n)); cov_t = np.zeros((T, 6, n))
+    _load().oracle_deform(ctypes.byref(g), pc, n, pm, ps, pq, T, pw, mu_t.ctypes.data_as(_P),
+                          cov_t.ctypes.data_as(_P))
+    return mu_t, cov_t
+
+
+def project(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w):
+    """proj[T][nv][nu]: the sum of every Gaussian's closed-form line integral (no cut-off)."""
+    G, g = make_geom(geom), make_grid(grid)
+    coef, pc = _d(coef); mu, pm = _d(mu); scale, ps = _d(scale); quat, pq = _d(quat)
+    rho, pr = _d(rho); angles, pa = _d(np.atleast_1d(angles)); w, pw = _d(np.atleast_2d(w))
+    n, T = mu.shape[1], angles.shape[0]
+    assert w.shape == (T, g.R)
+    out = np.zeros((T, G.nv, G.nu))
+    rc = _load().oracle_project(ctypes.byref(G), ctypes.byref(g), pc, n, pm, ps, pq, pr, T, pa,
+                                pw, out.ctypes.data_as(_P))
+    if rc != 0:
+        raise MemoryError("oracle_project failed")
+    return out
+
+
+def project_pixels(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, pt, pj, pi):
+    """The projection value at sampled pixels (pt[k], pj[k], pi[k])."""
+    G, g = make_geom(geom), make_grid(grid)
+    coef, pc = _d(coef); mu, pm = _d(mu); scale, ps = _d(scale); quat, pq = _d(quat)
+    rho, pr = _d(rho); angles, pa = _d(np.atleast_1d(angles)); w, pw = _d(np.atleast_2d(w))
+    pt, ppt = _i(pt); pj, ppj = _i(pj); pi, ppi = _i(pi)
+    n, T = mu.shape[1], angles.shape[0]
+    out = np.zeros(pt.shape[0])
+    rc = _load().oracle_project_pixels(ctypes.byref(G), ctypes.byref(g), pc, n, pm, ps, pq, pr,
+                                       T, pa, pw, pt.shape[0], ppt, ppj, ppi,
+                                       out.ctypes.data_as(_P))
+    if rc != 0:
+        raise MemoryError("oracle_project_pixels failed")
+    return out
+
+
+def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, grad_proj=None,
+                pixels=None):
+    """Gradients of L with dL/dI given densely (grad_proj[T][nv][nu]) or sparsely
+    (pixels = (pt, pj, pi, g)). Returns dict g_mu, g_scale, g_quat, g_rho, g_coef, g_w."""
+    G, g = make_geom(geom), make_grid(grid)
+    coef, pc = _d(coef); mu, pm = _d(mu); scale, ps = _d(scale); quat, pq = _d(quat)
+    rho, pr = _d(rho); angles, pa = _d(np.atleast_1d(angles)); w, pw = _d(np.atleast_2d(w))
+    n, T = mu.shape[1], angles.shape[0]
+    if pixels is None:
+        gp = np.asarray(grad_proj, dtype=np.float64).reshape(T, G.nv, G.nu)
+        pt, pj, pi = np.nonzero(gp)
+        pg = gp[pt, pj, pi]
+    else:
+        pt, pj, pi, pg = pixels
+    pt, ppt = _i(pt); pj, ppj = _i(pj); pi, ppi = _i(pi); pg, ppg = _d(pg)
+    out = dict(g_mu=np.zeros((3, n)), g_scale=np.zeros((3, n)), g_quat=np.zeros((4, n)),
+               g_rho=np.zeros(n), g_coef=np.zeros_like(coef), g_w=np.zeros((T, g.R)))
+    rc = _load().oracle_project_bwd(
+        ctypes.byref(G), ctypes.byref(g), pc, n, pm, ps, pq, pr, T, pa, pw, pt.shape[0], ppt,
+        ppj, ppi, ppg, *[out[k].ctypes.data_as(_P) for k in
+                         ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef", "g_w")])
+    if rc != 0:
+        raise MemoryError("oracle_project_bwd failed")
+    return out
+
+
+def line_integral(mu, cov6, rho, src, direction) -> float:
+    """One Gaussian's integral along the whole line src + lambda * direction."""
+    mu, pm = _d(mu); cov6, pc = _d(cov6); src, ps = _d(src); direction, pd = _d(direction)
+    return float(_load().oracle_line_integral(pm, pc, float(rho), ps, pd))
+
+
+def dvf(grid: dict, coef, w_t, x):
+    """Displacement sum_r w_r u_r(x) at points x[3][m] (Eq. 9), returned as [3][m]."""
+    g = make_grid(grid)
+    coef, pc = _d(coef); w_t, pw = _d(w_t); x, px = _d(x)
+    out = np.zeros((3, x.shape[1]))
+    _load().oracle_dvf(ctypes.byref(g), pc, pw, x.shape[1], px, out.ctypes.data_as(_P))
+    return out
+
+
+def phi(mu_t, cov_t, rho, x):
+    """phi(x) = sum_n rho_n exp(-(x-mu_n)^T Sigma_n^-1 (x-mu_n)/2) (Eq. 2-3, 6) at x[3][m];
+    mu_t [3][n], cov_t [6][n] of one time point."""
+    mu_t, pm = _d(mu_t); cov_t, pc = _d(cov_t); rho, pr = _d(rho); x, px = _d(x)
+    out = np.zeros(x.shape[1])
+    _load().oracle_phi(mu_t.shape[1], pm, pc, pr, x.shape[1], px, out.ctypes.data_as(_P))
+    return out

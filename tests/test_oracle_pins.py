@@ -1,0 +1,472 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: textbook values of the cubic
+B-spline (Eq. 10), closed forms of the FFD for zero / uniform / affine control lattices
+(Eq. 9-11), invariants of the deformation-informed warp (Eq. 7-8), the isotropic closed form
+and brute-force quadrature of the line integral (Eq. 1-4), geometric invariants of the
+projection, and central finite differences plus exact identities for the adjoint.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2506_22280_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------------------------------------
+# B-spline basis (Eq. 10)
+def test_bspline_knot_values(oracle_mod):
+    ref = json.load(open(os.path.join(GOLDEN, "bspline_knots.json")))
+    B, dB, d2B = oracle_mod.bspline(0.0)
+    np.testing.assert_allclose(B, ref["u0"]["B"], atol=1e-15)
+    np.testing.assert_allclose(dB, ref["u0"]["dB"], atol=1e-15)
+    np.testing.assert_allclose(d2B, ref["u0"]["d2B"], atol=1e-15)
+    B, _, _ = oracle_mod.bspline(0.5)
+    np.testing.assert_allclose(B, ref["u_half"]["B"], atol=1e-15)
+
+
+def test_bspline_partition_and_precision(oracle_mod):
+    for u in np.linspace(0.0, 0.999, 37):
+        B, dB, d2B = oracle_mod.bspline(u)
+        assert abs(B.sum() - 1.0) < 1e-14           # partition of unity
+        assert abs(dB.sum()) < 1e-14
+        assert abs(d2B.sum()) < 1e-14
+        l = np.arange(4) - 1.0
+        assert abs((l * B).sum() - u) < 1e-14        # linear precision
+        assert abs((l * l * B).sum() - (u * u + 1.0 / 3.0)) < 1e-14   # quadratic reproduction
+        assert (B >= 0).all()
+
+
+def test_bspline_continuity_and_derivatives(oracle_mod):
+    # C2 continuity across a knot: piece l at u=1 equals piece l-1 at u=0
+    B1, dB1, d2B1 = oracle_mod.bspline(1.0)
+    B0, dB0, d2B0 = oracle_mod.bspline(0.0)
+    np.testing.assert_allclose(B1[1:], B0[:3], atol=1e-15)
+    np.testing.assert_allclose(dB1[1:], dB0[:3], atol=1e-15)
+    np.testing.assert_allclose(d2B1[1:], d2B0[:3], atol=1e-15)
+    assert abs(B1[0]) < 1e-15 and abs(B0[3]) < 1e-15
+    # derivatives against central differences
+    h = 1e-5
+    for u in (0.1, 0.37, 0.8):
+        Bp, dBp, _ = oracle_mod.bspline(u + h)
+        Bm, dBm, _ = oracle_mod.bspline(u - h)
+        _, dB, d2B = oracle_mod.bspline(u)
+        np.testing.assert_allclose((Bp - Bm) / (2 * h), dB, atol=1e-9)
+        np.testing.assert_allclose((dBp - dBm) / (2 * h), d2B, atol=1e-9)
+
+
+# ------------------------------------------------------------------------------------------------
+# FFD (Eq. 9-11)
+def _grid(R=2, n=(7, 6, 5), h=(9.0, 11.0, 13.0), o=(-30.0, -25.0, -28.0)):
+    return dict(R=R, nx=n[0], ny=n[1], nz=n[2], origin=list(o), spacing=list(h))
+
+
+def _inner_points(grid, m, rng):
+    # points whose 4x4x4 stencil lies inside the lattice: p in [1, n-3)
+    lo = [grid["origin"][a] + 1.0 * grid["spacing"][a] for a in range(3)]
+    hi = [grid["origin"][a] + (grid[k] - 3.0) * grid["spacing"][a] - 1e-9
+          for a, k in enumerate(("nx", "ny", "nz"))]
+    return np.stack([rng.uniform(lo[a], hi[a], m) for a in range(3)])
+
+
+def test_ffd_zero_coefficients(oracle_mod):
+    g = _grid()
+    coef = np.zeros((g["R"], g["nz"], g["ny"], g["nx"], 3))
+    x = np.random.default_rng(1).uniform(-60, 60, (3, 50))
+    U, V = oracle_mod.ffd_eval(g, coef, x)
+    assert np.abs(U).max() == 0.0 and np.abs(V).max() == 0.0
+
+
+def test_ffd_uniform_shift_everywhere(oracle_mod):
+    g = _grid()
+    deltas = np.array([[1.5, -2.0, 0.25], [-0.7, 0.3, 4.0]])
+    coef = np.zeros((g["R"], g["nz"], g["ny"], g["nx"], 3))
+    for r in range(g["R"]):
+        coef[r] = deltas[r]
+    # includes points outside the lattice (clamped stencils keep the partition of unity)
+    x = np.random.default_rng(2).uniform(-80, 80, (3, 200))
+    U, V = oracle_mod.ffd_eval(g, coef, x)
+    for r in range(g["R"]):
+        np.testing.assert_allclose(U[r], np.repeat(deltas[r][:, None], 200, 1), atol=1e-13)
+    assert np.abs(V).max() < 1e-13
+
+
+def test_ffd_affine_lattice(oracle_mod):
+    rng = np.random.default_rng(3)
+    g = _grid()
+    A = rng.normal(0, 1, (g["R"], 3, 3))
+    b = rng.normal(0, 1, (g["R"], 3))
+    k, j, i = np.meshgrid(np.arange(g["nz"]), np.arange(g["ny"]), np.arange(g["nx"]),
+                          indexing="ij")
+    idx = np.stack([i, j, k], axis=-1).astype(float)          # (i, j, k) = lattice index
+    coef = np.einsum("rab,zyxb->rzyxa", A, idx) + b[:, None, None, None, :]
+    x = _inner_points(g, 300, rng)
+    U, V = oracle_mod.ffd_eval(g, coef, x)
+    h = np.array(g["spacing"]); o = np.array(g["origin"])
+    p = (x - o[:, None]) / h[:, None]
+    for r in range(g["R"]):
+        np.testing.assert_allclose(U[r], A[r] @ p + b[r][:, None], atol=1e-11)
+        Jr = A[r] / h[None, :]                                 # du_a/dx_b = A_ab / h_b
+        np.testing.assert_allclose(V[r], np.repeat(Jr.reshape(9, 1), x.shape[1], 1), atol=1e-12)
+
+
+def test_ffd_impulse_at_knots(oracle_mod):
+    # one control point set to e_a: at lattice nodes the weights are products of B(0)
+    g = _grid(R=1)
+    coef = np.zeros((1, g["nz"], g["ny"], g["nx"], 3))
+    ci, cj, ck = 3, 2, 2
+    coef[0, ck, cj, ci, 1] = 1.0
+    o = np.array(g["origin"]); h = np.array(g["spacing"])
+
+    def node(i, j, k):
+        return (o + h * np.array([i, j, k]))[:, None]
+
+    U, _ = oracle_mod.ffd_eval(g, coef, node(ci, cj, ck))
+    assert abs(U[0, 1, 0] - 8.0 / 27.0) < 1e-14
+    U, _ = oracle_mod.ffd_eval(g, coef, node(ci + 1, cj, ck))
+    assert abs(U[0, 1, 0] - 2.0 / 27.0) < 1e-14
+    U, _ = oracle_mod.ffd_eval(g, coef, node(ci, cj - 1, ck + 1))
+    assert abs(U[0, 1, 0] - 1.0 / 54.0) < 1e-14
+    U, _ = oracle_mod.ffd_eval(g, coef, node(ci + 2, cj, ck))
+    assert abs(U[0, 1, 0]) < 1e-15
+    assert abs(U[0, 0, 0]) < 1e-15 and abs(U[0, 2, 0]) < 1e-15
+
+
+def test_ffd_jacobian_central_differences(oracle_mod):
+    rng = np.random.default_rng(4)
+    g = _grid()
+    coef = rng.normal(0, 2.0, (g["R"], g["nz"], g["ny"], g["nx"], 3))
+    x = _inner_points(g, 40, rng)
+    _, V = oracle_mod.ffd_eval(g, coef, x)
+    eps = 1e-5
+    for b in range(3):
+        dx = np.zeros((3, 1)); dx[b] = eps
+        Up, _ = oracle_mod.ffd_eval(g, coef, x + dx)
+        Um, _ = oracle_mod.ffd_eval(g, coef, x - dx)
+        fd = (Up - Um) / (2 * eps)                             # [R][3][n]: d u_a / d x_b
+        for a in range(3):
+            np.testing.assert_allclose(V[:, 3 * a + b, :], fd[:, a, :], atol=1e-8)
+
+
+# ------------------------------------------------------------------------------------------------
+# Deformation-informed warp (Eq. 7-8) and the covariance factorisation (Sec. 3.1)
+def _unpack(cov6):
+    xx, xy, xz, yy, yz, zz = cov6
+    return np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+
+
+def test_deform_identity_and_rotation(oracle_mod):
+    rng = np.random.default_rng(5)
+    g = _grid()
+    n = 64
+    mu = rng.uniform(-20, 20, (3, n)); s = rng.uniform(0.5, 4, (3, n))
+    q = rng.normal(0, 1, (4, n))
+    coef = np.zeros((g["R"], g["nz"], g["ny"], g["nx"], 3))
+    w = rng.normal(0, 3, (2, g["R"]))
+    mu_t, cov_t = oracle_mod.deform(g, coef, mu, s, q, w)
+    for t in range(2):
+        np.testing.assert_allclose(mu_t[t], mu, atol=1e-13)
+        for k in range(n):
+            S = _unpack(cov_t[t][:, k])
+            np.testing.assert_allclose(S, S.T, atol=0)
+            ev = np.sort(np.linalg.eigvalsh(S))
+            np.testing.assert_allclose(ev, np.sort(s[:, k] ** 2), rtol=1e-12)
+
+
+def test_deform_quaternion_convention(oracle_mod):
+    # 30 degrees about +z: R = [[c,-s,0],[s,c,0],[0,0,1]] (right-handed, (w,x,y,z) order)
+    g = _grid(R=1)
+    coef = np.zeros((1, g["nz"], g["ny"], g["nx"], 3))
+    th = math.radians(30.0)
+    q = np.array([[math.cos(th / 2)], [0.0], [0.0], [math.sin(th / 2)]]) * 3.0  # unnormalised
+    s = np.array([[3.0], [1.0], [2.0]])
+    _, cov = oracle_mod.deform(g, coef, np.zeros((3, 1)), s, q, np.zeros((1, 1)))
+    Rz = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    np.testing.assert_allclose(_unpack(cov[0][:, 0]), Rz @ np.diag(s[:, 0] ** 2) @ Rz.T,
+                               atol=1e-13)
+    # 90 degrees about +x maps y to z
+    q = np.array([[math.cos(math.pi / 4)], [math.sin(math.pi / 4)], [0.0], [0.0]])
+    _, cov = oracle_mod.deform(g, coef, np.zeros((3, 1)), s, q, np.zeros((1, 1)))
+    np.testing.assert_allclose(_unpack(cov[0][:, 0]), np.diag([9.0, 4.0, 1.0]), atol=1e-13)
+
+
+def test_deform_uniform_shift_and_affine(oracle_mod):
+    rng = np.random.default_rng(6)
+    g = _grid()
+    n = 32
+    mu = _inner_points(g, n, rng); s = rng.uniform(0.5, 4, (3, n)); q = rng.normal(0, 1, (4, n))
+    w = rng.normal(0, 1.5, (3, g["R"]))
+    # uniform shift: translation only
+    deltas = rng.normal(0, 2, (g["R"], 3))
+    coef = np.zeros((g["R"], g["nz"], g["ny"], g["nx"], 3)) + deltas[:, None, None, None, :]
+    zero = np.zeros_like(coef)
+    mu0, cov0 = oracle_mod.deform(g, zero, mu, s, q, w)
+    mu_t, cov_t = oracle_mod.deform(g, coef, mu, s, q, w)
+    for t in range(3):
+        np.testing.assert_allclose(mu_t[t], mu + (w[t] @ deltas)[:, None], atol=1e-12)
+        np.testing.assert_allclose(cov_t[t], cov0[t], atol=1e-12)
+    # affine lattice: K = I + sum_r w_r A_r diag(1/h), Sigma' = K Sigma K^T
+    A = rng.normal(0, 0.05, (g["R"], 3, 3)) * np.array(g["spacing"])[None, None, :]
+    b = rng.normal(0, 1, (g["R"], 3))
+    k, j, i = np.meshgrid(np.arange(g["nz"]), np.arange(g["ny"]), np.arange(g["nx"]),
+                          indexing="ij")
+    idx = np.stack([i, j, k], axis=-1).astype(float)
+    coef = np.einsum("rab,zyxb->rzyxa", A, idx) + b[:, None, None, None, :]
+    mu_t, cov_t = oracle_mod.deform(g, coef, mu, s, q, w)
+    h = np.array(g["spacing"]); o = np.array(g["origin"])
+    p = (mu - o[:, None]) / h[:, None]
+    for t in range(3):
+        K = np.eye(3) + sum(w[t, r] * A[r] / h[None, :] for r in range(g["R"]))
+        disp = sum(w[t, r] * (A[r] @ p + b[r][:, None]) for r in range(g["R"]))
+        np.testing.assert_allclose(mu_t[t], mu + disp, atol=1e-11)
+        for kk in range(n):
+            np.testing.assert_allclose(_unpack(cov_t[t][:, kk]),
+                                       K @ _unpack(cov0[t][:, kk]) @ K.T, atol=1e-11)
+
+
+# ------------------------------------------------------------------------------------------------
+# Line integral of one Gaussian (Eq. 2 integrated along a ray, Eq. 4's quantity)
+def test_line_integral_isotropic_closed_form(oracle_mod):
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        sig = rng.uniform(0.5, 6.0); rho = rng.uniform(0.1, 2)
+        mu = rng.uniform(-20, 20, 3); src = rng.uniform(-500, 500, 3)
+        d = rng.normal(0, 1, 3)
+        dhat = d / np.linalg.norm(d)
+        v = mu - src
+        dperp = np.linalg.norm(v - (v @ dhat) * dhat)
+        ref = rho * sig * math.sqrt(2 * math.pi) * math.exp(-dperp ** 2 / (2 * sig ** 2))
+        cov = [sig ** 2, 0, 0, sig ** 2, 0, sig ** 2]
+        got = oracle_mod.line_integral(mu, cov, rho, src, d)
+        # the plain closed form subtracts c - b^2/a; allow for that in the far tail
+        assert abs(got - ref) <= 1e-12 * (1.0 + dperp ** 2 / sig ** 2) * ref + 1e-300
+
+
+def test_line_integral_quadrature_anisotropic(oracle_mod):
+    rng = np.random.default_rng(8)
+    for _ in range(12):
+        Q, _ = np.linalg.qr(rng.normal(0, 1, (3, 3)))
+        S = Q @ np.diag(rng.uniform(0.5, 5.0, 3) ** 2) @ Q.T
+        mu = rng.uniform(-10, 10, 3); rho = rng.uniform(0.1, 1.0)
+        src = np.array([1000.0, 0.0, 0.0]) + rng.normal(0, 5, 3)
+        tgt = np.array([-500.0, 0.0, 0.0]) + rng.normal(0, 10, 3)
+        d = tgt - src
+        dhat = d / np.linalg.norm(d)
+        # brute force: trapezoid over +-60 mm around the closest approach to mu
+        lam0 = (mu - src) @ dhat
+        lam = np.linspace(lam0 - 60.0, lam0 + 60.0, 200001)
+        pts = src[None, :] + lam[:, None] * dhat[None, :] - mu[None, :]
+        Ai = np.linalg.inv(S)
+        f = rho * np.exp(-0.5 * np.einsum("ka,ab,kb->k", pts, Ai, pts))
+        ref = np.trapezoid(f, lam)
+        cov = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+        got = oracle_mod.line_integral(mu, cov, rho, src, d)
+        assert abs(got - ref) <= 1e-9 * abs(ref) + 1e-14
+
+
+# ------------------------------------------------------------------------------------------------
+# Projection (Eq. 1, 3, 6): geometric invariants of the stated cone-beam convention
+def _single(mu, s, q=(1.0, 0.0, 0.0, 0.0), rho=1.0):
+    return (np.array(mu, float).reshape(3, 1), np.array(s, float).reshape(3, 1),
+            np.array(q, float).reshape(4, 1), np.array([rho], float))
+
+
+def _nomotion(R=1):
+    g = dict(R=R, nx=4, ny=4, nz=4, origin=[-300.0] * 3, spacing=[200.0] * 3)
+    return g, np.zeros((R, 4, 4, 4, 3))
+
+
+def test_projection_peak_location_and_orientation(oracle_mod):
+    geom = synth.geometry(65, 49, 0.5)
+    g, coef = _nomotion()
+    # theta = 0: source on +x, e_u = +y, e_v = +z; magnification SDD/SID = 1.5
+    mu, s, q, rho = _single([0.0, 4.0, -6.0], [0.6, 0.6, 0.6])
+    P = oracle_mod.project(geom, g, coef, mu, s, q, rho, [0.0], np.zeros((1, 1)))[0]
+    j, i = np.unravel_index(np.argmax(P), P.shape)
+    assert i == 32 + round(4.0 * 1.5 / 0.5) and j == 24 + round(-6.0 * 1.5 / 0.5)
+    # theta = 90 deg: source on +y, e_u = -x
+    mu, s, q, rho = _single([5.0, 0.0, 0.0], [0.6, 0.6, 0.6])
+    P = oracle_mod.project(geom, g, coef, mu, s, q, rho, [math.pi / 2], np.zeros((1, 1)))[0]
+    j, i = np.unravel_index(np.argmax(P), P.shape)
+    assert i == 32 - round(5.0 * 1.5 / 0.5) and j == 24
+
+
+def test_projection_rotation_invariance_and_half_turn(oracle_mod):
+    geom = synth.geometry(24, 20, 1.0)
+    g, coef = _nomotion()
+    # isotropic Gaussian at the isocentre: the same projection at every angle
+    mu, s, q, rho = _single([0.0, 0.0, 0.0], [3.0, 3.0, 3.0])
+    ang = np.array([0.0, 0.7, 2.0, 4.1])
+    P = oracle_mod.project(geom, g, coef, mu, s, q, rho, ang, np.zeros((4, 1)))
+    # (the plain closed form cancels c - b^2/a with c ~ (SID/sigma)^2: FP64 keeps ~1e-11 here)
+    for t in range(1, 4):
+        np.testing.assert_allclose(P[t], P[0], rtol=1e-9)
+    # anisotropic Gaussian on the rotation axis, rotated only about z: proj(theta+pi) == proj
+    th = 0.4
+    mu, s, q, rho = _single([0.0, 0.0, 3.0], [4.0, 1.0, 2.0],
+                            (math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)))
+    P = oracle_mod.project(geom, g, coef, mu, s, q, rho, [0.3, 0.3 + math.pi],
+                           np.zeros((2, 1)))
+    np.testing.assert_allclose(P[1], P[0], rtol=1e-10, atol=1e-14)
+    assert not np.allclose(P[0], P[0][:, ::-1])   # anisotropic: not trivially symmetric
+
+
+def test_projection_detector_integral_mass(oracle_mod):
+    # a small centred Gaussian: detector integral ~ M^2 (2 pi)^{3/2} rho s1 s2 s3
+    geom = synth.geometry(160, 160, 0.25)
+    g, coef = _nomotion()
+    s3 = [2.0, 1.5, 1.0]
+    mu, s, q, rho = _single([0.0, 0.0, 0.0], s3, (0.9, 0.2, -0.3, 0.1), 0.7)
+    P = oracle_mod.project(geom, g, coef, mu, s, q, rho, [0.5], np.zeros((1, 1)))[0]
+    M = geom["sdd"] / geom["sid"]
+    ref = M ** 2 * (2 * math.pi) ** 1.5 * 0.7 * np.prod(s3)
+    got = P.sum() * geom["pitch_u"] * geom["pitch_v"]
+    assert abs(got - ref) / ref < 2e-4
+
+
+def test_projection_superposition_and_linearity(oracle_mod):
+    p = synth.tiny(seed=1, n=64, nviews=2, det=16)
+    mu, s, q, rho = p.gaussians()
+    full = oracle_mod.project(p.geom, p.grid, p.coef, mu, s, q, rho, p.angles, p.w)
+    a = oracle_mod.project(p.geom, p.grid, p.coef, mu[:, :20], s[:, :20], q[:, :20], rho[:20],
+                           p.angles, p.w)
+    b = oracle_mod.project(p.geom, p.grid, p.coef, mu[:, 20:], s[:, 20:], q[:, 20:], rho[20:],
+                           p.angles, p.w)
+    np.testing.assert_allclose(full, a + b, rtol=1e-12)
+    twice = oracle_mod.project(p.geom, p.grid, p.coef, mu, s, q, 2.0 * rho.astype(float),
+                               p.angles, p.w)
+    np.testing.assert_allclose(twice, 2 * full, rtol=1e-13)
+
+
+def test_projection_matches_quadrature_with_motion(oracle_mod):
+    """A few pixels of a moving problem against brute-force ray quadrature of phi(x, t) built
+    from the oracle's own deformed Gaussians (pins the ray geometry and the sum)."""
+    p = synth.tiny(seed=2, n=24, nviews=2, det=16)
+    mu, s, q, rho = p.gaussians()
+    P = oracle_mod.project(p.geom, p.grid, p.coef, mu, s, q, rho, p.angles, p.w)
+    mu_t, cov_t = oracle_mod.deform(p.grid, p.coef, mu, s, q, p.w)
+    G = p.geom
+    for t, j, i in [(0, 7, 8), (1, 3, 12), (1, 10, 2)]:
+        th = float(p.angles[t])
+        src = G["sid"] * np.array([math.cos(th), math.sin(th), 0.0])
+        c = (G["sid"] - G["sdd"]) * np.array([math.cos(th), math.sin(th), 0.0])
+        eu = np.array([-math.sin(th), math.cos(th), 0.0]); ev = np.array([0.0, 0.0, 1.0])
+        pix = (c + ((i - (G["nu"] - 1) / 2) * G["pitch_u"]) * eu
+               + ((j - (G["nv"] - 1) / 2) * G["pitch_v"]) * ev)
+        d = (pix - src) / np.linalg.norm(pix - src)
+        lam = np.linspace(900.0, 1100.0, 400001)
+        pts = src[None, :] + lam[:, None] * d[None, :]
+        acc = np.zeros_like(lam)
+        for k in range(mu.shape[1]):
+            Ai = np.linalg.inv(_unpack(cov_t[t][:, k]))
+            x = pts - mu_t[t][:, k][None, :]
+            acc += float(rho[k]) * np.exp(-0.5 * np.einsum("ka,ab,kb->k", x, Ai, x))
+        ref = np.trapezoid(acc, lam)
+        assert abs(P[t, j, i] - ref) <= 1e-8 * max(abs(ref), 1e-3)
+
+
+# ------------------------------------------------------------------------------------------------
+# Adjoint: central differences of the oracle's forward, and exact identities
+def _tiny_grad_problem(seed=11):
+    rng = np.random.default_rng(seed)
+    n = 5
+    g = dict(R=2, nx=6, ny=5, nz=6, origin=[-26.0, -22.0, -27.0], spacing=[10.0, 11.0, 9.0])
+    mu = rng.uniform(-8, 8, (3, n)); mu[:, 0] = [-24.0, 20.0, 15.0]   # clamped stencil
+    s = rng.uniform(1.5, 4.0, (3, n)); q = rng.normal(0, 1, (4, n)); rho = rng.uniform(0.2, 1, n)
+    coef = rng.normal(0, 1.0, (2, 6, 5, 6, 3))
+    geom = synth.geometry(14, 12, 2.5)
+    angles = np.array([0.3, 2.2]); w = rng.normal(0, 1.0, (2, 2))
+    return geom, g, coef, mu, s, q, rho, angles, w
+
+
+def _loss(oracle_mod, geom, g, coef, mu, s, q, rho, angles, w, G):
+    P = oracle_mod.project(geom, g, coef, mu, s, q, rho, angles, w)
+    return float((P * G).sum()), P
+
+
+def test_adjoint_central_differences(oracle_mod):
+    geom, g, coef, mu, s, q, rho, angles, w = _tiny_grad_problem()
+    G = np.random.default_rng(12).normal(0, 1, (2, geom["nv"], geom["nu"]))
+    grads = oracle_mod.project_bwd(geom, g, coef, mu, s, q, rho, angles, w, grad_proj=G)
+    args = dict(coef=coef, mu=mu, s=s, q=q, rho=rho, w=w)
+    names = dict(coef="g_coef", mu="g_mu", s="g_scale", q="g_quat", rho="g_rho", w="g_w")
+    rng = np.random.default_rng(13)
+    for key, gk in names.items():
+        base = args[key]
+        flat = base.ravel()
+        picks = rng.choice(flat.size, size=min(flat.size, 12), replace=False)
+        if key == "coef":   # make sure the clamped Gaussian's stencil corner is probed
+            picks = np.concatenate([picks, [0, 5 * 3 * 6 * 6 - 1]])
+        for p in picks:
+            # Richardson-extrapolated central differences: O(h^4) truncation, and a step large
+            # enough that FP64 rounding of the loss (the plain closed form loses ~5 digits to
+            # c - b^2/a at SID = 1000 mm) stays below 1e-7 of the derivative
+            h = 2e-3 * max(1.0, abs(flat[p]))
+            cd = []
+            for hh in (h, h / 2):
+                vals = []
+                for sgn in (1, -1):
+                    a = {k: v.copy() for k, v in args.items()}
+                    a[key].ravel()[p] += sgn * hh
+                    vals.append(_loss(oracle_mod, geom, g, a["coef"], a["mu"], a["s"], a["q"],
+                                      a["rho"], angles, a["w"], G)[0])
+                cd.append((vals[0] - vals[1]) / (2 * hh))
+            fd = (4.0 * cd[1] - cd[0]) / 3.0
+            an = grads[gk].ravel()[p]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (key, p, fd, an)
+
+
+def test_adjoint_identities(oracle_mod):
+    geom, g, coef, mu, s, q, rho, angles, w = _tiny_grad_problem(seed=21)
+    G = np.random.default_rng(22).normal(0, 1, (2, geom["nv"], geom["nu"]))
+    gr = oracle_mod.project_bwd(geom, g, coef, mu, s, q, rho, angles, w, grad_proj=G)
+    L, _ = _loss(oracle_mod, geom, g, coef, mu, s, q, rho, angles, w, G)
+    # the projection is linear in rho
+    assert abs((gr["g_rho"] * rho).sum() - L) <= 1e-12 * max(1.0, abs(L))
+    # the quaternion is normalised: no gradient along q
+    np.testing.assert_allclose((gr["g_quat"] * q).sum(0), 0.0, atol=1e-12)
+    # one projection: u_r enters only as w_r u_r and is linear in d^r, so
+    # w_r dL/dw_r = sum_ijk d^r . dL/dd^r for every rank
+    gr1 = oracle_mod.project_bwd(geom, g, coef, mu, s, q, rho, angles[:1], w[:1],
+                                 grad_proj=G[:1])
+    for r in range(g["R"]):
+        lhs = w[0, r] * gr1["g_w"][0, r]
+        rhs = (coef[r] * gr1["g_coef"][r]).sum()
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
+
+
+def test_adjoint_sparse_equals_dense(oracle_mod):
+    geom, g, coef, mu, s, q, rho, angles, w = _tiny_grad_problem(seed=31)
+    G = np.zeros((2, geom["nv"], geom["nu"]))
+    G[0, 3, 4] = 1.5; G[1, 7, 9] = -0.5; G[1, 0, 0] = 2.0
+    dense = oracle_mod.project_bwd(geom, g, coef, mu, s, q, rho, angles, w, grad_proj=G)
+    pix = (np.array([1, 0, 1]), np.array([0, 3, 7]), np.array([0, 4, 9]),
+           np.array([2.0, 1.5, -0.5]))
+    sparse = oracle_mod.project_bwd(geom, g, coef, mu, s, q, rho, angles, w, pixels=pix)
+    for k in dense:
+        np.testing.assert_allclose(sparse[k], dense[k], rtol=1e-12, atol=1e-300)
+
+
+# ------------------------------------------------------------------------------------------------
+# Voxel query (Eq. 6, Eq. 9)
+def test_dvf_and_phi(oracle_mod):
+    rng = np.random.default_rng(41)
+    g = _grid()
+    deltas = rng.normal(0, 2, (g["R"], 3))
+    coef = np.zeros((g["R"], g["nz"], g["ny"], g["nx"], 3)) + deltas[:, None, None, None, :]
+    wt = np.array([0.5, -2.0])
+    x = rng.uniform(-20, 20, (3, 30))
+    np.testing.assert_allclose(oracle_mod.dvf(g, coef, wt, x),
+                               np.repeat((wt @ deltas)[:, None], 30, 1), atol=1e-12)
+    # phi of one Gaussian at its mean is rho; one sigma away along a principal axis, rho e^-1/2
+    mu_t = np.array([[1.0], [2.0], [3.0]]); cov = np.array([[4.0], [0.0], [0.0], [9.0], [0.0],
+                                                              [1.0]])
+    pts = np.array([[1.0, 3.0, 1.0, 1.0], [2.0, 2.0, 5.0, 2.0], [3.0, 3.0, 3.0, 3.5]])
+    np.testing.assert_allclose(oracle_mod.phi(mu_t, cov, np.array([0.8]), pts),
+                               [0.8, 0.8 * math.exp(-0.5), 0.8 * math.exp(-0.5),
+                                0.8 * math.exp(-0.125)], rtol=1e-14)
