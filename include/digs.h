@@ -1,0 +1,162 @@
+/*
+ * digs.h -- C ABI of libdigs, the gfx950 (MI355X) implementation of the deformation-informed
+ * Gaussian X-ray renderer of DIGS (Huang et al., "Dynamic CBCT Reconstruction using
+ * Deformation-Informed 4D Gaussian Splatting and a Low-Rank Free-Form Deformation Model").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays.   Every array argument is a DEVICE pointer to float32, C-contiguous, in the
+ *           structure-of-arrays layouts given per argument. Structs (digs_geom, digs_grid,
+ *           digs_tuning, digs_diag) are HOST pointers, read during the call only.
+ * Ownership. The caller owns every buffer. Entry points never allocate device memory, except
+ *           digs_plan_create (which owns the plan's workspace until digs_plan_destroy).
+ *           Outputs are overwritten, gradients included.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null stream). Work is
+ *           enqueued asynchronously; no entry point synchronises unless it says so.
+ * Errors.   0 on success, a negative DIGS_E* code otherwise; nothing else crosses the ABI.
+ *           Conditions that only the kernels can see (instance-list overflow, non-finite
+ *           values, folded deformations, Gaussians at or behind the source) are counted in a
+ *           diagnostics block inside the workspace; read it with digs_read_diagnostics after
+ *           the work has run. An overflow is never silent: the results of that call are then
+ *           incomplete and the call must be repeated with a larger capacity.
+ * Threads.  Calls are re-entrant when their workspaces differ. Calls that share a workspace
+ *           must be ordered on one stream.
+ * Units.    mm, mm^-1 (densities), radians. Quaternions (w,x,y,z), unnormalised (normalised
+ *           inside). Scales are linear standard deviations (mm). Activations of any learned
+ *           parameterisation belong to the caller.
+ *
+ * Symbols used below: N Gaussians, T projections (time points) in a call, R ranks of the
+ * low-rank motion model, (nx, ny, nz) control lattice, (nu, nv) detector columns and rows.
+ */
+#ifndef DIGS_H
+#define DIGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIGS_OK 0
+#define DIGS_EINVAL (-1)   /* null pointer, negative size, R outside 1..8, bad geometry       */
+#define DIGS_ENOWS (-2)    /* workspace missing, misaligned or smaller than required          */
+#define DIGS_EHIP (-3)     /* a HIP launch or runtime call failed (see digs_last_hip_error)    */
+#define DIGS_ECAPACITY (-4) /* instance capacity exceeded (reported by diagnostics checks)     */
+#define DIGS_ENOMEM (-5)   /* digs_plan_create could not allocate                             */
+
+#define DIGS_MAX_RANK 8
+#define DIGS_MAX_TILES 4096 /* detector tiles (16x16 pixels) per projection                   */
+
+/* Cone-beam CT geometry of a circular orbit about z (the paper's acquisition, Sec. 4.1).
+ * View angle theta: source at sid*(cos, sin, 0); detector centre at (sid - sdd)*(cos, sin, 0);
+ * detector axes e_u = (-sin, cos, 0), e_v = (0, 0, 1). Pixel (row j, column i) centre:
+ * centre + (x_i + off_u) e_u + (y_j + off_v) e_v, x_i = (i - (nu-1)/2) pitch_u,
+ * y_j = (j - (nv-1)/2) pitch_v. Projections are stored proj[t][j][i]. */
+typedef struct digs_geom {
+    float sid, sdd;          /* source-isocentre, source-detector distances (mm), sdd > sid > 0 */
+    int nu, nv;              /* detector columns, rows (>0; ceil(nu/16)*ceil(nv/16) <= 4096)  */
+    float pitch_u, pitch_v;  /* pixel pitch (mm, >0)                                           */
+    float off_u, off_v;      /* detector offset along e_u, e_v (mm)                            */
+} digs_geom;
+
+/* Uniform control lattice of the cubic B-spline FFD (Sec. 3.3, Eq. 10): control point (i,j,k)
+ * of rank r sits at origin + (i,j,k)*spacing and stores d^r_ijk. Lattice index space is
+ * 0-based; stencil indices outside the lattice are clamped to its edge. */
+typedef struct digs_grid {
+    int R;                   /* ranks N_r, 1..8                                                */
+    int nx, ny, nz;          /* lattice size (each >= 1)                                        */
+    float origin[3];         /* mm                                                             */
+    float spacing[3];        /* mm, > 0                                                        */
+} digs_grid;
+
+/* Launch tuning; NULL selects the defaults. */
+typedef struct digs_tuning {
+    float cull_radius;       /* Mahalanobis cut-off of each Gaussian's footprint (default 5)   */
+    int64_t capacity;        /* (Gaussian, tile) instances per call (default 16*N*T)           */
+    int splat_waves;         /* forward splat: waves per 16x16 tile, 4 (8x8 each) or 1 (default 4) */
+    int bwd_waves;           /* backward splat: waves per workgroup, 1..4 (default 4)          */
+} digs_tuning;
+
+/* Diagnostics counted by the kernels (read after the work has run). */
+typedef struct digs_diag {
+    uint64_t instances;      /* (Gaussian, tile) instances the last call needed               */
+    uint64_t capacity;       /* capacity of the workspace                                     */
+    uint32_t overflow;       /* nonzero if any call since the last reset exceeded capacity    */
+    uint32_t nonfinite;      /* (t,n) with non-finite inputs or singular K, skipped           */
+    uint32_t folded;         /* (t,n) with det K <= 0 (rendered, counted)                     */
+    uint32_t behind_source;  /* (t,n) whose mean is not in front of the source, skipped       */
+    uint32_t wide;           /* (t,n) whose footprint conic is not an ellipse: whole detector  */
+    uint32_t reserved[7];
+} digs_diag;
+
+/* ---------------------------------------------------------------------------------------------
+ * digs_ffd_eval -- the low-rank cubic B-spline FFD and its Jacobian (Sec. 3.3, Eq. 9-11).
+ *   coef  [R][nz][ny][nx][3]   control displacements d^r (mm per unit weight)
+ *   x     [3][n]               query points (mm)
+ *   w     [T][R] or NULL       temporal weights
+ *   disp  w == NULL: [R][3][n] per-rank u_r(x);  else [T][3][n] sum_r w[t][r] u_r(x)
+ *   jac   w == NULL: [R][9][n] per-rank grad u_r(x);  else [T][9][n] sum_r w[t][r] grad u_r(x)
+ *         (row-major 3x3, jac[.][3a+b][i] = d u_a / d x_b; the identity of Eq. 11 is NOT added)
+ *         jac may be NULL (skipped).
+ * n == 0 is a no-op. Errors: DIGS_EINVAL, DIGS_EHIP. */
+int digs_ffd_eval(const digs_grid *grid, const float *coef, int n, const float *x, int T,
+                  const float *w, float *disp, float *jac, void *stream);
+
+/* digs_deform_gaussians -- the deformation-informed warp (Sec. 3.2, Eq. 7-8): for every
+ * (t, n), mu' = mu + sum_r w_r(t) u_r(mu) and Sigma' = K Sigma K^T with
+ * K = I + sum_r w_r(t) grad u_r(mu), Sigma = R(q) diag(s^2) R(q)^T (Sec. 3.1); rho unchanged.
+ *   mu [3][n], scale [3][n], quat [4][n], w [T][R]
+ *   mu_t [T][3][n];  cov_t [T][6][n] packed (xx, xy, xz, yy, yz, zz)
+ * Errors: DIGS_EINVAL, DIGS_EHIP. */
+int digs_deform_gaussians(const digs_grid *grid, const float *coef, int n, const float *mu,
+                          const float *scale, const float *quat, int T, const float *w,
+                          float *mu_t, float *cov_t, void *stream);
+
+/* Workspace bytes that digs_project_fwd / digs_project_bwd need for this problem size (one
+ * workspace serves both). Returns 0 for invalid arguments. */
+size_t digs_workspace_size(const digs_geom *geom, const digs_grid *grid, int n, int T,
+                           const digs_tuning *tuning);
+
+/* digs_project_fwd -- projections of the deformed Gaussians (Sec. 3.1, Eq. 1, 3, 4, 6):
+ * proj[t][j][i] = sum_n of the integral of G_n(x | rho_n, mu'_{n,t}, Sigma'_{n,t}) along the
+ * whole ray from the source to pixel (j,i) at angle angles[t], each Gaussian cut off beyond
+ * tuning->cull_radius Mahalanobis units of its footprint.
+ *   mu [3][n], scale [3][n], quat [4][n], rho [n]; angles [T]; w [T][R]; proj [T][nv][nu]
+ *   ws / ws_bytes: device workspace of at least digs_workspace_size bytes, 256-byte aligned.
+ * The workspace keeps what digs_project_bwd can reuse (see DIGS_BWD_REUSE_FWD).
+ * n == 0 writes zeros. Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP. */
+int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+                     const float *mu, const float *scale, const float *quat, const float *rho,
+                     int T, const float *angles, const float *w, float *proj, void *ws,
+                     size_t ws_bytes, const digs_tuning *tuning, void *stream);
+
+#define DIGS_BWD_REUSE_FWD 1  /* ws holds the state of a digs_project_fwd with identical inputs */
+
+/* digs_project_bwd -- the hand-written adjoint of digs_project_fwd. Given grad_proj = dL/dproj
+ * [T][nv][nu], writes dL/d(each input):
+ *   g_mu [3][n], g_scale [3][n], g_quat [4][n], g_rho [n], g_coef [R][nz][ny][nx][3], g_w [T][R]
+ * The mean gradient includes the term through K(mu) (second derivatives of the B-spline).
+ * Without DIGS_BWD_REUSE_FWD in `flags` the forward set-up and binning are recomputed.
+ * Reductions are fixed-order: results are bitwise reproducible run to run.
+ * Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP. */
+int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+                     const float *mu, const float *scale, const float *quat, const float *rho,
+                     int T, const float *angles, const float *w, const float *grad_proj,
+                     float *g_mu, float *g_scale, float *g_quat, float *g_rho, float *g_coef,
+                     float *g_w, void *ws, size_t ws_bytes, const digs_tuning *tuning, int flags,
+                     void *stream);
+
+/* Diagnostics of a workspace: digs_read_diagnostics synchronises `stream` and copies the block
+ * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). */
+int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);
+int digs_reset_diagnostics(void *ws, void *stream);
+
+/* Message for a DIGS_E* code; the HIP error code of the last DIGS_EHIP on this thread. */
+const char *digs_strerror(int code);
+int digs_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIGS_H */

@@ -1,0 +1,254 @@
+"""ctypes binding of libdigs (include/digs.h): argument marshalling only.
+
+Every step of the renderer runs in the HIP library; this module converts torch tensors to device
+pointers, geometry/lattice dicts to the C structs, and raises on error codes. If the library is
+missing the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdigs.so")
+
+DIGS_BWD_REUSE_FWD = 1
+_ERRORS = {-1: "DIGS_EINVAL", -2: "DIGS_ENOWS", -3: "DIGS_EHIP", -4: "DIGS_ECAPACITY",
+           -5: "DIGS_ENOMEM"}
+
+
+class DigsError(RuntimeError):
+    def __init__(self, fn, code, hip=0):
+        self.code = code
+        super().__init__("%s failed: %s (%d)%s" % (fn, _ERRORS.get(code, "?"), code,
+                                                    (", hip error %d" % hip) if hip else ""))
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("sid", ctypes.c_float), ("sdd", ctypes.c_float), ("nu", ctypes.c_int),
+                ("nv", ctypes.c_int), ("pitch_u", ctypes.c_float), ("pitch_v", ctypes.c_float),
+                ("off_u", ctypes.c_float), ("off_v", ctypes.c_float)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("origin", ctypes.c_float * 3),
+                ("spacing", ctypes.c_float * 3)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("cull_radius", ctypes.c_float), ("capacity", ctypes.c_int64),
+                ("splat_waves", ctypes.c_int), ("bwd_waves", ctypes.c_int)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
+                ("overflow", ctypes.c_uint32), ("nonfinite", ctypes.c_uint32),
+                ("folded", ctypes.c_uint32), ("behind_source", ctypes.c_uint32),
+                ("wide", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+_VP = ctypes.c_void_p
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "digs_ffd_eval": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.c_int, _VP, ctypes.c_int,
+                                     _VP, _VP, _VP, _VP]),
+    "digs_deform_gaussians": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.c_int, _VP, _VP,
+                                             _VP, ctypes.c_int, _VP, _VP, _VP, _VP]),
+    "digs_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(Geom), ctypes.POINTER(Grid),
+                                              ctypes.c_int, ctypes.c_int,
+                                              ctypes.POINTER(Tuning)]),
+    "digs_project_fwd": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _VP,
+                                        ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
+                                        _VP, _VP, ctypes.c_size_t, ctypes.POINTER(Tuning), _VP]),
+    "digs_project_bwd": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _VP,
+                                        ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
+                                        _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
+                                        ctypes.POINTER(Tuning), ctypes.c_int, _VP]),
+    "digs_read_diagnostics": (ctypes.c_int, [_VP, ctypes.POINTER(Diag), _VP]),
+    "digs_reset_diagnostics": (ctypes.c_int, [_VP, _VP]),
+    "digs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "digs_last_hip_error": (ctypes.c_int, []),
+}
+
+
+def load():
+    """Load libdigs.so (built in-tree by paper_2506_22280_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdigs.so not found at %s: build it with "
+                              "`python -m paper_2506_22280_amd.build` (no CPU fallback exists)"
+                              % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise DigsError(fn, rc, load().digs_last_hip_error() if rc == -3 else 0)
+
+
+def make_geom(g: dict) -> Geom:
+    G = Geom()
+    G.sid, G.sdd = float(g["sid"]), float(g["sdd"])
+    G.nu, G.nv = int(g["nu"]), int(g["nv"])
+    G.pitch_u, G.pitch_v = float(g["pitch_u"]), float(g["pitch_v"])
+    G.off_u, G.off_v = float(g.get("off_u", 0.0)), float(g.get("off_v", 0.0))
+    return G
+
+
+def make_grid(g: dict) -> Grid:
+    G = Grid()
+    G.R, G.nx, G.ny, G.nz = int(g["R"]), int(g["nx"]), int(g["ny"]), int(g["nz"])
+    for a in range(3):
+        G.origin[a] = float(g["origin"][a])
+        G.spacing[a] = float(g["spacing"][a])
+    return G
+
+
+def make_tuning(t: dict | None):
+    if not t:
+        return None
+    T = Tuning()
+    T.cull_radius = float(t.get("cull_radius", 0.0))
+    T.capacity = int(t.get("capacity", 0))
+    T.splat_waves = int(t.get("splat_waves", 0))
+    T.bwd_waves = int(t.get("bwd_waves", 0))
+    return T
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libdigs takes device tensors")
+    if t.dtype != torch.float32 and t.dtype != torch.uint8:
+        raise ValueError("libdigs takes float32 tensors, got %s" % t.dtype)
+    if not t.is_contiguous():
+        raise ValueError("libdigs takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _byref(x):
+    return ctypes.byref(x) if x is not None else None
+
+
+# ------------------------------------------------------------------------------------------------
+def ffd_eval(grid: dict, coef, x, w=None, jac=True, stream=None):
+    """Per-rank (w None) or weighted (w [T][R]) FFD displacement and Jacobian (Eq. 9-11)."""
+    n = x.shape[1]
+    R = grid["R"]
+    lead = R if w is None else w.shape[0]
+    disp = torch.empty((lead, 3, n), device=x.device, dtype=torch.float32)
+    J = torch.empty((lead, 9, n), device=x.device, dtype=torch.float32) if jac else None
+    G = make_grid(grid)
+    _check("digs_ffd_eval", load().digs_ffd_eval(
+        ctypes.byref(G), _ptr(coef), n, _ptr(x), 0 if w is None else w.shape[0], _ptr(w),
+        _ptr(disp), _ptr(J), _stream(stream)))
+    return disp, J
+
+
+def deform_gaussians(grid: dict, coef, mu, scale, quat, w, stream=None):
+    """mu_t [T][3][n], cov_t [T][6][n] of the deformation-informed warp (Eq. 7-8)."""
+    n, T = mu.shape[1], w.shape[0]
+    mu_t = torch.empty((T, 3, n), device=mu.device, dtype=torch.float32)
+    cov_t = torch.empty((T, 6, n), device=mu.device, dtype=torch.float32)
+    G = make_grid(grid)
+    _check("digs_deform_gaussians", load().digs_deform_gaussians(
+        ctypes.byref(G), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat), T, _ptr(w),
+        _ptr(mu_t), _ptr(cov_t), _stream(stream)))
+    return mu_t, cov_t
+
+
+def workspace_size(geom: dict, grid: dict, n: int, T: int, tuning: dict | None = None) -> int:
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    return int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
+
+
+class Workspace:
+    """A device workspace for project_fwd/project_bwd that grows when a call needs more."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def diagnostics(self, stream=None) -> dict:
+        d = Diag()
+        _check("digs_read_diagnostics",
+               load().digs_read_diagnostics(_ptr(self.buf), ctypes.byref(d), _stream(stream)))
+        return d.as_dict()
+
+    def reset(self, stream=None):
+        _check("digs_reset_diagnostics",
+               load().digs_reset_diagnostics(_ptr(self.buf), _stream(stream)))
+
+
+def project_fwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, ws: Workspace,
+                tuning: dict | None = None, proj=None, stream=None):
+    """proj [T][nv][nu] of the deformed Gaussians (Eq. 1, 3, 4, 6)."""
+    n, T = mu.shape[1], angles.shape[0]
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
+    if nbytes == 0:
+        raise DigsError("digs_workspace_size", -1)
+    buf = ws.get(nbytes)
+    if proj is None:
+        proj = torch.empty((T, geom["nv"], geom["nu"]), device=mu.device, dtype=torch.float32)
+    _check("digs_project_fwd", load().digs_project_fwd(
+        ctypes.byref(G), ctypes.byref(R), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat),
+        _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(proj), _ptr(buf), buf.numel(), _byref(Tu),
+        _stream(stream)))
+    return proj
+
+
+def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, grad_proj,
+                ws: Workspace, tuning: dict | None = None, reuse_fwd: bool = False, out=None,
+                stream=None):
+    """dL/d(mu, scale, quat, rho, coef, w) given dL/dproj (hand-written adjoint)."""
+    n, T = mu.shape[1], angles.shape[0]
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
+    if nbytes == 0:
+        raise DigsError("digs_workspace_size", -1)
+    if reuse_fwd and (ws.buf is None or ws.buf.numel() < nbytes):
+        reuse_fwd = False
+    buf = ws.get(nbytes)
+    if out is None:
+        dev = mu.device
+        out = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
+                   g_quat=torch.empty((4, n), device=dev), g_rho=torch.empty((n,), device=dev),
+                   g_coef=torch.empty_like(coef), g_w=torch.empty((T, grid["R"]), device=dev))
+    _check("digs_project_bwd", load().digs_project_bwd(
+        ctypes.byref(G), ctypes.byref(R), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat),
+        _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(grad_proj), _ptr(out["g_mu"]),
+        _ptr(out["g_scale"]), _ptr(out["g_quat"]), _ptr(out["g_rho"]), _ptr(out["g_coef"]),
+        _ptr(out["g_w"]), _ptr(buf), buf.numel(), _byref(Tu),
+        DIGS_BWD_REUSE_FWD if reuse_fwd else 0, _stream(stream)))
+    return out

@@ -1,0 +1,292 @@
+// api.hip -- the extern "C" entry points of libdigs (declared in include/digs.h).
+#include <math.h>
+#include <string.h>
+
+#include "kernels.h"
+
+static thread_local int g_last_hip_error = 0;
+
+int digs_set_hip_error(hipError_t e)
+{
+    g_last_hip_error = (int)e;
+    return DIGS_EHIP;
+}
+
+static int check(hipError_t e) { return e == hipSuccess ? DIGS_OK : digs_set_hip_error(e); }
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static bool grid_ok(const digs_grid *g)
+{
+    return g && g->R >= 1 && g->R <= DIGS_MAX_RANK && g->nx >= 1 && g->ny >= 1 && g->nz >= 1 &&
+           g->spacing[0] > 0.0f && g->spacing[1] > 0.0f && g->spacing[2] > 0.0f &&
+           isfinite(g->origin[0]) && isfinite(g->origin[1]) && isfinite(g->origin[2]) &&
+           (size_t)(g->nx + 4) * (g->ny + 4) * (g->nz + 4) < (1u << 30);
+}
+
+static bool geom_ok(const digs_geom *g)
+{
+    if (!g || !(g->sid > 0.0f) || !(g->sdd > g->sid) || g->nu <= 0 || g->nv <= 0 ||
+        !(g->pitch_u > 0.0f) || !(g->pitch_v > 0.0f) || !isfinite(g->off_u) ||
+        !isfinite(g->off_v) || g->nu > 65535 || g->nv > 65535)
+        return false;
+    const long tx = (g->nu + DIGS_TILE - 1) / DIGS_TILE, ty = (g->nv + DIGS_TILE - 1) / DIGS_TILE;
+    return tx * ty <= DIGS_MAX_TILES;
+}
+
+DevGeom make_dev_geom(const digs_geom *g)
+{
+    DevGeom d;
+    d.sid = g->sid;
+    d.sdd = g->sdd;
+    d.nu = g->nu;
+    d.nv = g->nv;
+    d.pitch_u = g->pitch_u;
+    d.pitch_v = g->pitch_v;
+    d.off_u = g->off_u;
+    d.off_v = g->off_v;
+    d.tiles_x = (g->nu + DIGS_TILE - 1) / DIGS_TILE;
+    d.tiles_y = (g->nv + DIGS_TILE - 1) / DIGS_TILE;
+    d.ntiles = d.tiles_x * d.tiles_y;
+    return d;
+}
+
+DevGrid make_dev_grid(const digs_grid *g)
+{
+    DevGrid d;
+    d.R = g->R;
+    d.nx = g->nx;
+    d.ny = g->ny;
+    d.nz = g->nz;
+    d.ox = g->origin[0];
+    d.oy = g->origin[1];
+    d.oz = g->origin[2];
+    d.hx = g->spacing[0];
+    d.hy = g->spacing[1];
+    d.hz = g->spacing[2];
+    return d;
+}
+
+static int64_t default_capacity(int n, int T) { return (int64_t)16 * n * T + 4096; }
+
+bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
+               const digs_tuning *tuning, WsLayout *L)
+{
+    if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0) return false;
+    memset(L, 0, sizeof(*L));
+    const DevGeom G = make_dev_geom(geom);
+    L->n = n;
+    L->T = T;
+    L->R = grid->R;
+    L->nblk = (n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS;
+    L->ntiles = G.ntiles;
+    L->ncells = (grid->nx + 4) * (grid->ny + 4) * (grid->nz + 4);
+    L->gq_stride = 6 + 12 * grid->R;
+    int64_t cap = (tuning && tuning->capacity > 0) ? tuning->capacity : default_capacity(n, T);
+    if (cap > 0xFFFFFF00ll) cap = 0xFFFFFF00ll;   // list positions are 32-bit
+    L->cap = (size_t)cap;
+    const size_t N = (size_t)(n > 0 ? n : 1), TN = (size_t)(T > 0 ? T : 1) * N;
+    const size_t cnt_elems = (size_t)(T > 0 ? T : 1) * G.ntiles * (L->nblk > 0 ? L->nblk : 1) + 1;
+    const int nblk_r = (int)((N + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS);
+    size_t sc = scan_scratch_elems(cnt_elems);
+    size_t s2 = scan_scratch_elems(TN), s3 = scan_scratch_elems((size_t)256 * nblk_r);
+    if (s2 > sc) sc = s2;
+    if (s3 > sc) sc = s3;
+    L->scratch_elems = sc;
+    const int nparts = (int)((N + 255) / 256) * 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L->diag = take(sizeof(DiagBlock));
+    L->uv = take(sizeof(float) * 12 * grid->R * N);
+    L->rec = take(sizeof(float) * DIGS_REC_FLOATS * TN);
+    L->rect = take(sizeof(int) * 2 * TN);
+    L->gcount = take(sizeof(uint32_t) * TN);
+    L->cnt = take(sizeof(uint32_t) * cnt_elems);
+    L->scratch = take(sizeof(uint32_t) * sc);
+    L->list = take(sizeof(uint32_t) * L->cap);
+    L->inv = take(sizeof(uint32_t) * L->cap);
+    L->part = take(sizeof(float) * DIGS_PART_FLOATS * L->cap);
+    L->gwpart = take(sizeof(float) * (size_t)(T > 0 ? T : 1) * grid->R * nparts);
+    L->keys_a = take(sizeof(uint32_t) * N);
+    L->vals_a = take(sizeof(uint32_t) * N);
+    L->keys_b = take(sizeof(uint32_t) * N);
+    L->vals_b = take(sizeof(uint32_t) * N);
+    L->rhist = take(sizeof(uint32_t) * 256 * (size_t)nblk_r);
+    L->cell_lo = take(sizeof(uint32_t) * L->ncells);
+    L->cell_hi = take(sizeof(uint32_t) * L->ncells);
+    L->pos_of = take(sizeof(uint32_t) * N);
+    L->gq = take(sizeof(float) * L->gq_stride * N);
+    L->total = off;
+    return true;
+}
+
+extern "C" size_t digs_workspace_size(const digs_geom *geom, const digs_grid *grid, int n, int T,
+                                      const digs_tuning *tuning)
+{
+    WsLayout L;
+    if (!ws_layout(geom, grid, n, T, tuning, &L)) return 0;
+    return L.total;
+}
+
+extern "C" int digs_ffd_eval(const digs_grid *grid, const float *coef, int n, const float *x,
+                             int T, const float *w, float *disp, float *jac, void *stream)
+{
+    if (!grid_ok(grid) || n < 0) return DIGS_EINVAL;
+    if (n == 0) return DIGS_OK;
+    if (!coef || !x || !disp || (w && T <= 0)) return DIGS_EINVAL;
+    return check(launch_ffd_eval(make_dev_grid(grid), coef, n, x, w ? T : 0, w, disp, jac,
+                                 (hipStream_t)stream));
+}
+
+extern "C" int digs_deform_gaussians(const digs_grid *grid, const float *coef, int n,
+                                     const float *mu, const float *scale, const float *quat,
+                                     int T, const float *w, float *mu_t, float *cov_t,
+                                     void *stream)
+{
+    if (!grid_ok(grid) || n < 0 || T < 0) return DIGS_EINVAL;
+    if (n == 0 || T == 0) return DIGS_OK;
+    if (!coef || !mu || !scale || !quat || !w || !mu_t || !cov_t) return DIGS_EINVAL;
+    return check(launch_deform(make_dev_grid(grid), coef, n, mu, scale, quat, T, w, mu_t, cov_t,
+                               (hipStream_t)stream));
+}
+
+static int prepare(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+                   const float *mu, const float *scale, const float *quat, const float *rho,
+                   int T, const float *angles, const float *w, void *ws, size_t ws_bytes,
+                   const digs_tuning *tuning, RenderArgs *a)
+{
+    if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0) return DIGS_EINVAL;
+    if (tuning && (tuning->capacity < 0 || !(tuning->cull_radius >= 0.0f) ||
+                   (tuning->splat_waves != 0 && tuning->splat_waves != 1 &&
+                    tuning->splat_waves != 4) ||
+                   tuning->bwd_waves < 0 || tuning->bwd_waves > 4))
+        return DIGS_EINVAL;
+    if (T > 0 && n > 0 && (!coef || !mu || !scale || !quat || !rho || !angles || !w))
+        return DIGS_EINVAL;
+    if (!ws_layout(geom, grid, n, T, tuning, &a->L)) return DIGS_EINVAL;
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < a->L.total) return DIGS_ENOWS;
+    a->geom = make_dev_geom(geom);
+    a->grid = make_dev_grid(grid);
+    a->coef = coef;
+    a->mu = mu;
+    a->scale = scale;
+    a->quat = quat;
+    a->rho = rho;
+    a->angles = angles;
+    a->w = w;
+    a->n = n;
+    a->T = T;
+    a->cull = (tuning && tuning->cull_radius > 0.0f) ? tuning->cull_radius : 5.0f;
+    a->splat_waves = (tuning && tuning->splat_waves) ? tuning->splat_waves : 4;
+    a->bwd_waves = (tuning && tuning->bwd_waves) ? tuning->bwd_waves : 4;
+    a->ws = (char *)ws;
+    return DIGS_OK;
+}
+
+extern "C" int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *coef,
+                                int n, const float *mu, const float *scale, const float *quat,
+                                const float *rho, int T, const float *angles, const float *w,
+                                float *proj, void *ws, size_t ws_bytes,
+                                const digs_tuning *tuning, void *stream)
+{
+    RenderArgs a;
+    int rc = prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
+                     tuning, &a);
+    if (rc) return rc;
+    if (T == 0) return DIGS_OK;
+    if (!proj) return DIGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return check(render_zero(proj, (size_t)T * geom->nu * geom->nv, s));
+    hipError_t e = render_forward_setup(a, s);
+    if (e == hipSuccess) e = render_forward_splat(a, proj, s);
+    return check(e);
+}
+
+extern "C" int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, const float *coef,
+                                int n, const float *mu, const float *scale, const float *quat,
+                                const float *rho, int T, const float *angles, const float *w,
+                                const float *grad_proj, float *g_mu, float *g_scale,
+                                float *g_quat, float *g_rho, float *g_coef, float *g_w, void *ws,
+                                size_t ws_bytes, const digs_tuning *tuning, int flags,
+                                void *stream)
+{
+    RenderArgs a;
+    int rc = prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
+                     tuning, &a);
+    if (rc) return rc;
+    if (!g_coef || (n > 0 && (!g_mu || !g_scale || !g_quat || !g_rho)) ||
+        (T > 0 && (!g_w || (n > 0 && !grad_proj))))
+        return DIGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t ncoef = (size_t)grid->R * grid->nx * grid->ny * grid->nz * 3;
+    hipError_t e = hipSuccess;
+    if (n == 0 || T == 0) {
+        e = render_zero(g_coef, ncoef, s);
+        if (e == hipSuccess && T > 0) e = render_zero(g_w, (size_t)T * grid->R, s);
+        if (e == hipSuccess && n > 0) {
+            e = render_zero(g_mu, (size_t)3 * n, s);
+            if (e == hipSuccess) e = render_zero(g_scale, (size_t)3 * n, s);
+            if (e == hipSuccess) e = render_zero(g_quat, (size_t)4 * n, s);
+            if (e == hipSuccess) e = render_zero(g_rho, (size_t)n, s);
+        }
+        return check(e);
+    }
+    if (!(flags & DIGS_BWD_REUSE_FWD)) e = render_forward_setup(a, s);
+    if (e == hipSuccess)
+        e = render_backward(a, grad_proj, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    return check(e);
+}
+
+extern "C" int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream)
+{
+    if (!ws || !out) return DIGS_EINVAL;
+    DiagBlock d;
+    hipError_t e = hipMemcpyAsync(&d, ws, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return digs_set_hip_error(e);
+    memset(out, 0, sizeof(*out));
+    out->instances = d.instances;
+    out->capacity = d.capacity;
+    out->overflow = d.overflow;
+    out->nonfinite = d.nonfinite;
+    out->folded = d.folded;
+    out->behind_source = d.behind_source;
+    out->wide = d.wide;
+    return DIGS_OK;
+}
+
+__global__ void k_diag_reset(DiagBlock *d)
+{
+    d->instances = 0;
+    d->overflow = 0;
+    d->nonfinite = 0;
+    d->folded = 0;
+    d->behind_source = 0;
+    d->wide = 0;
+}
+
+extern "C" int digs_reset_diagnostics(void *ws, void *stream)
+{
+    if (!ws) return DIGS_EINVAL;
+    hipLaunchKernelGGL(k_diag_reset, dim3(1), dim3(1), 0, (hipStream_t)stream, (DiagBlock *)ws);
+    return check(hipGetLastError());
+}
+
+extern "C" const char *digs_strerror(int code)
+{
+    switch (code) {
+    case DIGS_OK: return "ok";
+    case DIGS_EINVAL: return "invalid argument";
+    case DIGS_ENOWS: return "workspace missing, misaligned or too small";
+    case DIGS_EHIP: return "HIP runtime error";
+    case DIGS_ECAPACITY: return "instance capacity exceeded";
+    case DIGS_ENOMEM: return "out of device memory";
+    default: return "unknown error";
+    }
+}
+
+extern "C" int digs_last_hip_error(void) { return g_last_hip_error; }

@@ -1,0 +1,65 @@
+// kernels.h -- internal interface between the libdigs entry points and their kernels.
+#pragma once
+
+#include "common.h"
+
+// ------------------------------------------------------------------------------------------
+// Workspace layout of digs_project_fwd / digs_project_bwd (byte offsets, 256-byte aligned).
+struct WsLayout {
+    size_t diag;       // DiagBlock
+    size_t uv;         // [3R + 9R][N] f32: per-rank u_r(mu), grad u_r(mu) at the canonical means
+    size_t rec;        // [T][N][16] f32 projected records
+    size_t rect;       // [T][N] int2 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
+    size_t gcount;     // [T][N] u32 tiles per (t,n), scanned in place to instance offsets
+    size_t cnt;        // [T][ntiles][nblk] u32 per-block tile counts, scanned in place
+    size_t scratch;    // scan block sums
+    size_t list;       // [cap] u32 Gaussian index of each instance, grouped by (t, tile)
+    size_t inv;        // [cap] u32 list position of instance (t, n, k) at gcount[t][n] + k
+    size_t part;       // [cap][12] f32 backward partial sums per instance
+    size_t gwpart;     // [T][R][4*ceil(N/256)] f32 per-wave partial sums of dL/dw
+    size_t keys_a, vals_a, keys_b, vals_b;  // [N] u32 cell sort ping-pong
+    size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
+    size_t cell_lo, cell_hi;                // [ncells] u32 range of each lattice cell
+    size_t pos_of;     // [N] u32 position of Gaussian n in cell order
+    size_t gq;         // [N][6 + 12R] f32 per-Gaussian coefficient-gradient sources, cell order
+    size_t total;
+    // derived sizes
+    int n, T, R, nblk, ntiles, ncells, gq_stride;
+    size_t cap;
+    size_t scratch_elems;
+};
+
+bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
+               const digs_tuning *tuning, WsLayout *L);
+
+DevGeom make_dev_geom(const digs_geom *g);
+DevGrid make_dev_grid(const digs_grid *g);
+
+// scan.hip
+size_t scan_scratch_elems(size_t n);
+hipError_t launch_exclusive_scan(uint32_t *data, size_t n, uint32_t *scratch, hipStream_t s);
+
+// ffd.hip
+hipError_t launch_ffd_eval(const DevGrid &g, const float *coef, int n, const float *x, int T,
+                           const float *w, float *disp, float *jac, hipStream_t s);
+hipError_t launch_deform(const DevGrid &g, const float *coef, int n, const float *mu,
+                         const float *scale, const float *quat, int T, const float *w,
+                         float *mu_t, float *cov_t, hipStream_t s);
+
+// render.hip
+struct RenderArgs {
+    DevGeom geom;
+    DevGrid grid;
+    const float *coef, *mu, *scale, *quat, *rho, *angles, *w;
+    int n, T;
+    float cull;
+    int splat_waves, bwd_waves;
+    char *ws;
+    WsLayout L;
+};
+hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s);   // a1-a4
+hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s);  // a5
+hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
+                           float *g_scale, float *g_quat, float *g_rho, float *g_coef,
+                           float *g_w, hipStream_t s);                   // a6-a8
+hipError_t render_zero(float *p, size_t count, hipStream_t s);

@@ -1,0 +1,1076 @@
+// render.hip -- forward and backward of the deformation-informed Gaussian X-ray renderer.
+//
+// Forward (per call of T projections):
+//   k_ffd_canonical  u_r, grad u_r at every canonical mean (Eq. 10-11), once per call
+//   k_setup          per (t, n): the warp of Eq. 7-9 (mu', Sigma' = M M^T, M = K R diag(s)) and
+//                    the projected record of the Gaussian's exact line integral (see below),
+//                    its cut-off bounding box and the detector tiles it touches
+//   k_bin_count/fill per projection, lists of Gaussians per 16x16 tile (bin.h)
+//   k_splat_fwd      one workgroup per (projection, tile), one wave per 8x8 pixel block, one
+//                    lane per pixel; records are read with scalar loads; every pixel is written
+//                    once (no atomics)
+// Backward:
+//   k_splat_bwd      one lane per (Gaussian, tile) instance looping over the tile's 256 pixels,
+//                    accumulating 12 moment sums; written per instance (no atomics)
+//   k_gauss_bwd      per Gaussian, over the call's projections: sums its instances, runs the
+//                    set-up and warp adjoints, reduces to the canonical parameters, and emits the
+//                    per-wave partial sums of dL/dw and the sources of dL/dcoef
+//   k_cell_*         stable radix sort of the Gaussians by lattice cell
+//   k_coef_grad      each control point gathers from the Gaussians of its 4x4x4 cells
+//
+// The exact line integral of one Gaussian (Eq. 2 along the ray of Eq. 1, the quantity that
+// Eq. 4 approximates) is evaluated in a whitened, cancellation-free form: with W = M^-1,
+// m = source - mu', m_w = W m, the centre ray through mu' meeting the detector at pixel
+// coordinates (us, vs), D_u = W e_u pitch_u, D_v = W e_v pitch_v, and delta = (i - us, j - vs),
+//   I_ij = |e_ij| amp q^-1/2 exp(-E / (2 q)),
+//   q = 1 + 2 g.delta + delta^T G delta,  E = delta^T H delta,
+//   H = beta^2 D_perp^T D_perp,  g = -beta (m_w.D)/c,  G = beta^2 D^T D / c,
+//   amp = rho sqrt(2 pi) beta / sqrt(c),  beta = (n.m)/SDD, c = |m_w|^2,
+// where D_perp removes the m_w component. This equals rho |e| sqrt(2 pi / a) exp(-(c - b^2/a)/2)
+// of the plain closed form without subtracting two large numbers.
+#include "bin.h"
+#include "ffd_device.h"
+#include "kernels.h"
+
+#define SETUP_TCHUNK 8
+#define SQRT_2PI 2.5066282746310002f
+#define C2_EXP2 (-0.72134752044448170f)   // -log2(e)/2
+#define LN2 0.69314718055994531f
+
+// ------------------------------------------------------------------------------------------
+// Diagnostics and small fills
+__global__ void k_diag_begin(DiagBlock *d, unsigned long long cap, uint32_t *cnt_last)
+{
+    d->instances = 0;
+    d->capacity = cap;
+    *cnt_last = 0;
+}
+
+__global__ void k_diag_check(DiagBlock *d)
+{
+    if (d->instances > d->capacity) d->overflow = 1u;
+}
+
+__global__ void k_fill_f32(float *p, size_t count, float v)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t v)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t render_zero(float *p, size_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    unsigned blocks = (unsigned)(((count + 255) / 256) < 65536 ? ((count + 255) / 256) : 65536);
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, count, 0.0f);
+    return hipGetLastError();
+}
+
+static hipError_t fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    unsigned blocks = (unsigned)(((count + 255) / 256) < 65536 ? ((count + 255) / 256) : 65536);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// a1: FFD at the canonical means, uv = [U (R x 3) ; V (R x 9)] x N
+__global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *__restrict__ coef,
+                                                       int n, const float *__restrict__ mu,
+                                                       float *__restrict__ uv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Stencil st;
+    make_stencil(g, mu[i], mu[n + i], mu[2 * n + i], st, false);
+    float *U = uv, *V = uv + (size_t)3 * g.R * n;
+    for (int r = 0; r < g.R; ++r) {
+        float u[3], J[9];
+        ffd_rank(g, coef, r, st, u, J);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) U[((size_t)r * 3 + a) * n + i] = u[a];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) V[((size_t)r * 9 + k) * n + i] = J[k];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-(t,n) geometry shared by the set-up and its adjoint.
+struct ViewTrig {
+    float ct, st;
+};
+
+struct SetupFwd {
+    // deformation
+    float K[9], Kinv[9], detK, mup[3], W[9];
+    // projection set-up
+    float alpha, xu, xv, m[3], mw[3], Du[3], Dv[3], c, ic, pa, pb, Dup[3], Dvp[3], beta, kap;
+    float Huu, Huv, Hvv, gu, gv, Guu, Guv, Gvv, amp, us, vs;
+    bool ok;
+};
+
+__device__ __forceinline__ float dot3(const float *a, const float *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// R = R(q_hat) row-major, RS = R diag(s); U [R][3], V [R][9], w [R]
+template <int NR>
+__device__ __forceinline__ void setup_forward(const DevGeom &G, const float *mu0,
+                                              const float *inv_s, const float *Rm,
+                                              const float (*U)[3], const float (*V)[9],
+                                              const float *wt, float rho, ViewTrig vt,
+                                              SetupFwd &f)
+{
+    // Eq. 9 and 11: mu' = mu + sum_r w_r u_r(mu), K = I + sum_r w_r grad u_r(mu)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f.K[k] = (k % 4 == 0) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f.mup[a] = mu0[a];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f.mup[a] = fmaf(wt[r], U[r][a], f.mup[a]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f.K[k] = fmaf(wt[r], V[r][k], f.K[k]);
+    }
+    f.detK = inv3(f.K, f.Kinv);
+    // W = M^-1 = diag(1/s) R^T K^-1 (Eq. 8 with Sigma = R S S^T R^T)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            f.W[3 * a + b] = inv_s[a] * (Rm[a] * f.Kinv[b] + Rm[3 + a] * f.Kinv[3 + b] +
+                                         Rm[6 + a] * f.Kinv[6 + b]);
+    const float ct = vt.ct, st = vt.st;
+    f.alpha = G.sid - (ct * f.mup[0] + st * f.mup[1]);
+    f.xu = st * f.mup[0] - ct * f.mup[1];
+    f.xv = -f.mup[2];
+    f.ok = isfinite(f.detK) && f.detK != 0.0f && f.alpha > 1e-3f * G.sid;
+    const float ia = 1.0f / f.alpha;
+    f.us = (-G.sdd * f.xu * ia - G.off_u) / G.pitch_u + 0.5f * (float)(G.nu - 1);
+    f.vs = (-G.sdd * f.xv * ia - G.off_v) / G.pitch_v + 0.5f * (float)(G.nv - 1);
+    f.m[0] = G.sid * ct - f.mup[0];
+    f.m[1] = G.sid * st - f.mup[1];
+    f.m[2] = -f.mup[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float *Wa = f.W + 3 * a;
+        f.mw[a] = Wa[0] * f.m[0] + Wa[1] * f.m[1] + Wa[2] * f.m[2];
+        f.Du[a] = G.pitch_u * (-st * Wa[0] + ct * Wa[1]);
+        f.Dv[a] = G.pitch_v * Wa[2];
+    }
+    f.c = dot3(f.mw, f.mw);
+    f.ic = 1.0f / f.c;
+    f.pa = dot3(f.mw, f.Du) * f.ic;
+    f.pb = dot3(f.mw, f.Dv) * f.ic;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f.Dup[a] = f.Du[a] - f.pa * f.mw[a];
+        f.Dvp[a] = f.Dv[a] - f.pb * f.mw[a];
+    }
+    f.beta = f.alpha / G.sdd;
+    f.kap = f.beta * f.beta;
+    f.Huu = f.kap * dot3(f.Dup, f.Dup);
+    f.Huv = f.kap * dot3(f.Dup, f.Dvp);
+    f.Hvv = f.kap * dot3(f.Dvp, f.Dvp);
+    f.gu = -f.beta * f.pa;
+    f.gv = -f.beta * f.pb;
+    f.Guu = f.kap * dot3(f.Du, f.Du) * f.ic;
+    f.Guv = f.kap * dot3(f.Du, f.Dv) * f.ic;
+    f.Gvv = f.kap * dot3(f.Dv, f.Dv) * f.ic;
+    f.amp = rho * SQRT_2PI * f.beta * sqrtf(f.ic);
+    f.ok = f.ok && isfinite(f.us) && isfinite(f.vs) && isfinite(f.Huu) && isfinite(f.Huv) &&
+           isfinite(f.Hvv) && isfinite(f.Guu) && isfinite(f.Guv) && isfinite(f.Gvv) &&
+           isfinite(f.amp) && isfinite(f.gu) && isfinite(f.gv);
+}
+
+// Bounding box (inclusive pixel ranges, clamped to the detector) of the cut-off footprint
+// {delta : E/q <= r^2} = {delta^T (H - r^2 G) delta - 2 r^2 g.delta - r^2 <= 0}.
+// Returns false when the conic is not an ellipse (then the box is the whole detector).
+__device__ __forceinline__ bool footprint_box(const DevGeom &G, const SetupFwd &f, float r,
+                                              int &x0, int &x1, int &y0, int &y1)
+{
+    const float r2 = r * r;
+    const float b00 = f.Huu - r2 * f.Guu, b01 = f.Huv - r2 * f.Guv, b11 = f.Hvv - r2 * f.Gvv;
+    const float det = b00 * b11 - b01 * b01;
+    if (!(b00 > 0.0f && det > 0.0f)) {
+        x0 = 0; x1 = G.nu - 1; y0 = 0; y1 = G.nv - 1;
+        return false;
+    }
+    const float id = 1.0f / det;
+    const float i00 = b11 * id, i01 = -b01 * id, i11 = b00 * id;
+    const float cu = r2 * (i00 * f.gu + i01 * f.gv), cv = r2 * (i01 * f.gu + i11 * f.gv);
+    const float k2 = r2 + (f.gu * cu + f.gv * cv) * r2;
+    const float hu = sqrtf(fmaxf(k2 * i00, 0.0f)), hv = sqrtf(fmaxf(k2 * i11, 0.0f));
+    const float lo_u = f.us + cu - hu - 1e-3f, hi_u = f.us + cu + hu + 1e-3f;
+    const float lo_v = f.vs + cv - hv - 1e-3f, hi_v = f.vs + cv + hv + 1e-3f;
+    // clamp in float before converting (boxes far off the detector stay empty)
+    x0 = (int)ceilf(fminf(fmaxf(lo_u, -1.0f), (float)G.nu));
+    x1 = (int)floorf(fminf(fmaxf(hi_u, -1.0f), (float)G.nu));
+    y0 = (int)ceilf(fminf(fmaxf(lo_v, -1.0f), (float)G.nv));
+    y1 = (int)floorf(fminf(fmaxf(hi_v, -1.0f), (float)G.nv));
+    x0 = max(x0, 0); y0 = max(y0, 0);
+    x1 = min(x1, G.nu - 1); y1 = min(y1, G.nv - 1);
+    return true;
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
+                                               const float *__restrict__ mu,
+                                               const float *__restrict__ scale,
+                                               const float *__restrict__ quat,
+                                               const float *__restrict__ rho,
+                                               const float *__restrict__ angles,
+                                               const float *__restrict__ w,
+                                               const float *__restrict__ uv, float cull,
+                                               float4 *__restrict__ rec,
+                                               int2 *__restrict__ rect,
+                                               uint32_t *__restrict__ gcount,
+                                               DiagBlock *__restrict__ diag)
+{
+    __shared__ unsigned long long wsum[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const int ii = valid ? i : 0;
+    float mu0[3], s[3], q[4], Rm[9], inv_s[3];
+    float U[NR][3], V[NR][9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mu0[a] = mu[(size_t)a * n + ii];
+        s[a] = scale[(size_t)a * n + ii];
+        inv_s[a] = 1.0f / s[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + ii];
+    const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    quat_to_rot(q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn, Rm);
+    const float rh = rho[ii];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) U[r][a] = uv[((size_t)r * 3 + a) * n + ii];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
+    }
+    bool inputs_ok = isfinite(mu0[0]) && isfinite(mu0[1]) && isfinite(mu0[2]) && s[0] > 0.0f &&
+                     s[1] > 0.0f && s[2] > 0.0f && isfinite(inv_s[0] * inv_s[1] * inv_s[2]) &&
+                     isfinite(qn) && isfinite(rh);
+    unsigned long long mycount = 0;
+    const int t0 = blockIdx.y * SETUP_TCHUNK, t1 = min(T, t0 + SETUP_TCHUNK);
+    for (int t = t0; t < t1; ++t) {
+        float wt[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) wt[r] = w[(size_t)t * NR + r];
+        ViewTrig vt;
+        sincosf(angles[t], &vt.st, &vt.ct);
+        SetupFwd f;
+        setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
+        int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+        bool ok = inputs_ok && f.ok;
+        if (valid) {
+            if (!inputs_ok || !(isfinite(f.detK) && f.detK != 0.0f))
+                atomicAdd(&diag->nonfinite, 1u);
+            else if (!(f.alpha > 1e-3f * G.sid))
+                atomicAdd(&diag->behind_source, 1u);
+            else if (!f.ok)
+                atomicAdd(&diag->nonfinite, 1u);
+            if (ok && f.detK <= 0.0f) atomicAdd(&diag->folded, 1u);
+        }
+        if (ok) {
+            if (!footprint_box(G, f, cull, x0, x1, y0, y1) && valid)
+                atomicAdd(&diag->wide, 1u);
+        }
+        uint32_t count = 0;
+        int2 rr = make_int2(1, 0);
+        if (valid && ok && x0 <= x1 && y0 <= y1) {
+            const int tx0 = x0 / DIGS_TILE, tx1 = x1 / DIGS_TILE;
+            const int ty0 = y0 / DIGS_TILE, ty1 = y1 / DIGS_TILE;
+            count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+            rr = make_int2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        } else {
+            x0 = 1; x1 = 0; y0 = 1; y1 = 0;
+        }
+        mycount += count;
+        if (valid) {
+            const size_t o = (size_t)t * n + i;
+            const float a = (ok ? f.amp : 0.0f);
+            rec[o * 4 + 0] = make_float4(f.us, f.vs, C2_EXP2 * f.Huu, 2.0f * C2_EXP2 * f.Huv);
+            rec[o * 4 + 1] = make_float4(C2_EXP2 * f.Hvv, 2.0f * f.gu, 2.0f * f.gv, f.Guu);
+            rec[o * 4 + 2] = make_float4(2.0f * f.Guv, f.Gvv, a,
+                                         __int_as_float(x0 | (x1 << 16)));
+            rec[o * 4 + 3] = make_float4(__int_as_float(y0 | (y1 << 16)), 0.0f, 0.0f, 0.0f);
+            if (!ok) {   // keep the record finite for the splat
+                rec[o * 4 + 0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                rec[o * 4 + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                rec[o * 4 + 2] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(1));
+                rec[o * 4 + 3] = make_float4(__int_as_float(1), 0.0f, 0.0f, 0.0f);
+            }
+            rect[o] = rr;
+            gcount[o] = count;
+        }
+    }
+    // exact total of instances (64-bit) for the capacity check
+    unsigned long long v = mycount;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane_id() == 0) wsum[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (tot) atomicAdd(&diag->instances, tot);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a4: binning sources
+struct TileSrc {
+    const int2 *rect;        // [T][N]
+    const uint32_t *goff;    // [T][N] scanned gcount
+    uint32_t *list, *inv;
+    size_t cap;
+    int items;               // N
+    int tiles_x;
+    struct Item {
+        int tx0, ty0, w, cnt, tiles_x;
+        __device__ int nkeys() const { return cnt; }
+        __device__ int key(int k) const { return (ty0 + k / w) * tiles_x + tx0 + k % w; }
+    };
+    __device__ Item load(int t, int item) const
+    {
+        const int2 r = rect[(size_t)t * items + item];
+        Item it;
+        it.tx0 = r.x & 0xffff;
+        const int tx1 = r.x >> 16;
+        it.ty0 = r.y & 0xffff;
+        const int ty1 = r.y >> 16;
+        it.w = tx1 - it.tx0 + 1;
+        it.cnt = (tx1 >= it.tx0 && ty1 >= it.ty0) ? it.w * (ty1 - it.ty0 + 1) : 0;
+        it.tiles_x = tiles_x;
+        return it;
+    }
+    __device__ void emit(int t, int item, const Item &, int k, uint32_t pos) const
+    {
+        if (pos < cap) list[pos] = (uint32_t)item;
+        const size_t g = (size_t)goff[(size_t)t * items + item] + k;
+        if (g < cap) inv[g] = pos;
+    }
+};
+
+struct RadixSrc {
+    const uint32_t *keys_in, *vals_in;
+    uint32_t *keys_out, *vals_out;
+    int items;
+    int shift;
+    struct Item {
+        uint32_t k;
+        __device__ int nkeys() const { return 1; }
+        __device__ int key(int) const { return (int)k; }
+    };
+    __device__ Item load(int, int item) const
+    {
+        Item it;
+        it.k = (keys_in[item] >> shift) & 255u;
+        return it;
+    }
+    __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
+    {
+        if (pos < (uint32_t)items) {
+            keys_out[pos] = keys_in[item];
+            vals_out[pos] = vals_in[item];
+        }
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// a5: forward splat. One workgroup per (projection, tile); with 4 waves each wave owns an 8x8
+// pixel block and skips Gaussians whose box misses it; with 1 wave the wave owns the 16x16 tile
+// in 4 passes of 64 pixels.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
+                                                          const float *__restrict__ rec,
+                                                          const uint32_t *__restrict__ list,
+                                                          const uint32_t *__restrict__ cnt,
+                                                          int nblk, unsigned cap,
+                                                          float *__restrict__ proj)
+{
+    const int t = blockIdx.y, tile = blockIdx.x;
+    const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
+    const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
+    const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
+    uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
+    begin = min(begin, cap);
+    end = min(max(end, begin), cap);
+    const float cu = 0.5f * (float)(G.nu - 1), cv = 0.5f * (float)(G.nv - 1);
+#pragma unroll
+    for (int pass = 0; pass < 4 / WAVES; ++pass) {
+        const int blkid = (WAVES == 4) ? wave : pass;
+        const int bx = tx * DIGS_TILE + (blkid & 1) * 8, by = ty * DIGS_TILE + (blkid >> 1) * 8;
+        const int px = bx + (lane & 7), py = by + (lane >> 3);
+        const float fi = (float)px, fj = (float)py;
+        float acc = 0.0f;
+        for (uint32_t k = begin; k < end; ++k) {
+            const uint32_t g = uniform(list[k]);
+            if (g >= (uint32_t)n) continue;
+            const float *r = rec + ((size_t)t * n + g) * DIGS_REC_FLOATS;
+            const int bxr = __float_as_int(r[11]), byr = __float_as_int(r[12]);
+            const int x0 = bxr & 0xffff, x1 = bxr >> 16, y0 = byr & 0xffff, y1 = byr >> 16;
+            if (x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7) continue;
+            const float du = fi - r[0], dv = fj - r[1];
+            const float q = fmaf(du, fmaf(r[7], du, fmaf(r[8], dv, r[5])),
+                                 fmaf(dv, fmaf(r[9], dv, r[6]), 1.0f));
+            const float e = fmaf(du, fmaf(r[2], du, r[3] * dv), r[4] * dv * dv);
+            const float rs = __builtin_amdgcn_rsqf(q);
+            const float x = e * (rs * rs);
+            acc = fmaf(r[10] * rs, __builtin_amdgcn_exp2f(x), acc);
+        }
+        if (px < G.nu && py < G.nv) {
+            const float xu = (fi - cu) * G.pitch_u + G.off_u, yv = (fj - cv) * G.pitch_v + G.off_v;
+            const float en = sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+            proj[((size_t)t * G.nv + py) * G.nu + px] = acc * en;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a6: backward splat. Lane = (Gaussian, tile) instance; the tile's dL/dI (times |e|) is staged in
+// LDS and read by broadcast. Twelve moment sums per instance:
+//  0 S_amp = sum g r 2^x      (dL/damp)
+//  1 S_Euu, 2 S_Euv, 3 S_Evv  sum A_E du^2, du dv, dv^2   (A_E = dL/dE, E natural)
+//  4 S_quu, 5 S_quv, 6 S_qvv  sum A_q du^2, du dv, dv^2   (A_q = dL/dq)
+//  7 S_qu, 8 S_qv, 9 S_q      sum A_q du, dv, 1
+//  10 S_Eu, 11 S_Ev           sum A_E du, dv
+__global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
+                                                   const float4 *__restrict__ rec,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint32_t *__restrict__ cnt, int nblk,
+                                                   unsigned cap,
+                                                   const float *__restrict__ grad_proj,
+                                                   float4 *__restrict__ part)
+{
+    __shared__ float gpx[DIGS_TILE_PX];
+    const int t = blockIdx.y, tile = blockIdx.x;
+    const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
+    const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
+    {
+        const int p = threadIdx.x;
+        const int px = tx * DIGS_TILE + (p & 15), py = ty * DIGS_TILE + (p >> 4);
+        float gv = 0.0f;
+        if (px < G.nu && py < G.nv) {
+            const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
+            const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
+            gv = grad_proj[((size_t)t * G.nv + py) * G.nu + px] *
+                 sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+        }
+        gpx[p] = gv;
+    }
+    __syncthreads();
+    const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
+    uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
+    begin = min(begin, cap);
+    end = min(max(end, begin), cap);
+    const float ox = (float)(tx * DIGS_TILE), oy = (float)(ty * DIGS_TILE);
+    for (uint32_t base = begin + wave * DIGS_WAVE; base < end; base += 4 * DIGS_WAVE) {
+        const uint32_t k = base + lane;
+        bool active = k < end;
+        uint32_t g = active ? list[k] : 0u;
+        active = active && g < (uint32_t)n;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+        if (active) {
+            const float4 *r = rec + ((size_t)t * n + g) * 4;
+            r0 = r[0];
+            r1 = r[1];
+            r2 = r[2];
+        }
+        const float us = r0.x, vs = r0.y, Hu = r0.z, Huv = r0.w, Hv = r1.x, gu2 = r1.y,
+                    gv2 = r1.z, Guu = r1.w, Guv2 = r2.x, Gvv = r2.y, amp = r2.z;
+        float S[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) S[c] = 0.0f;
+        const float du0 = ox - us, dv0 = oy - vs;
+        for (int row = 0; row < DIGS_TILE; ++row) {
+            const float dv = dv0 + (float)row;
+            const float dv2 = dv * dv;
+            const float qv = fmaf(dv, fmaf(Gvv, dv, gv2), 1.0f);
+            const float ev = Hv * dv2;
+            for (int col = 0; col < DIGS_TILE; ++col) {
+                const float gval = gpx[row * DIGS_TILE + col];
+                if (gval == 0.0f) continue;
+                const float du = du0 + (float)col;
+                const float q = fmaf(du, fmaf(Guu, du, fmaf(Guv2, dv, gu2)), qv);
+                const float e = fmaf(du, fmaf(Hu, du, Huv * dv), ev);
+                const float rs = __builtin_amdgcn_rsqf(q);
+                const float r2s = rs * rs;
+                const float x = e * r2s;
+                const float gr = gval * rs * __builtin_amdgcn_exp2f(x);
+                const float aE = -0.5f * gr * amp * r2s;
+                const float aq = aE * fmaf(2.0f * LN2, x, 1.0f);
+                const float du2 = du * du, duv = du * dv;
+                S[0] += gr;
+                S[1] = fmaf(aE, du2, S[1]);
+                S[2] = fmaf(aE, duv, S[2]);
+                S[3] = fmaf(aE, dv2, S[3]);
+                S[4] = fmaf(aq, du2, S[4]);
+                S[5] = fmaf(aq, duv, S[5]);
+                S[6] = fmaf(aq, dv2, S[6]);
+                S[7] = fmaf(aq, du, S[7]);
+                S[8] = fmaf(aq, dv, S[8]);
+                S[9] += aq;
+                S[10] = fmaf(aE, du, S[10]);
+                S[11] = fmaf(aE, dv, S[11]);
+            }
+        }
+        if (k < end) {
+            part[(size_t)k * 3 + 0] = make_float4(S[0], S[1], S[2], S[3]);
+            part[(size_t)k * 3 + 1] = make_float4(S[4], S[5], S[6], S[7]);
+            part[(size_t)k * 3 + 2] = make_float4(S[8], S[9], S[10], S[11]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a7: per-Gaussian adjoint of the set-up and of the warp, summed over the call's projections.
+template <int NR>
+__global__ __launch_bounds__(256) void k_gauss_bwd(
+    DevGeom G, DevGrid grid, int n, int T, const float *__restrict__ coef,
+    const float *__restrict__ mu, const float *__restrict__ scale, const float *__restrict__ quat,
+    const float *__restrict__ rho, const float *__restrict__ angles, const float *__restrict__ w,
+    const float *__restrict__ uv, const int2 *__restrict__ rect,
+    const uint32_t *__restrict__ goff, const uint32_t *__restrict__ inv,
+    const float4 *__restrict__ part, unsigned cap, const uint32_t *__restrict__ pos_of,
+    float *__restrict__ g_mu, float *__restrict__ g_scale, float *__restrict__ g_quat,
+    float *__restrict__ g_rho, float *__restrict__ gwpart, int nparts, float *__restrict__ gq,
+    int gq_stride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const int ii = valid ? i : 0;
+    const int lane = lane_id(), wave = threadIdx.x / DIGS_WAVE;
+    float mu0[3], s[3], q[4], Rm[9], inv_s[3];
+    float U[NR][3], V[NR][9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mu0[a] = mu[(size_t)a * n + ii];
+        s[a] = scale[(size_t)a * n + ii];
+        inv_s[a] = 1.0f / s[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + ii];
+    const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float qh[4] = {q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn};
+    quat_to_rot(qh[0], qh[1], qh[2], qh[3], Rm);
+    const float rh = rho[ii];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) U[r][a] = uv[((size_t)r * 3 + a) * n + ii];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
+    }
+    float RS[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) RS[3 * a + b] = Rm[3 * a + b] * s[b];
+
+    float gsum_mu[3] = {0.f, 0.f, 0.f}, gRS[9], P[NR][3], Q[NR][9], grho = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gRS[k] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P[r][a] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Q[r][k] = 0.0f;
+    }
+
+    for (int t = 0; t < T; ++t) {
+        float gwc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gwc[r] = 0.0f;
+        const int2 rr = rect[(size_t)t * n + ii];
+        const int tx0 = rr.x & 0xffff, tx1 = rr.x >> 16, ty0 = rr.y & 0xffff, ty1 = rr.y >> 16;
+        const int cntk = (valid && tx1 >= tx0 && ty1 >= ty0) ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
+                                                             : 0;
+        if (cntk > 0) {
+            float S[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) S[c] = 0.0f;
+            const uint32_t o = goff[(size_t)t * n + ii];
+            for (int k = 0; k < cntk; ++k) {
+                if ((size_t)o + k >= cap) break;
+                const uint32_t p = inv[o + k];
+                if (p >= cap) continue;
+                const float4 a = part[(size_t)p * 3 + 0], b = part[(size_t)p * 3 + 1],
+                             c = part[(size_t)p * 3 + 2];
+                S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
+                S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
+                S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
+            }
+            float wt[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) wt[r] = w[(size_t)t * NR + r];
+            ViewTrig vt;
+            sincosf(angles[t], &vt.st, &vt.ct);
+            SetupFwd f;
+            setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
+            // record gradients from the moment sums
+            const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
+            const float gGuu = S[4], gGuv = 2.0f * S[5], gGvv = S[6];
+            const float ggu = 2.0f * S[7], ggv = 2.0f * S[8];
+            const float gamp = S[0];
+            const float gus = -2.0f * (f.Huu * S[10] + f.Huv * S[11] + f.gu * S[9] +
+                                       f.Guu * S[7] + f.Guv * S[8]);
+            const float gvs = -2.0f * (f.Huv * S[10] + f.Hvv * S[11] + f.gv * S[9] +
+                                       f.Guv * S[7] + f.Gvv * S[8]);
+            // reverse of the record formulas
+            const float sic = sqrtf(f.ic);
+            grho += gamp * SQRT_2PI * f.beta * sic;
+            float gbeta = gamp * rh * SQRT_2PI * sic;
+            float gc = -0.5f * gamp * f.amp * f.ic;
+            const float Duu = dot3(f.Du, f.Du), Duv = dot3(f.Du, f.Dv), Dvv = dot3(f.Dv, f.Dv);
+            float gkap = (gGuu * Duu + gGuv * Duv + gGvv * Dvv) * f.ic;
+            gc -= (gGuu * f.Guu + gGuv * f.Guv + gGvv * f.Gvv) * f.ic;
+            float gDu[3], gDv[3], gmw[3], gDup[3], gDvp[3];
+            const float kic = f.kap * f.ic;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gDu[a] = kic * (2.0f * gGuu * f.Du[a] + gGuv * f.Dv[a]);
+                gDv[a] = kic * (2.0f * gGvv * f.Dv[a] + gGuv * f.Du[a]);
+            }
+            gbeta -= ggu * f.pa + ggv * f.pb;
+            float gpa = -ggu * f.beta, gpb = -ggv * f.beta;
+            gkap += gHuu * dot3(f.Dup, f.Dup) + gHuv * dot3(f.Dup, f.Dvp) +
+                    gHvv * dot3(f.Dvp, f.Dvp);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gDup[a] = f.kap * (2.0f * gHuu * f.Dup[a] + gHuv * f.Dvp[a]);
+                gDvp[a] = f.kap * (2.0f * gHvv * f.Dvp[a] + gHuv * f.Dup[a]);
+            }
+            gbeta += 2.0f * f.beta * gkap;
+            gpa -= dot3(gDup, f.mw);
+            gpb -= dot3(gDvp, f.mw);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gDu[a] += gDup[a];
+                gDv[a] += gDvp[a];
+                gmw[a] = -f.pa * gDup[a] - f.pb * gDvp[a];
+            }
+            const float gdu = gpa * f.ic, gdv = gpb * f.ic;
+            gc -= (gpa * f.pa + gpb * f.pb) * f.ic;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gmw[a] += gdu * f.Du[a] + gdv * f.Dv[a] + 2.0f * gc * f.mw[a];
+                gDu[a] += gdu * f.mw[a];
+                gDv[a] += gdv * f.mw[a];
+            }
+            float galpha = gbeta / G.sdd;
+            const float ia = 1.0f / f.alpha;
+            const float kuf = G.sdd * ia / G.pitch_u, kvf = G.sdd * ia / G.pitch_v;
+            const float gxu = -gus * kuf, gxv = -gvs * kvf;
+            galpha += gus * kuf * f.xu * ia + gvs * kvf * f.xv * ia;
+            // mw = W m, Du = pu W e_u, Dv = pv W e_v
+            const float eu[3] = {-vt.st, vt.ct, 0.0f};
+            float gW[9], gm[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gW[3 * a + b] = gmw[a] * f.m[b] + G.pitch_u * gDu[a] * eu[b] +
+                                    (b == 2 ? G.pitch_v * gDv[a] : 0.0f);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                gm[b] = f.W[b] * gmw[0] + f.W[3 + b] * gmw[1] + f.W[6 + b] * gmw[2];
+            float gmup[3] = {-gm[0], -gm[1], -gm[2]};
+            gmup[0] += -vt.ct * galpha + vt.st * gxu;
+            gmup[1] += -vt.st * galpha - vt.ct * gxu;
+            gmup[2] += -gxv;
+            // W = M^-1: dL/dM = -W^T gW W^T
+            float T1[9], gM[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    T1[3 * a + b] = f.W[a] * gW[b] + f.W[3 + a] * gW[3 + b] + f.W[6 + a] * gW[6 + b];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gM[3 * a + b] = -(T1[3 * a] * f.W[3 * b] + T1[3 * a + 1] * f.W[3 * b + 1] +
+                                      T1[3 * a + 2] * f.W[3 * b + 2]);
+            // M = K (R S): dL/dK = gM (RS)^T, dL/d(RS) += K^T gM
+            float gK[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    gK[3 * a + b] = gM[3 * a] * RS[3 * b] + gM[3 * a + 1] * RS[3 * b + 1] +
+                                    gM[3 * a + 2] * RS[3 * b + 2];
+                    gRS[3 * a + b] += f.K[a] * gM[b] + f.K[3 + a] * gM[3 + b] +
+                                      f.K[6 + a] * gM[6 + b];
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gsum_mu[a] += gmup[a];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                float c = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    P[r][a] = fmaf(wt[r], gmup[a], P[r][a]);
+                    c = fmaf(U[r][a], gmup[a], c);
+                }
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    Q[r][k] = fmaf(wt[r], gK[k], Q[r][k]);
+                    c = fmaf(V[r][k], gK[k], c);
+                }
+                gwc[r] = c;
+            }
+        }
+        // dL/dw[t][r]: per-wave partial sums in a fixed order
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const float sm = wave_sum(gwc[r]);
+            if (lane == 0)
+                gwpart[((size_t)t * NR + r) * nparts + blockIdx.x * 4 + wave] = sm;
+        }
+    }
+    if (!valid) return;
+    // dL/dmu = sum_t dL/dmu' + sum_r V_r^T P_r + sum_r Q_r : d(grad u_r)/dmu
+    float gmu[3] = {gsum_mu[0], gsum_mu[1], gsum_mu[2]};
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            gmu[c] += V[r][c] * P[r][0] + V[r][3 + c] * P[r][1] + V[r][6 + c] * P[r][2];
+    Stencil st;
+    DevGrid gg = grid;
+    make_stencil(gg, mu0[0], mu0[1], mu0[2], st, true);
+    for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(gg, coef, r, st, Q[r], gmu);
+    // RS = R diag(s)
+    float gR[9], gs[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        gs[b] = gRS[b] * Rm[b] + gRS[3 + b] * Rm[3 + b] + gRS[6 + b] * Rm[6 + b];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gR[3 * a + b] = gRS[3 * a + b] * s[b];
+    }
+    float gqh[4];
+    quat_rot_adjoint(qh[0], qh[1], qh[2], qh[3], gR, gqh);
+    const float dq = gqh[0] * qh[0] + gqh[1] * qh[1] + gqh[2] * qh[2] + gqh[3] * qh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g_mu[(size_t)a * n + i] = gmu[a];
+        g_scale[(size_t)a * n + i] = gs[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) g_quat[(size_t)a * n + i] = (gqh[a] - dq * qh[a]) * qn;
+    g_rho[i] = grho;
+    // sources of dL/dcoef in cell order: clamped cell, fraction, P_r, Q_r
+    const uint32_t slot = pos_of[i];
+    if (slot >= (uint32_t)n) return;
+    float *o = gq + (size_t)slot * gq_stride;
+    o[0] = __int_as_float(max(-2, min(st.fx, grid.nx + 1)));
+    o[1] = __int_as_float(max(-2, min(st.fy, grid.ny + 1)));
+    o[2] = __int_as_float(max(-2, min(st.fz, grid.nz + 1)));
+    o[3] = st.px;
+    o[4] = st.py;
+    o[5] = st.pz;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[6 + 12 * r + a] = P[r][a];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o[6 + 12 * r + 3 + k] = Q[r][k];
+    }
+}
+
+__global__ void k_gw_final(int T, int R, const float *__restrict__ gwpart, int nparts,
+                           float *__restrict__ g_w)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= T * R) return;
+    const float *p = gwpart + (size_t)idx * nparts;
+    float s = 0.0f;
+    for (int k = 0; k < nparts; ++k) s += p[k];
+    g_w[idx] = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// a8: cell sort and the control-point gather of dL/dcoef
+__global__ void k_cell_keys(DevGrid g, int n, const float *__restrict__ mu,
+                            uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float q[3] = {(mu[i] - g.ox) / g.hx, (mu[n + i] - g.oy) / g.hy,
+                        (mu[2 * n + i] - g.oz) / g.hz};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float f = floorf(q[a]);
+        f = fminf(fmaxf(f, -2.0f), (float)(dims[a] + 1));   // NaN-safe clamp
+        c[a] = (f == f) ? (int)f + 2 : 0;
+    }
+    keys[i] = ((uint32_t)c[2] * (g.ny + 4) + c[1]) * (g.nx + 4) + c[0];
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_cell_ranges(int n, const uint32_t *__restrict__ keys,
+                              const uint32_t *__restrict__ vals, uint32_t *__restrict__ lo,
+                              uint32_t *__restrict__ hi, uint32_t *__restrict__ pos_of)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) lo[k] = (uint32_t)p;
+    if (p == n - 1 || keys[p + 1] != k) hi[k] = (uint32_t)p + 1;
+    const uint32_t v = vals[p];
+    if (v < (uint32_t)n) pos_of[v] = (uint32_t)p;
+}
+
+template <int NR>
+__global__ __launch_bounds__(128) void k_coef_grad(DevGrid g, const float *__restrict__ gq,
+                                                   int gq_stride,
+                                                   const uint32_t *__restrict__ lo,
+                                                   const uint32_t *__restrict__ hi,
+                                                   float *__restrict__ g_coef)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int npts = g.nx * g.ny * g.nz;
+    if (idx >= npts) return;
+    const int i = idx % g.nx, j = (idx / g.nx) % g.ny, k = idx / (g.nx * g.ny);
+    float acc[NR][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0f;
+    const int lx = (i == 0) ? -2 : i - 2, hx = (i == g.nx - 1) ? g.nx + 1 : i + 1;
+    const int ly = (j == 0) ? -2 : j - 2, hy = (j == g.ny - 1) ? g.ny + 1 : j + 1;
+    const int lz = (k == 0) ? -2 : k - 2, hz = (k == g.nz - 1) ? g.nz + 1 : k + 1;
+    const float ihx = 1.0f / g.hx, ihy = 1.0f / g.hy, ihz = 1.0f / g.hz;
+    for (int cz = lz; cz <= hz; ++cz)
+        for (int cy = ly; cy <= hy; ++cy)
+            for (int cx = lx; cx <= hx; ++cx) {
+                const uint32_t cell = ((uint32_t)(cz + 2) * (g.ny + 4) + (cy + 2)) * (g.nx + 4) +
+                                      (cx + 2);
+                const uint32_t b = lo[cell], e = hi[cell];
+                for (uint32_t p = b; p < e; ++p) {
+                    const float *o = gq + (size_t)p * gq_stride;
+                    float B[4], dB[4];
+                    float wx = 0.f, dwx = 0.f, wy = 0.f, dwy = 0.f, wz = 0.f, dwz = 0.f;
+                    bspline4(o[3], B);
+                    bspline4_d(o[3], dB);
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        if (clampi(cx - 1 + l, g.nx) == i) { wx += B[l]; dwx += dB[l]; }
+                    bspline4(o[4], B);
+                    bspline4_d(o[4], dB);
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        if (clampi(cy - 1 + l, g.ny) == j) { wy += B[l]; dwy += dB[l]; }
+                    bspline4(o[5], B);
+                    bspline4_d(o[5], dB);
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        if (clampi(cz - 1 + l, g.nz) == k) { wz += B[l]; dwz += dB[l]; }
+                    const float w0 = wx * wy * wz, w1 = dwx * ihx * wy * wz,
+                                w2 = wx * dwy * ihy * wz, w3 = wx * wy * dwz * ihz;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const float *Pr = o + 6 + 12 * r, *Qr = Pr + 3;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            acc[r][a] += w0 * Pr[a] + w1 * Qr[3 * a] + w2 * Qr[3 * a + 1] +
+                                         w3 * Qr[3 * a + 2];
+                    }
+                }
+            }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g_coef[((size_t)r * npts + idx) * 3 + a] = acc[r][a];
+}
+
+// ------------------------------------------------------------------------------------------
+// host orchestration
+#define WS(a, off, type) reinterpret_cast<type>((a).ws + (a).L.off)
+
+template <class Src>
+static hipError_t launch_binning(const Src &src, int slices, int nbins, int nblk, int nbits,
+                                 uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
+                                 hipStream_t s)
+{
+    const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_bin_count<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
+                       cnt, nbins, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(cnt, cnt_elems, scratch, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_fill<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src, cnt,
+                       nbins, nblk, nbits);
+    return hipGetLastError();
+}
+
+static int bits_for(int nbins)
+{
+    int b = 0;
+    while ((1 << b) < nbins) ++b;
+    return b < 1 ? 1 : b;
+}
+
+template <int NR>
+static hipError_t setup_dispatch(const RenderArgs &a, hipStream_t s)
+{
+    const int n = a.n, T = a.T;
+    dim3 grid((n + 255) / 256, (T + SETUP_TCHUNK - 1) / SETUP_TCHUNK);
+    hipLaunchKernelGGL(k_setup<NR>, grid, dim3(256), 0, s, a.geom, n, T, a.mu, a.scale, a.quat,
+                       a.rho, a.angles, a.w, WS(a, uv, const float *), a.cull,
+                       WS(a, rec, float4 *), WS(a, rect, int2 *), WS(a, gcount, uint32_t *),
+                       WS(a, diag, DiagBlock *));
+    return hipGetLastError();
+}
+
+hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
+{
+    hipError_t e;
+    const size_t cnt_elems = (size_t)a.T * a.geom.ntiles * a.L.nblk;
+    uint32_t *cnt = WS(a, cnt, uint32_t *);
+    hipLaunchKernelGGL(k_diag_begin, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *),
+                       (unsigned long long)a.L.cap, cnt + cnt_elems);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ffd_canonical, dim3((a.n + 255) / 256), dim3(256), 0, s, a.grid,
+                       a.coef, a.n, a.mu, WS(a, uv, float *));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    switch (a.grid.R) {
+    case 1: e = setup_dispatch<1>(a, s); break;
+    case 2: e = setup_dispatch<2>(a, s); break;
+    case 3: e = setup_dispatch<3>(a, s); break;
+    case 4: e = setup_dispatch<4>(a, s); break;
+    case 5: e = setup_dispatch<5>(a, s); break;
+    case 6: e = setup_dispatch<6>(a, s); break;
+    case 7: e = setup_dispatch<7>(a, s); break;
+    default: e = setup_dispatch<8>(a, s); break;
+    }
+    if (e != hipSuccess) return e;
+    uint32_t *scratch = WS(a, scratch, uint32_t *);
+    // per-(t,n) instance offsets (Gaussian-major), then the tile lists
+    e = launch_exclusive_scan(WS(a, gcount, uint32_t *), (size_t)a.T * a.n, scratch, s);
+    if (e != hipSuccess) return e;
+    TileSrc src;
+    src.rect = WS(a, rect, const int2 *);
+    src.goff = WS(a, gcount, const uint32_t *);
+    src.list = WS(a, list, uint32_t *);
+    src.inv = WS(a, inv, uint32_t *);
+    src.cap = a.L.cap;
+    src.items = a.n;
+    src.tiles_x = a.geom.tiles_x;
+    e = launch_binning(src, a.T, a.geom.ntiles, a.L.nblk, bits_for(a.geom.ntiles), cnt,
+                       cnt_elems + 1, scratch, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_check, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *));
+    return hipGetLastError();
+}
+
+hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
+{
+    dim3 grid(a.geom.ntiles, a.T);
+    const unsigned cap = (unsigned)a.L.cap;
+    if (a.splat_waves == 1)
+        hipLaunchKernelGGL(k_splat_fwd<1>, grid, dim3(64), 0, s, a.geom, a.n, a.T,
+                           WS(a, rec, const float *), WS(a, list, const uint32_t *),
+                           WS(a, cnt, const uint32_t *), a.L.nblk, cap, proj);
+    else
+        hipLaunchKernelGGL(k_splat_fwd<4>, grid, dim3(256), 0, s, a.geom, a.n, a.T,
+                           WS(a, rec, const float *), WS(a, list, const uint32_t *),
+                           WS(a, cnt, const uint32_t *), a.L.nblk, cap, proj);
+    return hipGetLastError();
+}
+
+template <int NR>
+static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_scale,
+                                    float *g_quat, float *g_rho, float *g_coef, float *g_w,
+                                    hipStream_t s)
+{
+    const int n = a.n, T = a.T;
+    const int nb = (n + 255) / 256;
+    const int nparts = nb * 4;
+    hipLaunchKernelGGL(k_gauss_bwd<NR>, dim3(nb), dim3(256), 0, s, a.geom, a.grid, n, T, a.coef,
+                       a.mu, a.scale, a.quat, a.rho, a.angles, a.w, WS(a, uv, const float *),
+                       WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
+                       WS(a, inv, const uint32_t *), WS(a, part, const float4 *),
+                       (unsigned)a.L.cap, WS(a, pos_of, const uint32_t *), g_mu, g_scale, g_quat,
+                       g_rho, WS(a, gwpart, float *), nparts, WS(a, gq, float *), a.L.gq_stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gw_final, dim3((T * NR + 63) / 64), dim3(64), 0, s, T, NR,
+                       WS(a, gwpart, const float *), nparts, g_w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int npts = a.grid.nx * a.grid.ny * a.grid.nz;
+    hipLaunchKernelGGL(k_coef_grad<NR>, dim3((npts + 127) / 128), dim3(128), 0, s, a.grid,
+                       WS(a, gq, const float *), a.L.gq_stride, WS(a, cell_lo, const uint32_t *),
+                       WS(a, cell_hi, const uint32_t *), g_coef);
+    return hipGetLastError();
+}
+
+hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
+                           float *g_scale, float *g_quat, float *g_rho, float *g_coef,
+                           float *g_w, hipStream_t s)
+{
+    hipError_t e;
+    const int n = a.n;
+    // a6: per-instance moment sums
+    hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, n, a.T,
+                       WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
+                       WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap, grad_proj,
+                       WS(a, part, float4 *));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // cell sort of the Gaussians (LSD radix, 8 bits per pass)
+    uint32_t *ka = WS(a, keys_a, uint32_t *), *va = WS(a, vals_a, uint32_t *);
+    uint32_t *kb = WS(a, keys_b, uint32_t *), *vb = WS(a, vals_b, uint32_t *);
+    hipLaunchKernelGGL(k_cell_keys, dim3((n + 255) / 256), dim3(256), 0, s, a.grid, n, a.mu, ka,
+                       va);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nblk_r = (n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS;
+    const int kbits = bits_for(a.L.ncells);
+    for (int shift = 0; shift < kbits; shift += 8) {
+        RadixSrc src;
+        src.keys_in = ka;
+        src.vals_in = va;
+        src.keys_out = kb;
+        src.vals_out = vb;
+        src.items = n;
+        src.shift = shift;
+        e = launch_binning(src, 1, 256, nblk_r, 8, WS(a, rhist, uint32_t *), (size_t)256 * nblk_r,
+                           WS(a, scratch, uint32_t *), s);
+        if (e != hipSuccess) return e;
+        uint32_t *t0 = ka; ka = kb; kb = t0;
+        t0 = va; va = vb; vb = t0;
+    }
+    if ((e = fill_u32(WS(a, cell_lo, uint32_t *), (size_t)a.L.ncells, 0u, s)) != hipSuccess)
+        return e;
+    if ((e = fill_u32(WS(a, cell_hi, uint32_t *), (size_t)a.L.ncells, 0u, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_cell_ranges, dim3((n + 255) / 256), dim3(256), 0, s, n, ka, va,
+                       WS(a, cell_lo, uint32_t *), WS(a, cell_hi, uint32_t *),
+                       WS(a, pos_of, uint32_t *));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    switch (a.grid.R) {
+    case 1: return backward_dispatch<1>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    case 2: return backward_dispatch<2>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    case 3: return backward_dispatch<3>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    case 4: return backward_dispatch<4>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    case 5: return backward_dispatch<5>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    case 6: return backward_dispatch<6>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    case 7: return backward_dispatch<7>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    default: return backward_dispatch<8>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    }
+}

@@ -256,7 +256,7 @@ def batch_schedule(nviews: int, batch: int, seed: int):
     return [perm[i:i + batch] for i in range(0, nviews, batch)]
 
 
-def small_phantom(n: int = 2048, det_u: int = 96, det_v: int = 80, pitch: float = 2.0,
+def small_phantom(n: int = 2048, det_u: int = 90, det_v: int = 75, pitch: float = 2.0,
                   nviews: int = 8, R: int = 3, h: float = 20.0, seed: int = 0) -> Problem:
     """A scaled-down member of the lung family that the oracle finishes in seconds; its detector
     is not a multiple of the tile size, so it also exercises ragged tiles."""

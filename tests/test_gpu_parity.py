@@ -1,0 +1,214 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: forward per pixel |GPU - oracle| <= 1e-4 * max|oracle| of the projection; FFD and
+warp outputs <= 2e-5 of their maximum magnitude (FP32 arithmetic on mm-sized values);
+gradients norm-wise <= 1e-4 per parameter group (<= 1e-3 for the few-element groups) against
+the oracle's adjoint.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_22280_amd import _lib, synth
+from gpu_helpers import dev, max_rel_to_max, norm_rel, oracle_inputs, problem_tensors
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _grid_small(R=2):
+    return dict(R=R, nx=7, ny=6, nz=5, origin=[-30.0, -25.0, -28.0], spacing=[9.0, 11.0, 13.0])
+
+
+def test_ffd_eval_matches_oracle():
+    _print("case: ffd_eval R=2 lattice 7x6x5, 3000 points (some outside the lattice)")
+    rng = np.random.default_rng(100)
+    g = _grid_small()
+    coef = rng.normal(0, 2.0, (2, 5, 6, 7, 3)).astype(np.float32)
+    x = rng.uniform(-45, 55, (3, 3000)).astype(np.float32)
+    U, V = oracle.ffd_eval(g, coef, x)
+    d, J = _lib.ffd_eval(g, dev(coef), dev(x))
+    torch.cuda.synchronize()
+    assert max_rel_to_max(d.cpu().numpy(), U) < 2e-5
+    assert max_rel_to_max(J.cpu().numpy(), V) < 2e-5
+    w = rng.normal(0, 1, (3, 2)).astype(np.float32)
+    dw, Jw = _lib.ffd_eval(g, dev(coef), dev(x), w=dev(w))
+    refd = np.einsum("tr,ran->tan", w.astype(np.float64), U)
+    refJ = np.einsum("tr,ran->tan", w.astype(np.float64), V)
+    assert max_rel_to_max(dw.cpu().numpy(), refd) < 2e-5
+    assert max_rel_to_max(Jw.cpu().numpy(), refJ) < 2e-5
+
+
+def test_deform_matches_oracle():
+    _print("case: deform_gaussians tiny problem, 16 views")
+    p = synth.tiny(seed=5, n=2000)
+    t = problem_tensors(p)
+    mu_t, cov_t = _lib.deform_gaussians(p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["w"])
+    rm, rc = oracle.deform(p.grid, p.coef, p.mu, p.scale, p.quat, p.w)
+    torch.cuda.synchronize()
+    assert max_rel_to_max(mu_t.cpu().numpy(), rm) < 2e-6
+    assert max_rel_to_max(cov_t.cpu().numpy(), rc) < 2e-5
+
+
+def _fwd(p, t, tuning=None, ws=None):
+    ws = ws or _lib.Workspace()
+    proj = _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                            t["angles"], t["w"], ws, tuning=tuning)
+    torch.cuda.synchronize()
+    return proj, ws
+
+
+def test_project_fwd_tiny_all_pixels():
+    _print("case: project_fwd tiny (4096 Gaussians, 64x64, 16 views), every pixel")
+    p = synth.tiny()
+    t = problem_tensors(p)
+    proj, ws = _fwd(p, t)
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0 and d["behind_source"] == 0
+    for k in range(ref.shape[0]):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+
+
+def test_project_fwd_ragged_tiles_and_single_wave():
+    _print("case: project_fwd small phantom 90x75 (ragged tiles), 8 views, both splat shapes")
+    p = synth.small_phantom()
+    t = problem_tensors(p)
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for waves in (4, 1):
+        proj, _ = _fwd(p, t, tuning=dict(splat_waves=waves))
+        for k in range(ref.shape[0]):
+            err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+            assert err <= 1e-4, (waves, k, err)
+
+
+def test_project_fwd_full_size_sampled():
+    """The benchmark's launch: 200k Gaussians, 512x384, a batch of 64 uneven-time views;
+    2048 sampled pixels in each of 3 views of the batch against the uncut oracle."""
+    _print("case: project_fwd 200k Gaussians 512x384, batch of 64 views, sampled pixels")
+    p = synth.batched(seed=0)
+    batch = synth.batch_schedule(len(p.angles), 64, seed=0)[0]
+    t = problem_tensors(p, batch)
+    proj, ws = _fwd(p, t)
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0
+    rng = np.random.default_rng(7)
+    sel = [0, 31, 63]
+    m = 2048
+    pt = np.repeat(np.arange(len(sel)), m)
+    pj = rng.integers(0, p.geom["nv"], pt.size)
+    pi = rng.integers(0, p.geom["nu"], pt.size)
+    angles, w = p.views(batch[sel])
+    ref = oracle.project_pixels(p.geom, p.grid, p.coef, p.mu, p.scale, p.quat, p.rho, angles, w,
+                                pt, pj, pi)
+    got = proj.cpu().numpy()[np.asarray(sel)[pt], pj, pi]
+    pmax = proj.cpu().numpy()[sel].reshape(len(sel), -1).max(1)
+    err = np.abs(got - ref) / pmax[pt]
+    _print("max err / max", err.max())
+    assert err.max() <= 1e-4
+
+
+def test_project_deterministic_and_batch_invariant():
+    _print("case: bitwise repeatability; batched equals one view per launch")
+    p = synth.small_phantom(seed=3)
+    t = problem_tensors(p)
+    a, _ = _fwd(p, t)
+    b, _ = _fwd(p, t)
+    assert torch.equal(a, b)
+    for k in range(len(p.angles)):
+        tk = problem_tensors(p, [k])
+        s, _ = _fwd(p, tk)
+        assert torch.equal(s[0], a[k])
+
+
+def test_edge_cases():
+    _print("case: edge cases (no Gaussians, off-detector, behind the source, tiny capacity)")
+    p = synth.tiny(n=64, nviews=2, det=32)
+    t = problem_tensors(p)
+    ws = _lib.Workspace()
+    # no Gaussians: zeros
+    z = _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"][:, :0].contiguous(),
+                         t["scale"][:, :0].contiguous(), t["quat"][:, :0].contiguous(),
+                         t["rho"][:0].contiguous(), t["angles"], t["w"], ws)
+    torch.cuda.synchronize()
+    assert z.abs().max().item() == 0.0
+    # a Gaussian far off the detector contributes nothing; one behind the source is counted
+    mu = p.mu.copy()
+    mu[:, 0] = [0.0, 0.0, 900.0]
+    mu[:, 1] = [1500.0, 0.0, 0.0]
+    q = dict(t, mu=dev(mu))
+    ws2 = _lib.Workspace()
+    proj = _lib.project_fwd(p.geom, p.grid, q["coef"], q["mu"], q["scale"], q["quat"], q["rho"],
+                            q["angles"], q["w"], ws2)
+    d = ws2.diagnostics()
+    assert d["behind_source"] >= 1 and d["overflow"] == 0
+    assert torch.isfinite(proj).all()
+    # a capacity that is too small is reported, never silent
+    ws3 = _lib.Workspace()
+    _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                     t["angles"], t["w"], ws3, tuning=dict(capacity=8))
+    d = ws3.diagnostics()
+    assert d["overflow"] == 1 and d["instances"] > 8
+
+
+# ------------------------------------------------------------------------------------------------
+# Backward
+def _bwd_problem():
+    p = synth.tiny(seed=9, n=600, nviews=4, det=40)
+    G = np.random.default_rng(10).normal(0, 1, (4, 40, 40)).astype(np.float32)
+    return p, G
+
+
+def test_project_bwd_matches_oracle():
+    _print("case: project_bwd tiny (600 Gaussians, 4 views, 40x40) against the oracle adjoint")
+    p, G = _bwd_problem()
+    t = problem_tensors(p)
+    ws = _lib.Workspace()
+    _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                     t["angles"], t["w"], ws)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True)
+    torch.cuda.synchronize()
+    ref = oracle.project_bwd(p.geom, p.grid, *oracle_inputs(p), grad_proj=G)
+    errs = {k: norm_rel(out[k].cpu().numpy(), ref[k]) for k in ref}
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+    # recomputing the forward inside the backward gives the same bits
+    out2 = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                            t["angles"], t["w"], dev(G), _lib.Workspace(), reuse_fwd=False)
+    for k in out:
+        assert torch.equal(out[k], out2[k]), k
+
+
+def test_project_bwd_identities():
+    _print("case: gradient identities on the GPU (rho-linearity, quaternion, homogeneity)")
+    p, G = _bwd_problem()
+    t = problem_tensors(p)
+    ws = _lib.Workspace()
+    proj = _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                            t["angles"], t["w"], ws)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True)
+    torch.cuda.synchronize()
+    L = float((proj.double().cpu().numpy() * G).sum())
+    lhs = float((out["g_rho"].double().cpu().numpy() * p.rho).sum())
+    assert abs(lhs - L) <= 1e-5 * abs(L)
+    qg = (out["g_quat"].cpu().numpy().astype(np.float64) * p.quat).sum(0)
+    scale = np.abs(out["g_quat"].cpu().numpy()).max()
+    assert np.abs(qg).max() <= 1e-5 * scale
+    t1 = problem_tensors(p, [1])
+    ws1 = _lib.Workspace()
+    o1 = _lib.project_bwd(p.geom, p.grid, t1["coef"], t1["mu"], t1["scale"], t1["quat"],
+                          t1["rho"], t1["angles"], t1["w"], dev(G[1:2]), ws1)
+    torch.cuda.synchronize()
+    for r in range(p.grid["R"]):
+        lhs = float(p.w[1, r]) * float(o1["g_w"][0, r])
+        rhs = float((p.coef[r].astype(np.float64) * o1["g_coef"][r].double().cpu().numpy()).sum())
+        assert abs(lhs - rhs) <= 2e-4 * max(abs(lhs), 1e-12), (r, lhs, rhs)
