@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: fwd+bwd projections/s of the deformation-informed Gaussian X-ray renderer.
+
+Workload (the batched differentiable path): 200,000 Gaussians of the lung-like phantom, a
+512x384 detector at 0.8 mm (source-isocentre 1000 mm, source-detector 1500 mm), 1,320 views over
+a 60 s scan with irregular breathing, rank-3 FFD on a 29^3 lattice (10 mm). A step is one batch
+of 64 uneven-time views (a seeded permutation of the scan cut into 64s): the forward of every
+view (FFD at the canonical means, the warp, the projected records, tile binning, the splat), the
+gradient of the L2 projection loss against synthetic measured projections, and the hand-written
+backward to mu, scale, quaternion, density, FFD coefficients and the temporal weights.
+
+Inputs (Gaussians, lattice, per-batch angles and weights, measured projections) are resident in
+HBM before the timed region. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd projections/s @200k Gaussians 512×384 det; % HBM roofline; speedup vs plain"
+
+# Algorithmic FP32 work per (Gaussian, pixel) pair inside a footprint (FMA = 2, add/mul = 1,
+# rsqrt/exp2 = 1) and the VALU issue slots it occupies (a transcendental = TRANS_SLOTS slots).
+FWD_FLOP, FWD_VALU, FWD_TRANS = 27, 17, 2
+BWD_FLOP, BWD_VALU, BWD_TRANS = 55, 38, 2
+TRANS_SLOTS = 4
+LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes per cycle x clock
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per projection of one fwd+bwd step (see the design notes): Gaussians read
+# twice, lattice read twice and its gradient written, projection written, dL/dI read, Gaussian
+# gradients written, per batch of 64
+ALGO_BYTES_PER_PROJ = (2 * 200_000 * 44 + 3 * 29 ** 3 * 9 * 4 + 64 * 512 * 384 * 4 * 2 +
+                       200_000 * 44) / 64.0
+
+
+def peak_tflops(flop, valu, trans):
+    return LANE_OPS_PER_S * flop / (valu + TRANS_SLOTS * trans) / 1e12
+
+
+def cpu_baseline(p, params, batch_views, rows_every: int = 16):
+    """The FP64 oracle (uncut, as it stands) on one view of the batch, every `rows_every`-th
+    detector row: forward at those pixels and the adjoint of the L2 loss there."""
+    import oracle
+    oracle.build(force=False)
+    v = batch_views[0]
+    angles, w = p.views([v])
+    mu, scale, quat, rho, coef = params
+    nv, nu = p.geom["nv"], p.geom["nu"]
+    rows = np.arange(0, nv, rows_every)
+    pj = np.repeat(rows, nu)
+    pi = np.tile(np.arange(nu), rows.size)
+    pt = np.zeros_like(pj)
+    t0 = time.perf_counter()
+    val = oracle.project_pixels(p.geom, p.grid, coef, mu, scale, quat, rho, angles, w, pt, pj, pi)
+    g = val - 0.9 * val
+    oracle.project_bwd(p.geom, p.grid, coef, mu, scale, quat, rho, angles, w,
+                       pixels=(pt, pj, pi, g))
+    dt = time.perf_counter() - t0
+    frac = pj.size / float(nu * nv)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": frac / dt, "unit": "projections/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle, no cut-off: forward + L2 adjoint of one 512x384 view at "
+                      "every %dth detector row (%d pixels, 200k Gaussians) took %.2f s; value "
+                      "scales that to a whole view" % (rows_every, pj.size, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the HIP-event stage timing (plain timed loop only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the renderer has no multi-GPU path in this build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_22280_amd import _lib, synth
+
+    dev = torch.device("cuda:0")
+    p = synth.batched(seed=args.seed)
+    B = p.extra["batch"]
+    batches = [b for b in synth.batch_schedule(len(p.angles), B, args.seed) if len(b) == B]
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+    # reference phantom -> measured projections; the estimate being fitted is a perturbed copy
+    rng = np.random.default_rng(args.seed + 1)
+    ref = dict(coef=d(p.coef), mu=d(p.mu), scale=d(p.scale), quat=d(p.quat), rho=d(p.rho))
+    est_np = (p.mu + rng.normal(0, 0.3, p.mu.shape).astype(np.float32),
+              p.scale * np.exp(rng.normal(0, 0.05, p.scale.shape)).astype(np.float32),
+              p.quat + rng.normal(0, 0.05, p.quat.shape).astype(np.float32),
+              p.rho * (1 + rng.normal(0, 0.05, p.rho.shape)).astype(np.float32),
+              p.coef * np.float32(0.9))
+    est = dict(mu=d(est_np[0]), scale=d(est_np[1]), quat=d(est_np[2]), rho=d(est_np[3]),
+               coef=d(est_np[4]))
+    ang = [d(p.angles[b]) for b in batches]
+    wts = [d(p.w[b]) for b in batches]
+    ws = _lib.Workspace(dev)
+    meas = []
+    for k in range(len(batches)):
+        meas.append(_lib.project_fwd(p.geom, p.grid, ref["coef"], ref["mu"], ref["scale"],
+                                     ref["quat"], ref["rho"], ang[k], wts[k], ws).clone())
+    diag = ws.diagnostics()
+    if diag["overflow"]:
+        raise SystemExit("instance capacity exceeded while rendering the measured projections")
+    n, G, Gd = p.n, p.geom, p.grid
+    proj = torch.empty((B, G["nv"], G["nu"]), device=dev)
+    grads = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
+                 g_quat=torch.empty((4, n), device=dev), g_rho=torch.empty((n,), device=dev),
+                 g_coef=torch.empty_like(est["coef"]), g_w=torch.empty((B, Gd["R"]), device=dev))
+
+    def step(k):
+        kb = k % len(batches)
+        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], ws, proj=proj)
+        proj.sub_(meas[kb])                       # dL/dI of L = 1/2 ||I - P||^2
+        _lib.project_bwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], proj, ws, reuse_fwd=True, out=grads)
+
+    ws.reset()
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    # algorithmic pair counts of the batches the timed steps use
+    pairs = []
+    for k in range(args.steps):
+        kb = (args.warmup + k) % len(batches)
+        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], ws, proj=proj)
+        pairs.append(_lib.count_pairs(G, Gd, n, B, ws))
+    torch.cuda.synchronize()
+
+    if not args.no_profile:
+        _lib.profile_enable(True)
+        _lib.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {}
+    if not args.no_profile:
+        prof = _lib.profile_read(reset=True)
+        _lib.profile_enable(False)
+    diag = ws.diagnostics()
+    if diag["overflow"] or diag["nonfinite"]:
+        raise SystemExit("diagnostics report a problem: %s" % diag)
+
+    value = B * args.steps / dt
+    in_fp = sum(x[0] for x in pairs)
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "projections/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched_200k: 200k Gaussians (lung phantom), 512x384 detector "
+                                  "at 0.8 mm, 1320 views / 60 s, batches of 64 uneven-time "
+                                  "views, rank-3 FFD on 29^3 (10 mm)",
+                      "global_batch": B, "gaussians": n, "detector": [G["nu"], G["nv"]],
+                      "parallelism": "single GPU"}}
+    out["hbm_roofline_end_to_end"] = {
+        "algorithmic_bytes_per_projection": int(ALGO_BYTES_PER_PROJ),
+        "achieved_GBs": round(value * ALGO_BYTES_PER_PROJ / 1e9, 3),
+        "frac": round(value * ALGO_BYTES_PER_PROJ / 1e9 / HBM_PEAK_GBS, 6)}
+    if prof:
+        stages = {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items() if v[0]}
+        totals = {k: v[1] for k, v in prof.items() if v[0]}
+        out["stage_avg_ms_per_launch"] = stages
+        out["stage_share"] = {k: round(v / sum(totals.values()), 4) for k, v in totals.items()}
+        dom = max(("splat_fwd", "splat_bwd"), key=lambda k: totals.get(k, 0.0))
+        avg_s = prof[dom][1] / prof[dom][0] / 1e3
+        per_launch_pairs = in_fp / len(pairs)
+        flop, valu, trans = ((FWD_FLOP, FWD_VALU, FWD_TRANS) if dom == "splat_fwd" else
+                             (BWD_FLOP, BWD_VALU, BWD_TRANS))
+        achieved = per_launch_pairs * flop / avg_s / 1e12
+        peak = peak_tflops(flop, valu, trans)
+        out["roofline"] = {"kernel": "k_" + dom, "bound": "alu", "achieved": round(achieved, 3),
+                           "peak": round(peak, 2), "unit": "TFLOP/s",
+                           "frac": round(achieved / peak, 4), "traffic": None,
+                           "avg_launch_ms": round(avg_s * 1e3, 4),
+                           "pairs_per_launch": int(per_launch_pairs),
+                           "flop_per_pair": flop}
+        out["pairs_per_projection"] = {
+            "in_footprint": int(in_fp / len(pairs) / B),
+            "evaluated_fwd": int(sum(x[1] for x in pairs) / len(pairs) / B),
+            "evaluated_bwd": int(sum(x[2] for x in pairs) / len(pairs) / B)}
+    if not args.no_cpu_baseline:
+        params = tuple(x.astype(np.float64) for x in est_np[:4]) + (est_np[4],)
+        out["cpu_baseline"] = cpu_baseline(p, params, batches[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

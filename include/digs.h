@@ -152,6 +152,28 @@ int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, const float *
 int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);
 int digs_reset_diagnostics(void *ws, void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Measurement support (not on the compute path).
+ * digs_count_pairs: after a digs_project_fwd on `ws` (same arguments), synchronises `stream` and
+ * counts, over that call's projections: out[0] the (Gaussian, pixel) pairs inside each cut-off
+ * footprint and on the detector (the algorithmic work of the splat), out[1] the pairs the forward
+ * splat evaluates (8x8 pixel blocks touched by a footprint box), out[2] the pairs the backward
+ * splat evaluates (256 per (Gaussian, tile) instance). Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP.
+ * digs_profile_enable / digs_profile_read: when enabled, every kernel stage launched by the
+ * library is bracketed by two HIP events recorded on its launch stream; digs_profile_read
+ * waits for the recorded events and returns, per stage, the launches and summed milliseconds
+ * (reset != 0 clears the sums). Single-threaded use only. Returns the number of entries. */
+typedef struct digs_profile_entry {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} digs_profile_entry;
+
+int digs_count_pairs(const digs_geom *geom, const digs_grid *grid, int n, int T, void *ws,
+                     size_t ws_bytes, const digs_tuning *tuning, uint64_t *out, void *stream);
+int digs_profile_enable(int on);
+int digs_profile_read(digs_profile_entry *out, int max_entries, int reset);
+
 /* Message for a DIGS_E* code; the HIP error code of the last DIGS_EHIP on this thread. */
 const char *digs_strerror(int code);
 int digs_last_hip_error(void);

@@ -74,6 +74,12 @@ _SIGS = {
                                         ctypes.POINTER(Tuning), ctypes.c_int, _VP]),
     "digs_read_diagnostics": (ctypes.c_int, [_VP, ctypes.POINTER(Diag), _VP]),
     "digs_reset_diagnostics": (ctypes.c_int, [_VP, _VP]),
+    "digs_count_pairs": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), ctypes.c_int,
+                                        ctypes.c_int, _VP, ctypes.c_size_t,
+                                        ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_uint64),
+                                        _VP]),
+    "digs_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "digs_profile_read": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
     "digs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "digs_last_hip_error": (ctypes.c_int, []),
 }
@@ -252,3 +258,34 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
         _ptr(out["g_w"]), _ptr(buf), buf.numel(), _byref(Tu),
         DIGS_BWD_REUSE_FWD if reuse_fwd else 0, _stream(stream)))
     return out
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+def profile_enable(on: bool = True):
+    load().digs_profile_enable(1 if on else 0)
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{stage: (launches, total_ms)} from the HIP events recorded around each stage launch."""
+    buf = (ProfileEntry * 32)()
+    k = load().digs_profile_read(ctypes.cast(buf, ctypes.c_void_p), 32, 1 if reset else 0)
+    if k < 0:
+        raise DigsError("digs_profile_read", k)
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+            for i in range(k)}
+
+
+def count_pairs(geom: dict, grid: dict, n: int, T: int, ws: Workspace,
+                tuning: dict | None = None, stream=None):
+    """(pairs inside the cut-off footprints, forward-evaluated pairs, backward-evaluated pairs)
+    of the last project_fwd on ws."""
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    out = (ctypes.c_uint64 * 3)()
+    _check("digs_count_pairs", load().digs_count_pairs(
+        ctypes.byref(G), ctypes.byref(R), n, T, _ptr(ws.buf), ws.buf.numel(), _byref(Tu), out,
+        _stream(stream)))
+    return int(out[0]), int(out[1]), int(out[2])

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdigs.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "ffd.hip", "render.hip", "scan.hip", "plan.hip", "voxel.hip", "mlp.hip"]
+SOURCES = ["api.hip", "ffd.hip", "render.hip", "scan.hip", "prof.hip", "plan.hip", "voxel.hip",
+           "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

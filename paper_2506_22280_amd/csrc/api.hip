@@ -241,6 +241,30 @@ extern "C" int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, co
     return check(e);
 }
 
+extern "C" int digs_count_pairs(const digs_geom *geom, const digs_grid *grid, int n, int T,
+                                void *ws, size_t ws_bytes, const digs_tuning *tuning,
+                                uint64_t *out, void *stream)
+{
+    RenderArgs a;
+    if (!out) return DIGS_EINVAL;
+    const float dummy = 0.0f;
+    int rc = prepare(geom, grid, &dummy, n, &dummy, &dummy, &dummy, &dummy, T, &dummy, &dummy,
+                     ws, ws_bytes, tuning, &a);
+    if (rc) return rc;
+    out[0] = out[1] = out[2] = 0;
+    if (n == 0 || T == 0) return DIGS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = render_count_pairs(a, s);
+    DiagBlock d;
+    if (e == hipSuccess) e = hipMemcpyAsync(&d, ws, sizeof(d), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return digs_set_hip_error(e);
+    out[0] = d.stat[0];
+    out[1] = d.stat[1];
+    out[2] = d.stat[2];
+    return DIGS_OK;
+}
+
 extern "C" int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream)
 {
     if (!ws || !out) return DIGS_EINVAL;

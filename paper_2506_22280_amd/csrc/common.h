@@ -42,12 +42,13 @@ struct DevGrid {
 struct DiagBlock {           // device copy of digs_diag plus internal totals
     unsigned long long instances;
     unsigned long long capacity;
+    unsigned long long stat[3];   // digs_count_pairs
     unsigned int overflow;
     unsigned int nonfinite;
     unsigned int folded;
     unsigned int behind_source;
     unsigned int wide;
-    unsigned int reserved[7];
+    unsigned int reserved[1];
 };
 
 __device__ __forceinline__ int lane_id()

@@ -63,3 +63,4 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
                            float *g_scale, float *g_quat, float *g_rho, float *g_coef,
                            float *g_w, hipStream_t s);                   // a6-a8
 hipError_t render_zero(float *p, size_t count, hipStream_t s);
+hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s);   // measurement only

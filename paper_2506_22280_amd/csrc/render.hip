@@ -31,8 +31,10 @@
 #include "bin.h"
 #include "ffd_device.h"
 #include "kernels.h"
+#include "prof.h"
 
 #define SETUP_TCHUNK 8
+#define WS(a, off, type) reinterpret_cast<type>((a).ws + (a).L.off)
 #define SQRT_2PI 2.5066282746310002f
 #define C2_EXP2 (-0.72134752044448170f)   // -log2(e)/2
 #define LN2 0.69314718055994531f
@@ -438,6 +440,68 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
             proj[((size_t)t * G.nv + py) * G.nu + px] = acc * en;
         }
     }
+}
+
+// Measurement only: the pairs inside each footprint and on the detector, the pairs the forward
+// splat evaluates (64 per touched 8x8 block) and the pairs the backward splat evaluates.
+__global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, float cull,
+                                                     const float *__restrict__ rec,
+                                                     const uint32_t *__restrict__ list,
+                                                     const uint32_t *__restrict__ cnt, int nblk,
+                                                     unsigned cap, DiagBlock *__restrict__ diag)
+{
+    __shared__ unsigned long long tot[3];
+    if (threadIdx.x < 3) tot[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.y, tile = blockIdx.x;
+    const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
+    const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
+    const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
+    uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
+    begin = min(begin, cap);
+    end = min(max(end, begin), cap);
+    const int bx = tx * DIGS_TILE + (wave & 1) * 8, by = ty * DIGS_TILE + (wave >> 1) * 8;
+    const int px = bx + (lane & 7), py = by + (lane >> 3);
+    const bool on_det = px < G.nu && py < G.nv;
+    const float c2r2 = (-0.72134752044448170f) * cull * cull;   // exp2 argument at the cut-off
+    unsigned long long in_fp = 0, eval_f = 0;
+    for (uint32_t k = begin; k < end; ++k) {
+        const uint32_t g = uniform(list[k]);
+        if (g >= (uint32_t)n) continue;
+        const float *r = rec + ((size_t)t * n + g) * DIGS_REC_FLOATS;
+        const int bxr = __float_as_int(r[11]), byr = __float_as_int(r[12]);
+        const int x0 = bxr & 0xffff, x1 = bxr >> 16, y0 = byr & 0xffff, y1 = byr >> 16;
+        if (x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7) continue;
+        eval_f += 64;
+        const float du = (float)px - r[0], dv = (float)py - r[1];
+        const float q = fmaf(du, fmaf(r[7], du, fmaf(r[8], dv, r[5])),
+                             fmaf(dv, fmaf(r[9], dv, r[6]), 1.0f));
+        const float e = fmaf(du, fmaf(r[2], du, r[3] * dv), r[4] * dv * dv);
+        const bool inside = on_det && q > 0.0f && e >= c2r2 * q;
+        in_fp += __popcll(__ballot(inside));
+    }
+    if (lane == 0) {
+        atomicAdd(&tot[0], in_fp);
+        atomicAdd(&tot[1], eval_f);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&diag->stat[0], tot[0]);
+        atomicAdd(&diag->stat[1], tot[1]);
+        atomicAdd(&diag->stat[2], (unsigned long long)(end - begin) * DIGS_TILE_PX);
+    }
+}
+
+__global__ void k_stat_reset(DiagBlock *d) { d->stat[0] = d->stat[1] = d->stat[2] = 0; }
+
+hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stat_reset, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *));
+    hipLaunchKernelGGL(k_count_pairs, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, a.n,
+                       a.T, a.cull, WS(a, rec, const float *), WS(a, list, const uint32_t *),
+                       WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
+                       WS(a, diag, DiagBlock *));
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
@@ -901,22 +965,29 @@ __global__ __launch_bounds__(128) void k_coef_grad(DevGrid g, const float *__res
 
 // ------------------------------------------------------------------------------------------
 // host orchestration
-#define WS(a, off, type) reinterpret_cast<type>((a).ws + (a).L.off)
-
 template <class Src>
 static hipError_t launch_binning(const Src &src, int slices, int nbins, int nblk, int nbits,
                                  uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
                                  hipStream_t s)
 {
     const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_bin_count<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
-                       cnt, nbins, nblk);
+    {
+        ProfScope ps(PS_BIN_COUNT, s);
+        hipLaunchKernelGGL(k_bin_count<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
+                           cnt, nbins, nblk);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_exclusive_scan(cnt, cnt_elems, scratch, s);
+    {
+        ProfScope ps(PS_SCAN, s);
+        e = launch_exclusive_scan(cnt, cnt_elems, scratch, s);
+    }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_fill<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src, cnt,
-                       nbins, nblk, nbits);
+    {
+        ProfScope ps(PS_BIN_FILL, s);
+        hipLaunchKernelGGL(k_bin_fill<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
+                           cnt, nbins, nblk, nbits);
+    }
     return hipGetLastError();
 }
 
@@ -947,23 +1018,32 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_diag_begin, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *),
                        (unsigned long long)a.L.cap, cnt + cnt_elems);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ffd_canonical, dim3((a.n + 255) / 256), dim3(256), 0, s, a.grid,
-                       a.coef, a.n, a.mu, WS(a, uv, float *));
+    {
+        ProfScope ps(PS_FFD, s);
+        hipLaunchKernelGGL(k_ffd_canonical, dim3((a.n + 255) / 256), dim3(256), 0, s, a.grid,
+                           a.coef, a.n, a.mu, WS(a, uv, float *));
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    switch (a.grid.R) {
-    case 1: e = setup_dispatch<1>(a, s); break;
-    case 2: e = setup_dispatch<2>(a, s); break;
-    case 3: e = setup_dispatch<3>(a, s); break;
-    case 4: e = setup_dispatch<4>(a, s); break;
-    case 5: e = setup_dispatch<5>(a, s); break;
-    case 6: e = setup_dispatch<6>(a, s); break;
-    case 7: e = setup_dispatch<7>(a, s); break;
-    default: e = setup_dispatch<8>(a, s); break;
+    {
+        ProfScope ps(PS_SETUP, s);
+        switch (a.grid.R) {
+        case 1: e = setup_dispatch<1>(a, s); break;
+        case 2: e = setup_dispatch<2>(a, s); break;
+        case 3: e = setup_dispatch<3>(a, s); break;
+        case 4: e = setup_dispatch<4>(a, s); break;
+        case 5: e = setup_dispatch<5>(a, s); break;
+        case 6: e = setup_dispatch<6>(a, s); break;
+        case 7: e = setup_dispatch<7>(a, s); break;
+        default: e = setup_dispatch<8>(a, s); break;
+        }
     }
     if (e != hipSuccess) return e;
     uint32_t *scratch = WS(a, scratch, uint32_t *);
     // per-(t,n) instance offsets (Gaussian-major), then the tile lists
-    e = launch_exclusive_scan(WS(a, gcount, uint32_t *), (size_t)a.T * a.n, scratch, s);
+    {
+        ProfScope ps(PS_SCAN, s);
+        e = launch_exclusive_scan(WS(a, gcount, uint32_t *), (size_t)a.T * a.n, scratch, s);
+    }
     if (e != hipSuccess) return e;
     TileSrc src;
     src.rect = WS(a, rect, const int2 *);
@@ -984,6 +1064,7 @@ hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
 {
     dim3 grid(a.geom.ntiles, a.T);
     const unsigned cap = (unsigned)a.L.cap;
+    ProfScope ps(PS_SPLAT_FWD, s);
     if (a.splat_waves == 1)
         hipLaunchKernelGGL(k_splat_fwd<1>, grid, dim3(64), 0, s, a.geom, a.n, a.T,
                            WS(a, rec, const float *), WS(a, list, const uint32_t *),
@@ -1003,37 +1084,42 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     const int n = a.n, T = a.T;
     const int nb = (n + 255) / 256;
     const int nparts = nb * 4;
-    hipLaunchKernelGGL(k_gauss_bwd<NR>, dim3(nb), dim3(256), 0, s, a.geom, a.grid, n, T, a.coef,
-                       a.mu, a.scale, a.quat, a.rho, a.angles, a.w, WS(a, uv, const float *),
-                       WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
-                       WS(a, inv, const uint32_t *), WS(a, part, const float4 *),
-                       (unsigned)a.L.cap, WS(a, pos_of, const uint32_t *), g_mu, g_scale, g_quat,
-                       g_rho, WS(a, gwpart, float *), nparts, WS(a, gq, float *), a.L.gq_stride);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    {
+        ProfScope ps(PS_GAUSS_BWD, s);
+        hipLaunchKernelGGL(k_gauss_bwd<NR>, dim3(nb), dim3(256), 0, s, a.geom, a.grid, n, T,
+                           a.coef, a.mu, a.scale, a.quat, a.rho, a.angles, a.w,
+                           WS(a, uv, const float *), WS(a, rect, const int2 *),
+                           WS(a, gcount, const uint32_t *), WS(a, inv, const uint32_t *),
+                           WS(a, part, const float4 *), (unsigned)a.L.cap,
+                           WS(a, pos_of, const uint32_t *), g_mu, g_scale, g_quat, g_rho,
+                           WS(a, gwpart, float *), nparts, WS(a, gq, float *), a.L.gq_stride);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gw_final, dim3((T * NR + 63) / 64), dim3(64), 0, s, T, NR,
-                       WS(a, gwpart, const float *), nparts, g_w);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        ProfScope ps(PS_OTHER, s);
+        hipLaunchKernelGGL(k_gw_final, dim3((T * NR + 63) / 64), dim3(64), 0, s, T, NR,
+                           WS(a, gwpart, const float *), nparts, g_w);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
     const int npts = a.grid.nx * a.grid.ny * a.grid.nz;
-    hipLaunchKernelGGL(k_coef_grad<NR>, dim3((npts + 127) / 128), dim3(128), 0, s, a.grid,
-                       WS(a, gq, const float *), a.L.gq_stride, WS(a, cell_lo, const uint32_t *),
-                       WS(a, cell_hi, const uint32_t *), g_coef);
-    return hipGetLastError();
+    {
+        ProfScope ps(PS_COEF_GRAD, s);
+        hipLaunchKernelGGL(k_coef_grad<NR>, dim3((npts + 127) / 128), dim3(128), 0, s, a.grid,
+                           WS(a, gq, const float *), a.L.gq_stride,
+                           WS(a, cell_lo, const uint32_t *), WS(a, cell_hi, const uint32_t *),
+                           g_coef);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
-hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
-                           float *g_scale, float *g_quat, float *g_rho, float *g_coef,
-                           float *g_w, hipStream_t s)
+static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
 {
     hipError_t e;
     const int n = a.n;
-    // a6: per-instance moment sums
-    hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, n, a.T,
-                       WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
-                       WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap, grad_proj,
-                       WS(a, part, float4 *));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // cell sort of the Gaussians (LSD radix, 8 bits per pass)
     uint32_t *ka = WS(a, keys_a, uint32_t *), *va = WS(a, vals_a, uint32_t *);
     uint32_t *kb = WS(a, keys_b, uint32_t *), *vb = WS(a, vals_b, uint32_t *);
     hipLaunchKernelGGL(k_cell_keys, dim3((n + 255) / 256), dim3(256), 0, s, a.grid, n, a.mu, ka,
@@ -1049,8 +1135,8 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
         src.vals_out = vb;
         src.items = n;
         src.shift = shift;
-        e = launch_binning(src, 1, 256, nblk_r, 8, WS(a, rhist, uint32_t *), (size_t)256 * nblk_r,
-                           WS(a, scratch, uint32_t *), s);
+        e = launch_binning(src, 1, 256, nblk_r, 8, WS(a, rhist, uint32_t *),
+                           (size_t)256 * nblk_r, WS(a, scratch, uint32_t *), s);
         if (e != hipSuccess) return e;
         uint32_t *t0 = ka; ka = kb; kb = t0;
         t0 = va; va = vb; vb = t0;
@@ -1062,7 +1148,27 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
     hipLaunchKernelGGL(k_cell_ranges, dim3((n + 255) / 256), dim3(256), 0, s, n, ka, va,
                        WS(a, cell_lo, uint32_t *), WS(a, cell_hi, uint32_t *),
                        WS(a, pos_of, uint32_t *));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
+                           float *g_scale, float *g_quat, float *g_rho, float *g_coef,
+                           float *g_w, hipStream_t s)
+{
+    hipError_t e;
+    // a6: per-instance moment sums
+    {
+        ProfScope ps(PS_SPLAT_BWD, s);
+        hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, a.n,
+                           a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
+                           WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap, grad_proj,
+                           WS(a, part, float4 *));
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    // cell sort of the Gaussians (LSD radix, 8 bits per pass); its binning stages are timed
+    // under their own names
+    if ((e = cell_sort(a, s)) != hipSuccess) return e;
     switch (a.grid.R) {
     case 1: return backward_dispatch<1>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
     case 2: return backward_dispatch<2>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
