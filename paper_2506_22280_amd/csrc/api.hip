@@ -116,8 +116,8 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->keys_b = take(sizeof(uint32_t) * N);
     L->vals_b = take(sizeof(uint32_t) * N);
     L->rhist = take(sizeof(uint32_t) * 256 * (size_t)nblk_r);
-    L->cell_lo = take(sizeof(uint32_t) * L->ncells);
-    L->cell_hi = take(sizeof(uint32_t) * L->ncells);
+    L->cell_start = take(sizeof(uint32_t) * ((size_t)L->ncells + 1));
+    L->tnout = take(sizeof(float) * 22 * TN);
     L->pos_of = take(sizeof(uint32_t) * N);
     L->gq = take(sizeof(float) * L->gq_stride * N);
     L->total = off;

@@ -101,9 +101,9 @@ __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
                                                           float h[3])
 {
     const float *base = coef + (size_t)r * g.nz * g.ny * g.nx * 3;
-#pragma unroll
+#pragma unroll 1
     for (int n = 0; n < 4; ++n) {
-#pragma unroll
+#pragma unroll 1
         for (int m = 0; m < 4; ++m) {
             const float *row = base + ((size_t)(s.kk[n] * g.ny + s.jj[m]) * g.nx) * 3;
 #pragma unroll

@@ -19,7 +19,8 @@ struct WsLayout {
     size_t gwpart;     // [T][R][4*ceil(N/256)] f32 per-wave partial sums of dL/dw
     size_t keys_a, vals_a, keys_b, vals_b;  // [N] u32 cell sort ping-pong
     size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
-    size_t cell_lo, cell_hi;                // [ncells] u32 range of each lattice cell
+    size_t cell_start;                      // [ncells + 1] u32 first position of each cell
+    size_t tnout;      // [22][T][N] f32 per-(t,n) adjoint results
     size_t pos_of;     // [N] u32 position of Gaussian n in cell order
     size_t gq;         // [N][6 + 12R] f32 per-Gaussian coefficient-gradient sources, cell order
     size_t total;

@@ -12,9 +12,11 @@
 // Backward:
 //   k_splat_bwd      one lane per (Gaussian, tile) instance looping over the tile's 256 pixels,
 //                    accumulating 12 moment sums; written per instance (no atomics)
-//   k_gauss_bwd      per Gaussian, over the call's projections: sums its instances, runs the
-//                    set-up and warp adjoints, reduces to the canonical parameters, and emits the
-//                    per-wave partial sums of dL/dw and the sources of dL/dcoef
+//   k_tn_bwd         per (t, n): sums the instance partials and runs the set-up and warp adjoints;
+//                    per-wave partial sums of dL/dw
+//   k_gauss_reduce   per Gaussian, over the call's projections in order: reduces to the canonical
+//                    parameters (with the second-derivative term) and emits the sources of
+//                    dL/dcoef
 //   k_cell_*         stable radix sort of the Gaussians by lattice cell
 //   k_coef_grad      each control point gathers from the Gaussians of its 4x4x4 cells
 //
@@ -304,18 +306,17 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
         mycount += count;
         if (valid) {
             const size_t o = (size_t)t * n + i;
-            const float a = (ok ? f.amp : 0.0f);
-            rec[o * 4 + 0] = make_float4(f.us, f.vs, C2_EXP2 * f.Huu, 2.0f * C2_EXP2 * f.Huv);
-            rec[o * 4 + 1] = make_float4(C2_EXP2 * f.Hvv, 2.0f * f.gu, 2.0f * f.gv, f.Guu);
-            rec[o * 4 + 2] = make_float4(2.0f * f.Guv, f.Gvv, a,
-                                         __int_as_float(x0 | (x1 << 16)));
-            rec[o * 4 + 3] = make_float4(__int_as_float(y0 | (y1 << 16)), 0.0f, 0.0f, 0.0f);
-            if (!ok) {   // keep the record finite for the splat
+            if (ok) {
+                rec[o * 4 + 0] = make_float4(f.us, f.vs, C2_EXP2 * f.Huu, 2.0f * C2_EXP2 * f.Huv);
+                rec[o * 4 + 1] = make_float4(C2_EXP2 * f.Hvv, 2.0f * f.gu, 2.0f * f.gv, f.Guu);
+                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, f.Gvv, f.amp, 0.0f);
+            } else {   // keep the record finite
                 rec[o * 4 + 0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 rec[o * 4 + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                rec[o * 4 + 2] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(1));
-                rec[o * 4 + 3] = make_float4(__int_as_float(1), 0.0f, 0.0f, 0.0f);
+                rec[o * 4 + 2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
+            rec[o * 4 + 3] = make_float4(__int_as_float(x0 | (x1 << 16)),
+                                         __int_as_float(y0 | (y1 << 16)), 0.0f, 0.0f);
             rect[o] = rr;
             gcount[o] = count;
         }
@@ -393,51 +394,110 @@ struct RadixSrc {
 };
 
 // ------------------------------------------------------------------------------------------
-// a5: forward splat. One workgroup per (projection, tile); with 4 waves each wave owns an 8x8
-// pixel block and skips Gaussians whose box misses it; with 1 wave the wave owns the 16x16 tile
-// in 4 passes of 64 pixels.
+// a5: forward splat. One workgroup per (projection, tile), one wave per 8x8 pixel block (with
+// WAVES == 1 a single wave takes the tile's four blocks in turn). The wave walks the tile's list
+// in chunks of 64 entries, keeps the Gaussians whose footprint box meets its block (ballot and
+// compaction in LDS) and evaluates them 8 at a time: lane = (Gaussian slot, column), each lane
+// running down the 8 rows of its column with forward differences of the two quadratic forms
+// (two adds each per row). The per-lane row sums are reduced over the 8 slots at the end in a
+// fixed order, and every pixel is written once.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
-                                                          const float *__restrict__ rec,
+                                                          const float4 *__restrict__ rec,
                                                           const uint32_t *__restrict__ list,
                                                           const uint32_t *__restrict__ cnt,
                                                           int nblk, unsigned cap,
                                                           float *__restrict__ proj)
 {
+    __shared__ uint32_t ids[WAVES][DIGS_WAVE];
     const int t = blockIdx.y, tile = blockIdx.x;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
-    const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
+    const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
+    const int gslot = lane >> 3, col = lane & 7;
     const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
     uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
-    const float cu = 0.5f * (float)(G.nu - 1), cv = 0.5f * (float)(G.nv - 1);
-#pragma unroll
+    const float4 *rt = rec + (size_t)t * n * 4;
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int pass = 0; pass < 4 / WAVES; ++pass) {
         const int blkid = (WAVES == 4) ? wave : pass;
         const int bx = tx * DIGS_TILE + (blkid & 1) * 8, by = ty * DIGS_TILE + (blkid >> 1) * 8;
-        const int px = bx + (lane & 7), py = by + (lane >> 3);
-        const float fi = (float)px, fj = (float)py;
-        float acc = 0.0f;
-        for (uint32_t k = begin; k < end; ++k) {
-            const uint32_t g = uniform(list[k]);
-            if (g >= (uint32_t)n) continue;
-            const float *r = rec + ((size_t)t * n + g) * DIGS_REC_FLOATS;
-            const int bxr = __float_as_int(r[11]), byr = __float_as_int(r[12]);
-            const int x0 = bxr & 0xffff, x1 = bxr >> 16, y0 = byr & 0xffff, y1 = byr >> 16;
-            if (x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7) continue;
-            const float du = fi - r[0], dv = fj - r[1];
-            const float q = fmaf(du, fmaf(r[7], du, fmaf(r[8], dv, r[5])),
-                                 fmaf(dv, fmaf(r[9], dv, r[6]), 1.0f));
-            const float e = fmaf(du, fmaf(r[2], du, r[3] * dv), r[4] * dv * dv);
-            const float rs = __builtin_amdgcn_rsqf(q);
-            const float x = e * (rs * rs);
-            acc = fmaf(r[10] * rs, __builtin_amdgcn_exp2f(x), acc);
+        const float fi = (float)(bx + col), fby = (float)by;
+        float acc[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc[r] = 0.0f;
+        for (uint32_t c0 = begin; c0 < end; c0 += DIGS_WAVE) {
+            const uint32_t k = c0 + lane;
+            uint32_t g = 0;
+            bool hit = false;
+            if (k < end) {
+                g = list[k];
+                if (g < (uint32_t)n) {
+                    const float4 b = rt[(size_t)g * 4 + 3];
+                    const int bxr = __float_as_int(b.x), byr = __float_as_int(b.y);
+                    hit = !((bxr >> 16) < bx || (bxr & 0xffff) > bx + 7 || (byr >> 16) < by ||
+                            (byr & 0xffff) > by + 7);
+                }
+            }
+            const unsigned long long m = __ballot(hit);
+            const int ns = __popcll(m);
+            if (hit) ids[wave][__popcll(m & lanemask_lt())] = g;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int j = 0; j < ns; j += 8) {
+                const int s = j + gslot;
+                float4 r0 = zero4, r1 = zero4, r2 = zero4;
+                if (s < ns) {
+                    const size_t gg = ids[wave][s];
+                    r0 = rt[gg * 4 + 0];
+                    r1 = rt[gg * 4 + 1];
+                    r2 = rt[gg * 4 + 2];
+                }
+                // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu), r2 = (Guv2, Gvv, amp, -)
+                const float du = fi - r0.x, dv0 = fby - r0.y;
+                const float Aq = fmaf(du, fmaf(r1.w, du, r1.y), 1.0f);
+                const float Bq = fmaf(r2.x, du, r1.z), Cq = r2.y;
+                const float AE = r0.z * du * du, BE = r0.w * du, CE = r1.x;
+                const float s1 = fmaf(2.0f, dv0, 1.0f);
+                float q = fmaf(dv0, fmaf(Cq, dv0, Bq), Aq);
+                float dq = fmaf(Cq, s1, Bq);
+                const float ddq = 2.0f * Cq;
+                float e = fmaf(dv0, fmaf(CE, dv0, BE), AE);
+                float de = fmaf(CE, s1, BE);
+                const float dde = 2.0f * CE;
+                const float amp = r2.z;
+#pragma unroll
+                for (int row = 0; row < 8; ++row) {
+                    const float rs = __builtin_amdgcn_rsqf(q);
+                    const float x = e * (rs * rs);
+                    acc[row] = fmaf(amp * rs, __builtin_amdgcn_exp2f(x), acc[row]);
+                    q += dq;
+                    dq += ddq;
+                    e += de;
+                    de += dde;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
+        // sum over the 8 Gaussian slots (lane bits 3..5) in a fixed order
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            acc[r] += __shfl_xor(acc[r], 8, 64);
+            acc[r] += __shfl_xor(acc[r], 16, 64);
+            acc[r] += __shfl_xor(acc[r], 32, 64);
+        }
+        float v = acc[0];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v = (gslot == r) ? acc[r] : v;
+        const int px = bx + col, py = by + gslot;
         if (px < G.nu && py < G.nv) {
-            const float xu = (fi - cu) * G.pitch_u + G.off_u, yv = (fj - cv) * G.pitch_v + G.off_v;
-            const float en = sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
-            proj[((size_t)t * G.nv + py) * G.nu + px] = acc * en;
+            const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
+            const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
+            proj[((size_t)t * G.nv + py) * G.nu + px] =
+                v * sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
         }
     }
 }
@@ -469,7 +529,7 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
         const uint32_t g = uniform(list[k]);
         if (g >= (uint32_t)n) continue;
         const float *r = rec + ((size_t)t * n + g) * DIGS_REC_FLOATS;
-        const int bxr = __float_as_int(r[11]), byr = __float_as_int(r[12]);
+        const int bxr = __float_as_int(r[12]), byr = __float_as_int(r[13]);
         const int x0 = bxr & 0xffff, x1 = bxr >> 16, y0 = byr & 0xffff, y1 = byr >> 16;
         if (x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7) continue;
         eval_f += 64;
@@ -505,13 +565,19 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 }
 
 // ------------------------------------------------------------------------------------------
-// a6: backward splat. Lane = (Gaussian, tile) instance; the tile's dL/dI (times |e|) is staged in
-// LDS and read by broadcast. Twelve moment sums per instance:
+// a6: backward splat. One workgroup per (projection, tile); the tile's dL/dI (times |e|) is staged
+// in LDS (row stride 18 keeps the four 8x8 blocks in distinct banks). Each wave takes chunks of
+// 64 list entries, compacts the (entry, 8x8 block) pairs whose footprint box meets the block into
+// a pair list (block-major), and gives each lane one pair: the lane runs over the block's 64
+// pixels with forward differences along each row and accumulates twelve moment sums, which are
+// added into the entry's LDS slot in block order (fixed order, no atomics) and written as the
+// instance's partial:
 //  0 S_amp = sum g r 2^x      (dL/damp)
 //  1 S_Euu, 2 S_Euv, 3 S_Evv  sum A_E du^2, du dv, dv^2   (A_E = dL/dE, E natural)
 //  4 S_quu, 5 S_quv, 6 S_qvv  sum A_q du^2, du dv, dv^2   (A_q = dL/dq)
 //  7 S_qu, 8 S_qv, 9 S_q      sum A_q du, dv, 1
 //  10 S_Eu, 11 S_Ev           sum A_E du, dv
+#define GPX_STRIDE 18
 __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                                                    const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ list,
@@ -520,10 +586,12 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                                                    const float *__restrict__ grad_proj,
                                                    float4 *__restrict__ part)
 {
-    __shared__ float gpx[DIGS_TILE_PX];
+    __shared__ float gpx[DIGS_TILE * GPX_STRIDE];
+    __shared__ uint32_t pairs[4][4 * DIGS_WAVE];
+    __shared__ float accS[4][DIGS_WAVE][13];
     const int t = blockIdx.y, tile = blockIdx.x;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
-    const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
+    const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
     {
         const int p = threadIdx.x;
         const int px = tx * DIGS_TILE + (p & 15), py = ty * DIGS_TILE + (p >> 4);
@@ -534,118 +602,346 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
             gv = grad_proj[((size_t)t * G.nv + py) * G.nu + px] *
                  sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
         }
-        gpx[p] = gv;
+        gpx[(p >> 4) * GPX_STRIDE + (p & 15)] = gv;
     }
     __syncthreads();
     const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
     uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
-    const float ox = (float)(tx * DIGS_TILE), oy = (float)(ty * DIGS_TILE);
-    for (uint32_t base = begin + wave * DIGS_WAVE; base < end; base += 4 * DIGS_WAVE) {
-        const uint32_t k = base + lane;
-        bool active = k < end;
-        uint32_t g = active ? list[k] : 0u;
-        active = active && g < (uint32_t)n;
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-        if (active) {
-            const float4 *r = rec + ((size_t)t * n + g) * 4;
-            r0 = r[0];
-            r1 = r[1];
-            r2 = r[2];
+    const float4 *rt = rec + (size_t)t * n * 4;
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int tx0 = tx * DIGS_TILE, ty0 = ty * DIGS_TILE;
+    float *acc = &accS[wave][lane][0];
+    for (uint32_t c0 = begin + wave * DIGS_WAVE; c0 < end; c0 += 4 * DIGS_WAVE) {
+        const uint32_t k = c0 + lane;
+        bool valid = k < end;
+        uint32_t g = valid ? list[k] : 0u;
+        valid = valid && g < (uint32_t)n;
+        int bx0 = 1, bx1 = 0, by0 = 1, by1 = 0;
+        if (valid) {
+            const float4 b = rt[(size_t)g * 4 + 3];
+            const int bxr = __float_as_int(b.x), byr = __float_as_int(b.y);
+            bx0 = bxr & 0xffff; bx1 = bxr >> 16; by0 = byr & 0xffff; by1 = byr >> 16;
         }
-        const float us = r0.x, vs = r0.y, Hu = r0.z, Huv = r0.w, Hv = r1.x, gu2 = r1.y,
-                    gv2 = r1.z, Guu = r1.w, Guv2 = r2.x, Gvv = r2.y, amp = r2.z;
-        float S[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) S[c] = 0.0f;
-        const float du0 = ox - us, dv0 = oy - vs;
-        for (int row = 0; row < DIGS_TILE; ++row) {
-            const float dv = dv0 + (float)row;
-            const float dv2 = dv * dv;
-            const float qv = fmaf(dv, fmaf(Gvv, dv, gv2), 1.0f);
-            const float ev = Hv * dv2;
-            for (int col = 0; col < DIGS_TILE; ++col) {
-                const float gval = gpx[row * DIGS_TILE + col];
-                if (gval == 0.0f) continue;
-                const float du = du0 + (float)col;
-                const float q = fmaf(du, fmaf(Guu, du, fmaf(Guv2, dv, gu2)), qv);
-                const float e = fmaf(du, fmaf(Hu, du, Huv * dv), ev);
-                const float rs = __builtin_amdgcn_rsqf(q);
-                const float r2s = rs * rs;
-                const float x = e * r2s;
-                const float gr = gval * rs * __builtin_amdgcn_exp2f(x);
-                const float aE = -0.5f * gr * amp * r2s;
-                const float aq = aE * fmaf(2.0f * LN2, x, 1.0f);
-                const float du2 = du * du, duv = du * dv;
-                S[0] += gr;
-                S[1] = fmaf(aE, du2, S[1]);
-                S[2] = fmaf(aE, duv, S[2]);
-                S[3] = fmaf(aE, dv2, S[3]);
-                S[4] = fmaf(aq, du2, S[4]);
-                S[5] = fmaf(aq, duv, S[5]);
-                S[6] = fmaf(aq, dv2, S[6]);
-                S[7] = fmaf(aq, du, S[7]);
-                S[8] = fmaf(aq, dv, S[8]);
-                S[9] += aq;
-                S[10] = fmaf(aE, du, S[10]);
-                S[11] = fmaf(aE, dv, S[11]);
+        for (int c = 0; c < 12; ++c) acc[c] = 0.0f;
+        int np = 0;
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            const int bx = tx0 + (blk & 1) * 8, by = ty0 + (blk >> 1) * 8;
+            const bool hit = valid && !(bx1 < bx || bx0 > bx + 7 || by1 < by || by0 > by + 7);
+            const unsigned long long m = __ballot(hit);
+            if (hit) pairs[wave][np + __popcll(m & lanemask_lt())] = ((uint32_t)lane << 2) | blk;
+            np += __popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int j = 0; j < np; j += DIGS_WAVE) {
+            const int pidx = j + lane;
+            const bool active = pidx < np;
+            const uint32_t pr = active ? pairs[wave][pidx] : 0u;
+            const int e = (int)(pr >> 2), blk = (int)(pr & 3u);
+            const uint32_t ge = (uint32_t)__shfl((int)g, e, 64);
+            float4 r0 = zero4, r1 = zero4, r2 = zero4;
+            if (active) {
+                r0 = rt[(size_t)ge * 4 + 0];
+                r1 = rt[(size_t)ge * 4 + 1];
+                r2 = rt[(size_t)ge * 4 + 2];
+            }
+            // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu), r2 = (Guv2, Gvv, amp, -)
+            const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8;
+            const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
+            const float cA = -0.5f * r2.z;
+            const float Cq = r1.w, CE = r0.z;
+            const float s1 = fmaf(2.0f, du0, 1.0f);
+            const float qa = fmaf(Cq, du0, 0.0f), ea = CE * du0;
+            float S[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) S[c] = 0.0f;
+            const float *gp = gpx + lby * GPX_STRIDE + lbx;
+            for (int row = 0; row < 8; ++row) {
+                const float dv = dv0 + (float)row;
+                // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
+                const float Bq = fmaf(r2.x, dv, r1.y);
+                const float Aq = fmaf(dv, fmaf(r2.y, dv, r1.z), 1.0f);
+                const float BE = r0.w * dv, AE = r1.x * dv * dv;
+                float q = fmaf(du0, qa + Bq, Aq);
+                float dq = fmaf(Cq, s1, Bq);
+                const float ddq = 2.0f * Cq;
+                float ee = fmaf(du0, ea + BE, AE);
+                float de = fmaf(CE, s1, BE);
+                const float dde = 2.0f * CE;
+                float du = du0;
+                float e0 = 0.f, e1 = 0.f, e2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const float gval = gp[row * GPX_STRIDE + c];
+                    const float rs = __builtin_amdgcn_rsqf(q);
+                    const float r2s = rs * rs;
+                    const float x = ee * r2s;
+                    const float gr = gval * rs * __builtin_amdgcn_exp2f(x);
+                    const float aE = gr * (cA * r2s);
+                    const float aq = aE * fmaf(2.0f * LN2, x, 1.0f);
+                    S[0] += gr;
+                    e0 += aE;
+                    const float tE = aE * du;
+                    e1 += tE;
+                    e2 = fmaf(tE, du, e2);
+                    q0 += aq;
+                    const float tq = aq * du;
+                    q1 += tq;
+                    q2 = fmaf(tq, du, q2);
+                    du += 1.0f;
+                    q += dq;
+                    dq += ddq;
+                    ee += de;
+                    de += dde;
+                }
+                const float dv2 = dv * dv;
+                S[1] += e2;
+                S[2] = fmaf(dv, e1, S[2]);
+                S[3] = fmaf(dv2, e0, S[3]);
+                S[4] += q2;
+                S[5] = fmaf(dv, q1, S[5]);
+                S[6] = fmaf(dv2, q0, S[6]);
+                S[7] += q1;
+                S[8] = fmaf(dv, q0, S[8]);
+                S[9] += q0;
+                S[10] += e1;
+                S[11] = fmaf(dv, e0, S[11]);
+            }
+            // add into the entry's slot, one block at a time (an entry appears once per block)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (active && blk == b) {
+                    float *dst = &accS[wave][e][0];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) dst[c] += S[c];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
         if (k < end) {
-            part[(size_t)k * 3 + 0] = make_float4(S[0], S[1], S[2], S[3]);
-            part[(size_t)k * 3 + 1] = make_float4(S[4], S[5], S[6], S[7]);
-            part[(size_t)k * 3 + 2] = make_float4(S[8], S[9], S[10], S[11]);
+            part[(size_t)k * 3 + 0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            part[(size_t)k * 3 + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+            part[(size_t)k * 3 + 2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// a7: per-Gaussian adjoint of the set-up and of the warp, summed over the call's projections.
+// a7: adjoint of the set-up and of the warp. k_tn_bwd runs one thread per (t, n): it sums the
+// instance partials of (t, n), recomputes the set-up, and back-propagates the record gradients to
+// dL/dmu', dL/dK, dL/d(R diag(s)) and dL/drho, which it stores per (t, n); it also forms the
+// per-(t, n) terms of dL/dw[t][r] and reduces them per wave in a fixed order. k_gauss_reduce then
+// runs one thread per Gaussian over the call's projections (fixed order), adds the term through
+// K(mu) (second derivatives of the B-spline), and finishes the chain to the canonical parameters.
+#define TN_FIELDS 22   // gmu' (3), gK (9), gRS (9), grho (1)
+
 template <int NR>
-__global__ __launch_bounds__(256) void k_gauss_bwd(
-    DevGeom G, DevGrid grid, int n, int T, const float *__restrict__ coef,
-    const float *__restrict__ mu, const float *__restrict__ scale, const float *__restrict__ quat,
-    const float *__restrict__ rho, const float *__restrict__ angles, const float *__restrict__ w,
-    const float *__restrict__ uv, const int2 *__restrict__ rect,
-    const uint32_t *__restrict__ goff, const uint32_t *__restrict__ inv,
-    const float4 *__restrict__ part, unsigned cap, const uint32_t *__restrict__ pos_of,
-    float *__restrict__ g_mu, float *__restrict__ g_scale, float *__restrict__ g_quat,
-    float *__restrict__ g_rho, float *__restrict__ gwpart, int nparts, float *__restrict__ gq,
-    int gq_stride)
+__global__ __launch_bounds__(256) void k_tn_bwd(
+    DevGeom G, int n, int T, const float *__restrict__ mu, const float *__restrict__ scale,
+    const float *__restrict__ quat, const float *__restrict__ rho,
+    const float *__restrict__ angles, const float *__restrict__ w, const float *__restrict__ uv,
+    const int2 *__restrict__ rect, const uint32_t *__restrict__ goff,
+    const uint32_t *__restrict__ inv, const float4 *__restrict__ part, unsigned cap,
+    float *__restrict__ tnout, float *__restrict__ gwpart, int nparts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     const int lane = lane_id(), wave = threadIdx.x / DIGS_WAVE;
-    float mu0[3], s[3], q[4], Rm[9], inv_s[3];
-    float U[NR][3], V[NR][9];
+    const size_t o = (size_t)t * n + ii;
+    const int2 rr = rect[o];
+    const int tx0 = rr.x & 0xffff, tx1 = rr.x >> 16, ty0 = rr.y & 0xffff, ty1 = rr.y >> 16;
+    const int cntk = (valid && tx1 >= tx0 && ty1 >= ty0) ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
+    float out[TN_FIELDS];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        mu0[a] = mu[(size_t)a * n + ii];
-        s[a] = scale[(size_t)a * n + ii];
-        inv_s[a] = 1.0f / s[a];
+    for (int c = 0; c < TN_FIELDS; ++c) out[c] = 0.0f;
+    float gwc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) gwc[r] = 0.0f;
+    if (cntk > 0) {
+        float S[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) S[c] = 0.0f;
+        const uint32_t base = goff[o];
+        for (int k = 0; k < cntk; ++k) {
+            if ((size_t)base + k >= cap) break;
+            const uint32_t p = inv[base + k];
+            if (p >= cap) continue;
+            const float4 a = part[(size_t)p * 3 + 0], b = part[(size_t)p * 3 + 1],
+                         c = part[(size_t)p * 3 + 2];
+            S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
+            S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
+            S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
+        }
+        float mu0[3], s[3], inv_s[3], q[4], Rm[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mu0[a] = mu[(size_t)a * n + ii];
+            s[a] = scale[(size_t)a * n + ii];
+            inv_s[a] = 1.0f / s[a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + ii];
+        const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        quat_to_rot(q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn, Rm);
+        const float rh = rho[ii];
+        float U[NR][3], V[NR][9], wt[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            wt[r] = w[(size_t)t * NR + r];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) U[r][a] = uv[((size_t)r * 3 + a) * n + ii];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
+        }
+        ViewTrig vt;
+        sincosf(angles[t], &vt.st, &vt.ct);
+        SetupFwd f;
+        setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
+        // record gradients from the moment sums
+        const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
+        const float gGuu = S[4], gGuv = 2.0f * S[5], gGvv = S[6];
+        const float ggu = 2.0f * S[7], ggv = 2.0f * S[8];
+        const float gamp = S[0];
+        const float gus = -2.0f * (f.Huu * S[10] + f.Huv * S[11] + f.gu * S[9] + f.Guu * S[7] +
+                                   f.Guv * S[8]);
+        const float gvs = -2.0f * (f.Huv * S[10] + f.Hvv * S[11] + f.gv * S[9] + f.Guv * S[7] +
+                                   f.Gvv * S[8]);
+        // reverse of the record formulas
+        const float sic = sqrtf(f.ic);
+        const float grho = gamp * SQRT_2PI * f.beta * sic;
+        float gbeta = gamp * rh * SQRT_2PI * sic;
+        float gc = -0.5f * gamp * f.amp * f.ic;
+        const float Duu = dot3(f.Du, f.Du), Duv = dot3(f.Du, f.Dv), Dvv = dot3(f.Dv, f.Dv);
+        float gkap = (gGuu * Duu + gGuv * Duv + gGvv * Dvv) * f.ic;
+        gc -= (gGuu * f.Guu + gGuv * f.Guv + gGvv * f.Gvv) * f.ic;
+        float gDu[3], gDv[3], gmw[3], gDup[3], gDvp[3];
+        const float kic = f.kap * f.ic;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gDu[a] = kic * (2.0f * gGuu * f.Du[a] + gGuv * f.Dv[a]);
+            gDv[a] = kic * (2.0f * gGvv * f.Dv[a] + gGuv * f.Du[a]);
+        }
+        gbeta -= ggu * f.pa + ggv * f.pb;
+        float gpa = -ggu * f.beta, gpb = -ggv * f.beta;
+        gkap += gHuu * dot3(f.Dup, f.Dup) + gHuv * dot3(f.Dup, f.Dvp) + gHvv * dot3(f.Dvp, f.Dvp);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gDup[a] = f.kap * (2.0f * gHuu * f.Dup[a] + gHuv * f.Dvp[a]);
+            gDvp[a] = f.kap * (2.0f * gHvv * f.Dvp[a] + gHuv * f.Dup[a]);
+        }
+        gbeta += 2.0f * f.beta * gkap;
+        gpa -= dot3(gDup, f.mw);
+        gpb -= dot3(gDvp, f.mw);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gDu[a] += gDup[a];
+            gDv[a] += gDvp[a];
+            gmw[a] = -f.pa * gDup[a] - f.pb * gDvp[a];
+        }
+        const float gdu = gpa * f.ic, gdv = gpb * f.ic;
+        gc -= (gpa * f.pa + gpb * f.pb) * f.ic;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gmw[a] += gdu * f.Du[a] + gdv * f.Dv[a] + 2.0f * gc * f.mw[a];
+            gDu[a] += gdu * f.mw[a];
+            gDv[a] += gdv * f.mw[a];
+        }
+        float galpha = gbeta / G.sdd;
+        const float ia = 1.0f / f.alpha;
+        const float kuf = G.sdd * ia / G.pitch_u, kvf = G.sdd * ia / G.pitch_v;
+        const float gxu = -gus * kuf, gxv = -gvs * kvf;
+        galpha += gus * kuf * f.xu * ia + gvs * kvf * f.xv * ia;
+        // mw = W m, Du = pu W e_u, Dv = pv W e_v
+        const float eu[3] = {-vt.st, vt.ct, 0.0f};
+        float gW[9], gm[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                gW[3 * a + b] = gmw[a] * f.m[b] + G.pitch_u * gDu[a] * eu[b] +
+                                (b == 2 ? G.pitch_v * gDv[a] : 0.0f);
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            gm[b] = f.W[b] * gmw[0] + f.W[3 + b] * gmw[1] + f.W[6 + b] * gmw[2];
+        float gmup[3] = {-gm[0], -gm[1], -gm[2]};
+        gmup[0] += -vt.ct * galpha + vt.st * gxu;
+        gmup[1] += -vt.st * galpha - vt.ct * gxu;
+        gmup[2] += -gxv;
+        // W = M^-1: dL/dM = -W^T gW W^T
+        float T1[9], gM[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                T1[3 * a + b] = f.W[a] * gW[b] + f.W[3 + a] * gW[3 + b] + f.W[6 + a] * gW[6 + b];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                gM[3 * a + b] = -(T1[3 * a] * f.W[3 * b] + T1[3 * a + 1] * f.W[3 * b + 1] +
+                                  T1[3 * a + 2] * f.W[3 * b + 2]);
+        // M = K (R S): dL/dK = gM (RS)^T, dL/d(RS) = K^T gM
+        float RS[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) RS[3 * a + b] = Rm[3 * a + b] * s[b];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = gmup[a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                out[3 + 3 * a + b] = gM[3 * a] * RS[3 * b] + gM[3 * a + 1] * RS[3 * b + 1] +
+                                     gM[3 * a + 2] * RS[3 * b + 2];
+                out[12 + 3 * a + b] = f.K[a] * gM[b] + f.K[3 + a] * gM[3 + b] +
+                                      f.K[6 + a] * gM[6 + b];
+            }
+        out[21] = grho;
+        // per-(t, n) term of dL/dw[t][r] = u_r . dL/dmu' + grad u_r : dL/dK
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            float c = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) c = fmaf(U[r][a], out[a], c);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) c = fmaf(V[r][k], out[3 + k], c);
+            gwc[r] = c;
+        }
     }
+    if (valid) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + ii];
-    const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const float qh[4] = {q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn};
-    quat_to_rot(qh[0], qh[1], qh[2], qh[3], Rm);
-    const float rh = rho[ii];
+        for (int c = 0; c < TN_FIELDS; ++c) tnout[((size_t)c * T + t) * n + i] = out[c];
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) U[r][a] = uv[((size_t)r * 3 + a) * n + ii];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
+        const float sm = wave_sum(gwc[r]);
+        if (lane == 0) gwpart[((size_t)t * NR + r) * nparts + blockIdx.x * 4 + wave] = sm;
     }
-    float RS[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) RS[3 * a + b] = Rm[3 * a + b] * s[b];
+}
 
-    float gsum_mu[3] = {0.f, 0.f, 0.f}, gRS[9], P[NR][3], Q[NR][9], grho = 0.0f;
+template <int NR>
+__global__ __launch_bounds__(256) void k_gauss_reduce(
+    DevGrid grid, int n, int T, const float *__restrict__ coef, const float *__restrict__ mu,
+    const float *__restrict__ scale, const float *__restrict__ quat,
+    const float *__restrict__ w, const float *__restrict__ uv, const float *__restrict__ tnout,
+    const uint32_t *__restrict__ pos_of, float *__restrict__ g_mu, float *__restrict__ g_scale,
+    float *__restrict__ g_quat, float *__restrict__ g_rho, float *__restrict__ gq, int gq_stride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gsum[3] = {0.f, 0.f, 0.f}, gRS[9], P[NR][3], Q[NR][9], grho = 0.0f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) gRS[k] = 0.0f;
 #pragma unroll
@@ -655,171 +951,51 @@ __global__ __launch_bounds__(256) void k_gauss_bwd(
 #pragma unroll
         for (int k = 0; k < 9; ++k) Q[r][k] = 0.0f;
     }
-
+    const size_t TN = (size_t)T * n;
     for (int t = 0; t < T; ++t) {
-        float gwc[NR];
+        const float *src = tnout + (size_t)t * n + i;
+        float gmup[3], gK[9];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gwc[r] = 0.0f;
-        const int2 rr = rect[(size_t)t * n + ii];
-        const int tx0 = rr.x & 0xffff, tx1 = rr.x >> 16, ty0 = rr.y & 0xffff, ty1 = rr.y >> 16;
-        const int cntk = (valid && tx1 >= tx0 && ty1 >= ty0) ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
-                                                             : 0;
-        if (cntk > 0) {
-            float S[12];
+        for (int a = 0; a < 3; ++a) gmup[a] = src[a * TN];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) S[c] = 0.0f;
-            const uint32_t o = goff[(size_t)t * n + ii];
-            for (int k = 0; k < cntk; ++k) {
-                if ((size_t)o + k >= cap) break;
-                const uint32_t p = inv[o + k];
-                if (p >= cap) continue;
-                const float4 a = part[(size_t)p * 3 + 0], b = part[(size_t)p * 3 + 1],
-                             c = part[(size_t)p * 3 + 2];
-                S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
-                S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
-                S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
-            }
-            float wt[NR];
+        for (int k = 0; k < 9; ++k) gK[k] = src[(3 + k) * TN];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) wt[r] = w[(size_t)t * NR + r];
-            ViewTrig vt;
-            sincosf(angles[t], &vt.st, &vt.ct);
-            SetupFwd f;
-            setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
-            // record gradients from the moment sums
-            const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
-            const float gGuu = S[4], gGuv = 2.0f * S[5], gGvv = S[6];
-            const float ggu = 2.0f * S[7], ggv = 2.0f * S[8];
-            const float gamp = S[0];
-            const float gus = -2.0f * (f.Huu * S[10] + f.Huv * S[11] + f.gu * S[9] +
-                                       f.Guu * S[7] + f.Guv * S[8]);
-            const float gvs = -2.0f * (f.Huv * S[10] + f.Hvv * S[11] + f.gv * S[9] +
-                                       f.Guv * S[7] + f.Gvv * S[8]);
-            // reverse of the record formulas
-            const float sic = sqrtf(f.ic);
-            grho += gamp * SQRT_2PI * f.beta * sic;
-            float gbeta = gamp * rh * SQRT_2PI * sic;
-            float gc = -0.5f * gamp * f.amp * f.ic;
-            const float Duu = dot3(f.Du, f.Du), Duv = dot3(f.Du, f.Dv), Dvv = dot3(f.Dv, f.Dv);
-            float gkap = (gGuu * Duu + gGuv * Duv + gGvv * Dvv) * f.ic;
-            gc -= (gGuu * f.Guu + gGuv * f.Guv + gGvv * f.Gvv) * f.ic;
-            float gDu[3], gDv[3], gmw[3], gDup[3], gDvp[3];
-            const float kic = f.kap * f.ic;
+        for (int k = 0; k < 9; ++k) gRS[k] += src[(12 + k) * TN];
+        grho += src[21 * TN];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                gDu[a] = kic * (2.0f * gGuu * f.Du[a] + gGuv * f.Dv[a]);
-                gDv[a] = kic * (2.0f * gGvv * f.Dv[a] + gGuv * f.Du[a]);
-            }
-            gbeta -= ggu * f.pa + ggv * f.pb;
-            float gpa = -ggu * f.beta, gpb = -ggv * f.beta;
-            gkap += gHuu * dot3(f.Dup, f.Dup) + gHuv * dot3(f.Dup, f.Dvp) +
-                    gHvv * dot3(f.Dvp, f.Dvp);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                gDup[a] = f.kap * (2.0f * gHuu * f.Dup[a] + gHuv * f.Dvp[a]);
-                gDvp[a] = f.kap * (2.0f * gHvv * f.Dvp[a] + gHuv * f.Dup[a]);
-            }
-            gbeta += 2.0f * f.beta * gkap;
-            gpa -= dot3(gDup, f.mw);
-            gpb -= dot3(gDvp, f.mw);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                gDu[a] += gDup[a];
-                gDv[a] += gDvp[a];
-                gmw[a] = -f.pa * gDup[a] - f.pb * gDvp[a];
-            }
-            const float gdu = gpa * f.ic, gdv = gpb * f.ic;
-            gc -= (gpa * f.pa + gpb * f.pb) * f.ic;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                gmw[a] += gdu * f.Du[a] + gdv * f.Dv[a] + 2.0f * gc * f.mw[a];
-                gDu[a] += gdu * f.mw[a];
-                gDv[a] += gdv * f.mw[a];
-            }
-            float galpha = gbeta / G.sdd;
-            const float ia = 1.0f / f.alpha;
-            const float kuf = G.sdd * ia / G.pitch_u, kvf = G.sdd * ia / G.pitch_v;
-            const float gxu = -gus * kuf, gxv = -gvs * kvf;
-            galpha += gus * kuf * f.xu * ia + gvs * kvf * f.xv * ia;
-            // mw = W m, Du = pu W e_u, Dv = pv W e_v
-            const float eu[3] = {-vt.st, vt.ct, 0.0f};
-            float gW[9], gm[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    gW[3 * a + b] = gmw[a] * f.m[b] + G.pitch_u * gDu[a] * eu[b] +
-                                    (b == 2 ? G.pitch_v * gDv[a] : 0.0f);
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                gm[b] = f.W[b] * gmw[0] + f.W[3 + b] * gmw[1] + f.W[6 + b] * gmw[2];
-            float gmup[3] = {-gm[0], -gm[1], -gm[2]};
-            gmup[0] += -vt.ct * galpha + vt.st * gxu;
-            gmup[1] += -vt.st * galpha - vt.ct * gxu;
-            gmup[2] += -gxv;
-            // W = M^-1: dL/dM = -W^T gW W^T
-            float T1[9], gM[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    T1[3 * a + b] = f.W[a] * gW[b] + f.W[3 + a] * gW[3 + b] + f.W[6 + a] * gW[6 + b];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    gM[3 * a + b] = -(T1[3 * a] * f.W[3 * b] + T1[3 * a + 1] * f.W[3 * b + 1] +
-                                      T1[3 * a + 2] * f.W[3 * b + 2]);
-            // M = K (R S): dL/dK = gM (RS)^T, dL/d(RS) += K^T gM
-            float gK[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    gK[3 * a + b] = gM[3 * a] * RS[3 * b] + gM[3 * a + 1] * RS[3 * b + 1] +
-                                    gM[3 * a + 2] * RS[3 * b + 2];
-                    gRS[3 * a + b] += f.K[a] * gM[b] + f.K[3 + a] * gM[3 + b] +
-                                      f.K[6 + a] * gM[6 + b];
-                }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) gsum_mu[a] += gmup[a];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                float c = 0.0f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    P[r][a] = fmaf(wt[r], gmup[a], P[r][a]);
-                    c = fmaf(U[r][a], gmup[a], c);
-                }
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    Q[r][k] = fmaf(wt[r], gK[k], Q[r][k]);
-                    c = fmaf(V[r][k], gK[k], c);
-                }
-                gwc[r] = c;
-            }
-        }
-        // dL/dw[t][r]: per-wave partial sums in a fixed order
+        for (int a = 0; a < 3; ++a) gsum[a] += gmup[a];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const float sm = wave_sum(gwc[r]);
-            if (lane == 0)
-                gwpart[((size_t)t * NR + r) * nparts + blockIdx.x * 4 + wave] = sm;
+            const float wr = w[(size_t)t * NR + r];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) P[r][a] = fmaf(wr, gmup[a], P[r][a]);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Q[r][k] = fmaf(wr, gK[k], Q[r][k]);
         }
     }
-    if (!valid) return;
     // dL/dmu = sum_t dL/dmu' + sum_r V_r^T P_r + sum_r Q_r : d(grad u_r)/dmu
-    float gmu[3] = {gsum_mu[0], gsum_mu[1], gsum_mu[2]};
+    float gmu[3] = {gsum[0], gsum[1], gsum[2]};
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            gmu[c] += V[r][c] * P[r][0] + V[r][3 + c] * P[r][1] + V[r][6 + c] * P[r][2];
+        for (int c = 0; c < 3; ++c) {
+            const float *V = uv + ((size_t)3 * NR + r * 9) * n + i;
+            gmu[c] += V[c * (size_t)n] * P[r][0] + V[(3 + c) * (size_t)n] * P[r][1] +
+                      V[(6 + c) * (size_t)n] * P[r][2];
+        }
+    const float mu0[3] = {mu[i], mu[n + i], mu[2 * n + i]};
     Stencil st;
-    DevGrid gg = grid;
-    make_stencil(gg, mu0[0], mu0[1], mu0[2], st, true);
-    for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(gg, coef, r, st, Q[r], gmu);
-    // RS = R diag(s)
+    make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
+    for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(grid, coef, r, st, Q[r], gmu);
+    // R diag(s) -> s, R(q)
+    const float s[3] = {scale[i], scale[n + i], scale[2 * n + i]};
+    float q[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + i];
+    const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float qh[4] = {q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn};
+    float Rm[9];
+    quat_to_rot(qh[0], qh[1], qh[2], qh[3], Rm);
     float gR[9], gs[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -889,27 +1065,34 @@ __global__ void k_cell_keys(DevGrid g, int n, const float *__restrict__ mu,
     vals[i] = (uint32_t)i;
 }
 
-__global__ void k_cell_ranges(int n, const uint32_t *__restrict__ keys,
-                              const uint32_t *__restrict__ vals, uint32_t *__restrict__ lo,
-                              uint32_t *__restrict__ hi, uint32_t *__restrict__ pos_of)
+// cell_start[k] = number of Gaussians whose cell key is below k (for every key 0..ncells);
+// pos_of[n] = position of Gaussian n in cell order
+__global__ void k_cell_start(int n, int ncells, const uint32_t *__restrict__ keys,
+                             const uint32_t *__restrict__ vals, uint32_t *__restrict__ cell_start,
+                             uint32_t *__restrict__ pos_of)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) lo[k] = (uint32_t)p;
-    if (p == n - 1 || keys[p + 1] != k) hi[k] = (uint32_t)p + 1;
-    const uint32_t v = vals[p];
-    if (v < (uint32_t)n) pos_of[v] = (uint32_t)p;
+    if (p > n) return;
+    const uint32_t hi = (p < n) ? min(keys[p], (uint32_t)ncells) : (uint32_t)ncells;
+    const uint32_t lo = (p > 0) ? min(keys[p - 1], (uint32_t)ncells) + 1u : 0u;
+    for (uint32_t k = lo; k <= hi; ++k) cell_start[k] = (uint32_t)p;
+    if (p < n) {
+        const uint32_t v = vals[p];
+        if (v < (uint32_t)n) pos_of[v] = (uint32_t)p;
+    }
 }
 
+// One wave per control point: for each (cz, cy) row of its candidate cells the Gaussians of
+// the cells cx = lx..hx are contiguous in cell order; lanes stride over them, and the per-lane
+// sums are reduced over the wave in a fixed order.
 template <int NR>
-__global__ __launch_bounds__(128) void k_coef_grad(DevGrid g, const float *__restrict__ gq,
+__global__ __launch_bounds__(256) void k_coef_grad(DevGrid g, const float *__restrict__ gq,
                                                    int gq_stride,
-                                                   const uint32_t *__restrict__ lo,
-                                                   const uint32_t *__restrict__ hi,
+                                                   const uint32_t *__restrict__ cell_start,
                                                    float *__restrict__ g_coef)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = blockIdx.x * 4 + threadIdx.x / DIGS_WAVE;
+    const int lane = lane_id();
     const int npts = g.nx * g.ny * g.nz;
     if (idx >= npts) return;
     const int i = idx % g.nx, j = (idx / g.nx) % g.ny, k = idx / (g.nx * g.ny);
@@ -921,46 +1104,48 @@ __global__ __launch_bounds__(128) void k_coef_grad(DevGrid g, const float *__res
     const int lz = (k == 0) ? -2 : k - 2, hz = (k == g.nz - 1) ? g.nz + 1 : k + 1;
     const float ihx = 1.0f / g.hx, ihy = 1.0f / g.hy, ihz = 1.0f / g.hz;
     for (int cz = lz; cz <= hz; ++cz)
-        for (int cy = ly; cy <= hy; ++cy)
-            for (int cx = lx; cx <= hx; ++cx) {
-                const uint32_t cell = ((uint32_t)(cz + 2) * (g.ny + 4) + (cy + 2)) * (g.nx + 4) +
-                                      (cx + 2);
-                const uint32_t b = lo[cell], e = hi[cell];
-                for (uint32_t p = b; p < e; ++p) {
-                    const float *o = gq + (size_t)p * gq_stride;
-                    float B[4], dB[4];
-                    float wx = 0.f, dwx = 0.f, wy = 0.f, dwy = 0.f, wz = 0.f, dwz = 0.f;
-                    bspline4(o[3], B);
-                    bspline4_d(o[3], dB);
+        for (int cy = ly; cy <= hy; ++cy) {
+            const uint32_t row = ((uint32_t)(cz + 2) * (g.ny + 4) + (cy + 2)) * (g.nx + 4);
+            const uint32_t b = cell_start[row + (lx + 2)], e = cell_start[row + (hx + 2) + 1];
+            for (uint32_t p = b + lane; p < e; p += DIGS_WAVE) {
+                const float *o = gq + (size_t)p * gq_stride;
+                const int cx = __float_as_int(o[0]);
+                float B[4], dB[4];
+                float wx = 0.f, dwx = 0.f, wy = 0.f, dwy = 0.f, wz = 0.f, dwz = 0.f;
+                bspline4(o[3], B);
+                bspline4_d(o[3], dB);
 #pragma unroll
-                    for (int l = 0; l < 4; ++l)
-                        if (clampi(cx - 1 + l, g.nx) == i) { wx += B[l]; dwx += dB[l]; }
-                    bspline4(o[4], B);
-                    bspline4_d(o[4], dB);
+                for (int l = 0; l < 4; ++l)
+                    if (clampi(cx - 1 + l, g.nx) == i) { wx += B[l]; dwx += dB[l]; }
+                bspline4(o[4], B);
+                bspline4_d(o[4], dB);
 #pragma unroll
-                    for (int l = 0; l < 4; ++l)
-                        if (clampi(cy - 1 + l, g.ny) == j) { wy += B[l]; dwy += dB[l]; }
-                    bspline4(o[5], B);
-                    bspline4_d(o[5], dB);
+                for (int l = 0; l < 4; ++l)
+                    if (clampi(cy - 1 + l, g.ny) == j) { wy += B[l]; dwy += dB[l]; }
+                bspline4(o[5], B);
+                bspline4_d(o[5], dB);
 #pragma unroll
-                    for (int l = 0; l < 4; ++l)
-                        if (clampi(cz - 1 + l, g.nz) == k) { wz += B[l]; dwz += dB[l]; }
-                    const float w0 = wx * wy * wz, w1 = dwx * ihx * wy * wz,
-                                w2 = wx * dwy * ihy * wz, w3 = wx * wy * dwz * ihz;
+                for (int l = 0; l < 4; ++l)
+                    if (clampi(cz - 1 + l, g.nz) == k) { wz += B[l]; dwz += dB[l]; }
+                const float w0 = wx * wy * wz, w1 = dwx * ihx * wy * wz,
+                            w2 = wx * dwy * ihy * wz, w3 = wx * wy * dwz * ihz;
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        const float *Pr = o + 6 + 12 * r, *Qr = Pr + 3;
+                for (int r = 0; r < NR; ++r) {
+                    const float *Pr = o + 6 + 12 * r, *Qr = Pr + 3;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a)
-                            acc[r][a] += w0 * Pr[a] + w1 * Qr[3 * a] + w2 * Qr[3 * a + 1] +
-                                         w3 * Qr[3 * a + 2];
-                    }
+                    for (int a = 0; a < 3; ++a)
+                        acc[r][a] += w0 * Pr[a] + w1 * Qr[3 * a] + w2 * Qr[3 * a + 1] +
+                                     w3 * Qr[3 * a + 2];
                 }
             }
+        }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) g_coef[((size_t)r * npts + idx) * 3 + a] = acc[r][a];
+        for (int a = 0; a < 3; ++a) {
+            const float v = wave_sum(acc[r][a]);
+            if (lane == 0) g_coef[((size_t)r * npts + idx) * 3 + a] = v;
+        }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1067,11 +1252,11 @@ hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
     ProfScope ps(PS_SPLAT_FWD, s);
     if (a.splat_waves == 1)
         hipLaunchKernelGGL(k_splat_fwd<1>, grid, dim3(64), 0, s, a.geom, a.n, a.T,
-                           WS(a, rec, const float *), WS(a, list, const uint32_t *),
+                           WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, cap, proj);
     else
         hipLaunchKernelGGL(k_splat_fwd<4>, grid, dim3(256), 0, s, a.geom, a.n, a.T,
-                           WS(a, rec, const float *), WS(a, list, const uint32_t *),
+                           WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, cap, proj);
     return hipGetLastError();
 }
@@ -1087,14 +1272,20 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     hipError_t e;
     {
         ProfScope ps(PS_GAUSS_BWD, s);
-        hipLaunchKernelGGL(k_gauss_bwd<NR>, dim3(nb), dim3(256), 0, s, a.geom, a.grid, n, T,
-                           a.coef, a.mu, a.scale, a.quat, a.rho, a.angles, a.w,
-                           WS(a, uv, const float *), WS(a, rect, const int2 *),
-                           WS(a, gcount, const uint32_t *), WS(a, inv, const uint32_t *),
-                           WS(a, part, const float4 *), (unsigned)a.L.cap,
-                           WS(a, pos_of, const uint32_t *), g_mu, g_scale, g_quat, g_rho,
-                           WS(a, gwpart, float *), nparts, WS(a, gq, float *), a.L.gq_stride);
+        hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, T), dim3(256), 0, s, a.geom, n, T, a.mu,
+                           a.scale, a.quat, a.rho, a.angles, a.w, WS(a, uv, const float *),
+                           WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
+                           WS(a, inv, const uint32_t *), WS(a, part, const float4 *),
+                           (unsigned)a.L.cap, WS(a, tnout, float *), WS(a, gwpart, float *),
+                           nparts);
         e = hipGetLastError();
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_gauss_reduce<NR>, dim3(nb), dim3(256), 0, s, a.grid, n, T,
+                               a.coef, a.mu, a.scale, a.quat, a.w, WS(a, uv, const float *),
+                               WS(a, tnout, const float *), WS(a, pos_of, const uint32_t *),
+                               g_mu, g_scale, g_quat, g_rho, WS(a, gq, float *), a.L.gq_stride);
+            e = hipGetLastError();
+        }
     }
     if (e != hipSuccess) return e;
     {
@@ -1107,10 +1298,9 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     const int npts = a.grid.nx * a.grid.ny * a.grid.nz;
     {
         ProfScope ps(PS_COEF_GRAD, s);
-        hipLaunchKernelGGL(k_coef_grad<NR>, dim3((npts + 127) / 128), dim3(128), 0, s, a.grid,
+        hipLaunchKernelGGL(k_coef_grad<NR>, dim3((npts + 3) / 4), dim3(256), 0, s, a.grid,
                            WS(a, gq, const float *), a.L.gq_stride,
-                           WS(a, cell_lo, const uint32_t *), WS(a, cell_hi, const uint32_t *),
-                           g_coef);
+                           WS(a, cell_start, const uint32_t *), g_coef);
         e = hipGetLastError();
     }
     return e;
@@ -1141,13 +1331,8 @@ static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
         uint32_t *t0 = ka; ka = kb; kb = t0;
         t0 = va; va = vb; vb = t0;
     }
-    if ((e = fill_u32(WS(a, cell_lo, uint32_t *), (size_t)a.L.ncells, 0u, s)) != hipSuccess)
-        return e;
-    if ((e = fill_u32(WS(a, cell_hi, uint32_t *), (size_t)a.L.ncells, 0u, s)) != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_cell_ranges, dim3((n + 255) / 256), dim3(256), 0, s, n, ka, va,
-                       WS(a, cell_lo, uint32_t *), WS(a, cell_hi, uint32_t *),
-                       WS(a, pos_of, uint32_t *));
+    hipLaunchKernelGGL(k_cell_start, dim3((n + 1 + 255) / 256), dim3(256), 0, s, n, a.L.ncells,
+                       ka, va, WS(a, cell_start, uint32_t *), WS(a, pos_of, uint32_t *));
     return hipGetLastError();
 }
 
