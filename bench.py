@@ -28,11 +28,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd projections/s @200k Gaussians 512×384 det; % HBM roofline; speedup vs plain"
 
-# Algorithmic FP32 work per (Gaussian, pixel) pair inside a footprint (FMA = 2, add/mul = 1,
-# rsqrt/exp2 = 1) and the VALU issue slots it occupies (a transcendental = TRANS_SLOTS slots).
-FWD_FLOP, FWD_VALU, FWD_TRANS = 27, 17, 2
-BWD_FLOP, BWD_VALU, BWD_TRANS = 55, 38, 2
-TRANS_SLOTS = 4
+# Algorithmic FP32 work per (Gaussian, pixel) pair inside a cut-off footprint, in the splats'
+# forward-difference formulation (FMA = 2 FLOP, add/mul = 1, rsqrt/exp2 = 1), and the VALU issue
+# slots it needs: forward 4 adds (q, dq, E, dE) + 3 muls + 1 FMA + rsqrt + exp2; backward the same
+# evaluation plus the 12 moment sums of the adjoint (22 VALU ops + rsqrt + exp2). A transcendental
+# issues at half the FMA rate on gfx950 (measured), i.e. TRANS_SLOTS = 2 slots.
+FWD_FLOP, FWD_VALU, FWD_TRANS = 11, 8, 2
+BWD_FLOP, BWD_VALU, BWD_TRANS = 27, 22, 2
+TRANS_SLOTS = 2
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes per cycle x clock
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per projection of one fwd+bwd step (see the design notes): Gaussians read
@@ -82,6 +85,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event stage timing (plain timed loop only)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the timed region, run a plain device-to-device copy of this many "
+                         "MiB three times (the reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the renderer has no multi-GPU path in this build "
@@ -133,6 +139,13 @@ def main():
         _lib.project_bwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
                          ang[kb], wts[kb], proj, ws, reuse_fwd=True, out=grads)
 
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb << 18, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ws.reset()
     for k in range(args.warmup):
         step(k)

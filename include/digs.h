@@ -158,7 +158,7 @@ int digs_reset_diagnostics(void *ws, void *stream);
  * counts, over that call's projections: out[0] the (Gaussian, pixel) pairs inside each cut-off
  * footprint and on the detector (the algorithmic work of the splat), out[1] the pairs the forward
  * splat evaluates (8x8 pixel blocks touched by a footprint box), out[2] the pairs the backward
- * splat evaluates (256 per (Gaussian, tile) instance). Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP.
+ * splat evaluates (the same blocks). Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP.
  * digs_profile_enable / digs_profile_read: when enabled, every kernel stage launched by the
  * library is bracketed by two HIP events recorded on its launch stream; digs_profile_read
  * waits for the recorded events and returns, per stage, the launches and summed milliseconds

@@ -199,11 +199,21 @@ class Workspace:
     def __init__(self, device="cuda"):
         self.device = device
         self.buf = None
+        self._gen = 0
 
     def get(self, nbytes: int):
         if self.buf is None or self.buf.numel() < nbytes:
             self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self._gen += 1
         return self.buf
+
+    def stamp(self):
+        """Changes whenever a call re-bins into this workspace (or it is reallocated): a
+        backward may reuse the forward's binning only while the stamp is unchanged."""
+        return self._gen
+
+    def touched(self):
+        self._gen += 1
 
     def diagnostics(self, stream=None) -> dict:
         d = Diag()
@@ -231,6 +241,7 @@ def project_fwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, w
         ctypes.byref(G), ctypes.byref(R), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat),
         _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(proj), _ptr(buf), buf.numel(), _byref(Tu),
         _stream(stream)))
+    ws.touched()
     return proj
 
 
@@ -257,6 +268,8 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
         _ptr(out["g_scale"]), _ptr(out["g_quat"]), _ptr(out["g_rho"]), _ptr(out["g_coef"]),
         _ptr(out["g_w"]), _ptr(buf), buf.numel(), _byref(Tu),
         DIGS_BWD_REUSE_FWD if reuse_fwd else 0, _stream(stream)))
+    if not reuse_fwd:
+        ws.touched()
     return out
 
 

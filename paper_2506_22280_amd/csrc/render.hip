@@ -502,8 +502,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
     }
 }
 
-// Measurement only: the pairs inside each footprint and on the detector, the pairs the forward
-// splat evaluates (64 per touched 8x8 block) and the pairs the backward splat evaluates.
+// Measurement only: the pairs inside each footprint and on the detector, and the pairs the forward
+// and backward splats evaluate (64 per 8x8 block that a footprint box touches, in both).
 __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, float cull,
                                                      const float *__restrict__ rec,
                                                      const uint32_t *__restrict__ list,
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
     if (threadIdx.x == 0) {
         atomicAdd(&diag->stat[0], tot[0]);
         atomicAdd(&diag->stat[1], tot[1]);
-        atomicAdd(&diag->stat[2], (unsigned long long)(end - begin) * DIGS_TILE_PX);
+        atomicAdd(&diag->stat[2], tot[1]);   // the backward splat walks the same blocks
     }
 }
 
