@@ -113,6 +113,19 @@ int digs_deform_gaussians(const digs_grid *grid, const float *coef, int n, const
                           const float *scale, const float *quat, int T, const float *w,
                           float *mu_t, float *cov_t, void *stream);
 
+/* digs_temporal_weights -- the temporal weights w_r(t) of the low-rank motion model: a cubic
+ * 1-D B-spline in time (Sec. 3.3, after Eq. 11; Sec. 4.2 places a control value every 4 time
+ * points), with the lattice's knot convention: control value j sits at time t0 + j*dt;
+ * p = (times[t] - t0)/dt, f = floor(p), u = p - f and
+ *   w[t][r] = sum_{l=0..3} B_l(u) ctrl[clamp(f - 1 + l, 0, Ct - 1)][r].
+ *   ctrl [Ct][R] control values, times [T] (any unit, the same as t0 and dt), w [T][R] out.
+ * digs_temporal_weights_bwd: g_ctrl [Ct][R] = the adjoint applied to g_w [T][R] (overwritten).
+ * Errors: DIGS_EINVAL (Ct < 1, R outside 1..8, dt <= 0, null pointers), DIGS_EHIP. */
+int digs_temporal_weights(int Ct, int R, const float *ctrl, float t0, float dt, int T,
+                          const float *times, float *w, void *stream);
+int digs_temporal_weights_bwd(int Ct, int R, float t0, float dt, int T, const float *times,
+                              const float *g_w, float *g_ctrl, void *stream);
+
 /* Workspace bytes that digs_project_fwd / digs_project_bwd need for this problem size (one
  * workspace serves both). Returns 0 for invalid arguments. */
 size_t digs_workspace_size(const digs_geom *geom, const digs_grid *grid, int n, int T,

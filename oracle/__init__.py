@@ -13,6 +13,8 @@ Functions mirror the product's entry points in argument meaning (not in precisio
   project_bwd                 reverse mode of ``project`` for a sparse dL/dI
   line_integral               one Gaussian along one line
   dvf, phi        Eq. 9, 6    displacement field and dynamic attenuation at query points
+  temporal_weights            the 1-D cubic B-spline w_r(t) of the temporal control values, and
+  temporal_weights_bwd        its adjoint
 """
 from __future__ import annotations
 
@@ -82,6 +84,10 @@ def _load():
         lib.oracle_line_integral.restype = ctypes.c_double
         lib.oracle_dvf.argtypes = [ctypes.POINTER(Grid), _P, _P, ctypes.c_int, _P, _P]
         lib.oracle_phi.argtypes = [ctypes.c_int, _P, _P, _P, ctypes.c_int, _P, _P]
+        lib.oracle_temporal_weights.argtypes = [ctypes.c_int, ctypes.c_int, _P, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int, _P, _P]
+        lib.oracle_temporal_weights_bwd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                    ctypes.c_double, ctypes.c_int, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -225,3 +231,23 @@ def phi(mu_t, cov_t, rho, x):
     out = np.zeros(x.shape[1])
     _load().oracle_phi(mu_t.shape[1], pm, pc, pr, x.shape[1], px, out.ctypes.data_as(_P))
     return out
+
+
+def temporal_weights(ctrl, t0: float, dt: float, times):
+    """w[T][R] of the temporal cubic B-spline over control values ctrl[Ct][R] every dt from t0."""
+    ctrl, pc = _d(ctrl); times, pt = _d(np.atleast_1d(times))
+    Ct, R = ctrl.shape
+    w = np.zeros((times.shape[0], R))
+    _load().oracle_temporal_weights(Ct, R, pc, float(t0), float(dt), times.shape[0], pt,
+                                    w.ctypes.data_as(_P))
+    return w
+
+
+def temporal_weights_bwd(Ct: int, t0: float, dt: float, times, g_w):
+    """dL/dctrl[Ct][R] given dL/dw[T][R]."""
+    times, pt = _d(np.atleast_1d(times)); g_w, pg = _d(g_w)
+    R = g_w.shape[1]
+    g = np.zeros((Ct, R))
+    _load().oracle_temporal_weights_bwd(Ct, R, float(t0), float(dt), times.shape[0], pt, pg,
+                                        g.ctypes.data_as(_P))
+    return g

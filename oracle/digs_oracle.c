@@ -683,3 +683,38 @@ void oracle_phi(int n, const double *mu_t, const double *cov_t, const double *rh
         phi[i] = acc;
     }
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Sec. 3.3 (text after Eq. 11) and Sec. 4.2: the temporal weights w_r(t) of the low-rank motion
+ * model are a 1-D cubic B-spline in time over control values c[j][r] placed every `dt` (the paper
+ * uses a control point every 4 time points) starting at t0. The same 0-based knot and clamping
+ * convention as the spatial lattice: p = (t - t0)/dt, f = floor(p), u = p - f,
+ * w_r(t) = sum_l B_l(u) c[clamp(f - 1 + l)][r]. */
+void oracle_temporal_weights(int Ct, int R, const double *ctrl, double t0, double dt, int T,
+                             const double *times, double *w)
+{
+    for (int t = 0; t < T; ++t) {
+        double p = (times[t] - t0) / dt, f = floor(p), B[4], dB[4], d2B[4];
+        oracle_bspline(p - f, B, dB, d2B);
+        for (int r = 0; r < R; ++r) {
+            double acc = 0.0;
+            for (int l = 0; l < 4; ++l) acc += B[l] * ctrl[(size_t)clampi((int)f - 1 + l, Ct) * R + r];
+            w[(size_t)t * R + r] = acc;
+        }
+    }
+}
+
+/* Reverse mode of the above: g_ctrl[j][r] = sum over t and l with clamp(f_t - 1 + l) = j of
+ * B_l(u_t) g_w[t][r]. */
+void oracle_temporal_weights_bwd(int Ct, int R, double t0, double dt, int T, const double *times,
+                                 const double *g_w, double *g_ctrl)
+{
+    memset(g_ctrl, 0, sizeof(double) * (size_t)Ct * R);
+    for (int t = 0; t < T; ++t) {
+        double p = (times[t] - t0) / dt, f = floor(p), B[4], dB[4], d2B[4];
+        oracle_bspline(p - f, B, dB, d2B);
+        for (int l = 0; l < 4; ++l)
+            for (int r = 0; r < R; ++r)
+                g_ctrl[(size_t)clampi((int)f - 1 + l, Ct) * R + r] += B[l] * g_w[(size_t)t * R + r];
+    }
+}

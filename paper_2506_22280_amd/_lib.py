@@ -80,6 +80,11 @@ _SIGS = {
                                         _VP]),
     "digs_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "digs_profile_read": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
+    "digs_temporal_weights": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.c_float,
+                                             ctypes.c_float, ctypes.c_int, _VP, _VP, _VP]),
+    "digs_temporal_weights_bwd": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                                 ctypes.c_float, ctypes.c_int, _VP, _VP, _VP,
+                                                 _VP]),
     "digs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "digs_last_hip_error": (ctypes.c_int, []),
 }
@@ -186,6 +191,25 @@ def deform_gaussians(grid: dict, coef, mu, scale, quat, w, stream=None):
         ctypes.byref(G), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat), T, _ptr(w),
         _ptr(mu_t), _ptr(cov_t), _stream(stream)))
     return mu_t, cov_t
+
+
+def temporal_weights(ctrl, t0: float, dt: float, times, stream=None):
+    """w [T][R] of the temporal cubic B-spline over control values ctrl [Ct][R]."""
+    Ct, R = ctrl.shape
+    T = times.shape[0]
+    w = torch.empty((T, R), device=ctrl.device, dtype=torch.float32)
+    _check("digs_temporal_weights", load().digs_temporal_weights(
+        Ct, R, _ptr(ctrl), float(t0), float(dt), T, _ptr(times), _ptr(w), _stream(stream)))
+    return w
+
+
+def temporal_weights_bwd(Ct: int, t0: float, dt: float, times, g_w, stream=None):
+    """dL/dctrl [Ct][R] given dL/dw [T][R]."""
+    T, R = g_w.shape
+    g = torch.empty((Ct, R), device=g_w.device, dtype=torch.float32)
+    _check("digs_temporal_weights_bwd", load().digs_temporal_weights_bwd(
+        Ct, R, float(t0), float(dt), T, _ptr(times), _ptr(g_w), _ptr(g), _stream(stream)))
+    return g
 
 
 def workspace_size(geom: dict, grid: dict, n: int, T: int, tuning: dict | None = None) -> int:

@@ -108,7 +108,6 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->cnt = take(sizeof(uint32_t) * cnt_elems);
     L->scratch = take(sizeof(uint32_t) * sc);
     L->list = take(sizeof(uint32_t) * L->cap);
-    L->inv = take(sizeof(uint32_t) * L->cap);
     L->part = take(sizeof(float) * DIGS_PART_FLOATS * L->cap);
     L->gwpart = take(sizeof(float) * (size_t)(T > 0 ? T : 1) * grid->R * nparts);
     L->keys_a = take(sizeof(uint32_t) * N);
@@ -152,6 +151,31 @@ extern "C" int digs_deform_gaussians(const digs_grid *grid, const float *coef, i
     if (!coef || !mu || !scale || !quat || !w || !mu_t || !cov_t) return DIGS_EINVAL;
     return check(launch_deform(make_dev_grid(grid), coef, n, mu, scale, quat, T, w, mu_t, cov_t,
                                (hipStream_t)stream));
+}
+
+static bool temporal_ok(int Ct, int R, float t0, float dt, int T)
+{
+    return Ct >= 1 && R >= 1 && R <= DIGS_MAX_RANK && T >= 0 && isfinite(t0) && dt > 0.0f &&
+           isfinite(dt) && (int64_t)Ct * R < (1ll << 30) && (int64_t)T * R < (1ll << 30);
+}
+
+extern "C" int digs_temporal_weights(int Ct, int R, const float *ctrl, float t0, float dt, int T,
+                                     const float *times, float *w, void *stream)
+{
+    if (!temporal_ok(Ct, R, t0, dt, T)) return DIGS_EINVAL;
+    if (T == 0) return DIGS_OK;
+    if (!ctrl || !times || !w) return DIGS_EINVAL;
+    return check(launch_temporal_fwd(Ct, R, ctrl, t0, dt, T, times, w, (hipStream_t)stream));
+}
+
+extern "C" int digs_temporal_weights_bwd(int Ct, int R, float t0, float dt, int T,
+                                         const float *times, const float *g_w, float *g_ctrl,
+                                         void *stream)
+{
+    if (!temporal_ok(Ct, R, t0, dt, T)) return DIGS_EINVAL;
+    if (!g_ctrl || (T > 0 && (!times || !g_w))) return DIGS_EINVAL;
+    if (T == 0) return check(render_zero(g_ctrl, (size_t)Ct * R, (hipStream_t)stream));
+    return check(launch_temporal_bwd(Ct, R, t0, dt, T, times, g_w, g_ctrl, (hipStream_t)stream));
 }
 
 static int prepare(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,

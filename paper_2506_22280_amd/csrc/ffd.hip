@@ -105,3 +105,68 @@ hipError_t launch_deform(const DevGrid &g, const float *coef, int n, const float
                        quat, T, w, mu_t, cov_t);
     return hipGetLastError();
 }
+
+// ------------------------------------------------------------------------------------------
+// Temporal weights of the low-rank motion model: a 1-D cubic B-spline in time over control
+// values placed every dt from t0 (Sec. 3.3 after Eq. 11; Sec. 4.2 puts one every 4 time points),
+// with the lattice's 0-based knot and clamping convention. One thread per (t, r).
+__global__ __launch_bounds__(256) void k_temporal_fwd(int Ct, int R, const float *__restrict__ ctrl,
+                                                      float t0, float idt, int T,
+                                                      const float *__restrict__ times,
+                                                      float *__restrict__ w)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= T * R) return;
+    const int t = idx / R, r = idx % R;
+    const float p = (times[t] - t0) * idt, f = floorf(p);
+    float B[4];
+    bspline4(p - f, B);
+    const int fi = (int)fminf(fmaxf(f, -4.0f), (float)Ct + 4.0f);
+    float acc = 0.0f;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) acc = fmaf(B[l], ctrl[(size_t)clampi(fi - 1 + l, Ct) * R + r], acc);
+    w[idx] = acc;
+}
+
+// Adjoint: each control value gathers, in time order, the pieces of the time points whose
+// stencil (after clamping) lands on it. One thread per (control point, r); no atomics.
+__global__ __launch_bounds__(256) void k_temporal_bwd(int Ct, int R, float t0, float idt, int T,
+                                                      const float *__restrict__ times,
+                                                      const float *__restrict__ g_w,
+                                                      float *__restrict__ g_ctrl)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ct * R) return;
+    const int j = idx / R, r = idx % R;
+    float acc = 0.0f;
+    for (int t = 0; t < T; ++t) {
+        const float p = (times[t] - t0) * idt, f = floorf(p);
+        const int fi = (int)fminf(fmaxf(f, -4.0f), (float)Ct + 4.0f);
+        if (clampi(fi - 1, Ct) > j || clampi(fi + 2, Ct) < j) continue;
+        float B[4];
+        bspline4(p - f, B);
+        float s = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) s += (clampi(fi - 1 + l, Ct) == j) ? B[l] : 0.0f;
+        acc = fmaf(s, g_w[(size_t)t * R + r], acc);
+    }
+    g_ctrl[idx] = acc;
+}
+
+hipError_t launch_temporal_fwd(int Ct, int R, const float *ctrl, float t0, float dt, int T,
+                               const float *times, float *w, hipStream_t s)
+{
+    const int m = T * R;
+    hipLaunchKernelGGL(k_temporal_fwd, dim3((m + 255) / 256), dim3(256), 0, s, Ct, R, ctrl, t0,
+                       1.0f / dt, T, times, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_temporal_bwd(int Ct, int R, float t0, float dt, int T, const float *times,
+                               const float *g_w, float *g_ctrl, hipStream_t s)
+{
+    const int m = Ct * R;
+    hipLaunchKernelGGL(k_temporal_bwd, dim3((m + 255) / 256), dim3(256), 0, s, Ct, R, t0,
+                       1.0f / dt, T, times, g_w, g_ctrl);
+    return hipGetLastError();
+}

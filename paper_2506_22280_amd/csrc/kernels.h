@@ -14,8 +14,7 @@ struct WsLayout {
     size_t cnt;        // [T][ntiles][nblk] u32 per-block tile counts, scanned in place
     size_t scratch;    // scan block sums
     size_t list;       // [cap] u32 Gaussian index of each instance, grouped by (t, tile)
-    size_t inv;        // [cap] u32 list position of instance (t, n, k) at gcount[t][n] + k
-    size_t part;       // [cap][12] f32 backward partial sums per instance
+    size_t part;       // [cap][12] f32 backward partial sums, instance (t,n,k) at gcount[t][n]+k
     size_t gwpart;     // [T][R][4*ceil(N/256)] f32 per-wave partial sums of dL/dw
     size_t keys_a, vals_a, keys_b, vals_b;  // [N] u32 cell sort ping-pong
     size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
@@ -46,6 +45,10 @@ hipError_t launch_ffd_eval(const DevGrid &g, const float *coef, int n, const flo
 hipError_t launch_deform(const DevGrid &g, const float *coef, int n, const float *mu,
                          const float *scale, const float *quat, int T, const float *w,
                          float *mu_t, float *cov_t, hipStream_t s);
+hipError_t launch_temporal_fwd(int Ct, int R, const float *ctrl, float t0, float dt, int T,
+                               const float *times, float *w, hipStream_t s);
+hipError_t launch_temporal_bwd(int Ct, int R, float t0, float dt, int T, const float *times,
+                               const float *g_w, float *g_ctrl, hipStream_t s);
 
 // render.hip
 struct RenderArgs {

@@ -337,8 +337,7 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
 // a4: binning sources
 struct TileSrc {
     const int2 *rect;        // [T][N]
-    const uint32_t *goff;    // [T][N] scanned gcount
-    uint32_t *list, *inv;
+    uint32_t *list;
     size_t cap;
     int items;               // N
     int tiles_x;
@@ -360,11 +359,9 @@ struct TileSrc {
         it.tiles_x = tiles_x;
         return it;
     }
-    __device__ void emit(int t, int item, const Item &, int k, uint32_t pos) const
+    __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
     {
         if (pos < cap) list[pos] = (uint32_t)item;
-        const size_t g = (size_t)goff[(size_t)t * items + item] + k;
-        if (g < cap) inv[g] = pos;
     }
 };
 
@@ -571,7 +568,8 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // a pair list (block-major), and gives each lane one pair: the lane runs over the block's 64
 // pixels with forward differences along each row and accumulates twelve moment sums, which are
 // added into the entry's LDS slot in block order (fixed order, no atomics) and written as the
-// instance's partial:
+// instance's partial, at the instance's slot in Gaussian-major order (so that the per-Gaussian
+// reduction reads each Gaussian's partials contiguously):
 //  0 S_amp = sum g r 2^x      (dL/damp)
 //  1 S_Euu, 2 S_Euv, 3 S_Evv  sum A_E du^2, du dv, dv^2   (A_E = dL/dE, E natural)
 //  4 S_quu, 5 S_quv, 6 S_qvv  sum A_q du^2, du dv, dv^2   (A_q = dL/dq)
@@ -583,6 +581,8 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                                                    const uint32_t *__restrict__ list,
                                                    const uint32_t *__restrict__ cnt, int nblk,
                                                    unsigned cap,
+                                                   const int2 *__restrict__ rect,
+                                                   const uint32_t *__restrict__ goff,
                                                    const float *__restrict__ grad_proj,
                                                    float4 *__restrict__ part)
 {
@@ -725,10 +725,19 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        if (k < end) {
-            part[(size_t)k * 3 + 0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-            part[(size_t)k * 3 + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-            part[(size_t)k * 3 + 2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
+        if (valid) {
+            // instance slot of (t, g, this tile): the Gaussian's instances are contiguous, in
+            // row-major order over its tile rectangle
+            const size_t o = (size_t)t * n + g;
+            const int2 rr = rect[o];
+            const int rtx0 = rr.x & 0xffff, rtx1 = rr.x >> 16, rty0 = rr.y & 0xffff;
+            const size_t slot =
+                (size_t)goff[o] + (size_t)((ty - rty0) * (rtx1 - rtx0 + 1) + (tx - rtx0));
+            if (slot < cap) {
+                part[slot * 3 + 0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                part[slot * 3 + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+                part[slot * 3 + 2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -750,7 +759,7 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
     const float *__restrict__ quat, const float *__restrict__ rho,
     const float *__restrict__ angles, const float *__restrict__ w, const float *__restrict__ uv,
     const int2 *__restrict__ rect, const uint32_t *__restrict__ goff,
-    const uint32_t *__restrict__ inv, const float4 *__restrict__ part, unsigned cap,
+    const float4 *__restrict__ part, unsigned cap,
     float *__restrict__ tnout, float *__restrict__ gwpart, int nparts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -774,11 +783,9 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
         for (int c = 0; c < 12; ++c) S[c] = 0.0f;
         const uint32_t base = goff[o];
         for (int k = 0; k < cntk; ++k) {
-            if ((size_t)base + k >= cap) break;
-            const uint32_t p = inv[base + k];
-            if (p >= cap) continue;
-            const float4 a = part[(size_t)p * 3 + 0], b = part[(size_t)p * 3 + 1],
-                         c = part[(size_t)p * 3 + 2];
+            const size_t p = (size_t)base + k;
+            if (p >= cap) break;
+            const float4 a = part[p * 3 + 0], b = part[p * 3 + 1], c = part[p * 3 + 2];
             S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
             S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
             S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
@@ -1232,9 +1239,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     if (e != hipSuccess) return e;
     TileSrc src;
     src.rect = WS(a, rect, const int2 *);
-    src.goff = WS(a, gcount, const uint32_t *);
     src.list = WS(a, list, uint32_t *);
-    src.inv = WS(a, inv, uint32_t *);
     src.cap = a.L.cap;
     src.items = a.n;
     src.tiles_x = a.geom.tiles_x;
@@ -1275,7 +1280,7 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
         hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, T), dim3(256), 0, s, a.geom, n, T, a.mu,
                            a.scale, a.quat, a.rho, a.angles, a.w, WS(a, uv, const float *),
                            WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
-                           WS(a, inv, const uint32_t *), WS(a, part, const float4 *),
+                           WS(a, part, const float4 *),
                            (unsigned)a.L.cap, WS(a, tnout, float *), WS(a, gwpart, float *),
                            nparts);
         e = hipGetLastError();
@@ -1346,7 +1351,8 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
         ProfScope ps(PS_SPLAT_BWD, s);
         hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, a.n,
                            a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
-                           WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap, grad_proj,
+                           WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
+                           WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *), grad_proj,
                            WS(a, part, float4 *));
         e = hipGetLastError();
     }

@@ -212,3 +212,19 @@ def test_project_bwd_identities():
         lhs = float(p.w[1, r]) * float(o1["g_w"][0, r])
         rhs = float((p.coef[r].astype(np.float64) * o1["g_coef"][r].double().cpu().numpy()).sum())
         assert abs(lhs - rhs) <= 2e-4 * max(abs(lhs), 1e-12), (r, lhs, rhs)
+
+
+def test_temporal_weights_matches_oracle():
+    _print("case: temporal weights, 40 control values x rank 3, 1320 time points (some outside)")
+    rng = np.random.default_rng(61)
+    Ct, R, t0, dt = 40, 3, 0.0, 4.0
+    ctrl = rng.normal(0, 5.0, (Ct, R)).astype(np.float32)
+    times = rng.uniform(-8.0, dt * Ct + 8.0, 1320).astype(np.float32)
+    w = _lib.temporal_weights(dev(ctrl), t0, dt, dev(times))
+    ref = oracle.temporal_weights(ctrl, t0, dt, times)
+    gw = rng.normal(0, 1, (1320, R)).astype(np.float32)
+    gc = _lib.temporal_weights_bwd(Ct, t0, dt, dev(times), dev(gw))
+    gref = oracle.temporal_weights_bwd(Ct, t0, dt, times, gw)
+    torch.cuda.synchronize()
+    assert max_rel_to_max(w.cpu().numpy(), ref) < 2e-6
+    assert max_rel_to_max(gc.cpu().numpy(), gref) < 2e-6

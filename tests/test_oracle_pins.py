@@ -470,3 +470,33 @@ def test_dvf_and_phi(oracle_mod):
     np.testing.assert_allclose(oracle_mod.phi(mu_t, cov, np.array([0.8]), pts),
                                [0.8, 0.8 * math.exp(-0.5), 0.8 * math.exp(-0.5),
                                 0.8 * math.exp(-0.125)], rtol=1e-14)
+
+
+# ------------------------------------------------------------------------------------------------
+# Temporal weights: the 1-D cubic B-spline in time (Sec. 3.3 after Eq. 11; Sec. 4.2)
+def test_temporal_weights_pins(oracle_mod):
+    rng = np.random.default_rng(51)
+    Ct, R, t0, dt = 12, 3, -1.5, 4.0
+    times = rng.uniform(t0 - 10.0, t0 + dt * Ct + 10.0, 200)
+    # partition of unity: constant control values give constant weights everywhere
+    const = np.tile(np.array([[0.7, -2.0, 5.0]]), (Ct, 1))
+    np.testing.assert_allclose(oracle_mod.temporal_weights(const, t0, dt, times),
+                               np.tile(const[:1], (200, 1)), rtol=1e-13)
+    # linear precision: control values linear in the knot index reproduce the linear function
+    # of time wherever the stencil is not clamped
+    a, b = np.array([0.3, -1.1, 2.0]), np.array([1.0, 0.5, -3.0])
+    lin = np.arange(Ct)[:, None] * a[None, :] + b[None, :]
+    inner = times[(times >= t0 + dt) & (times < t0 + dt * (Ct - 2))]
+    p = (inner - t0) / dt
+    np.testing.assert_allclose(oracle_mod.temporal_weights(lin, t0, dt, inner),
+                               p[:, None] * a[None, :] + b[None, :], rtol=1e-12, atol=1e-12)
+    # at a knot the weights are (c[j-1] + 4 c[j] + c[j+1]) / 6
+    c = rng.normal(0, 1, (Ct, R))
+    j = 5
+    np.testing.assert_allclose(oracle_mod.temporal_weights(c, t0, dt, np.array([t0 + j * dt])),
+                               ((c[j - 1] + 4 * c[j] + c[j + 1]) / 6.0)[None, :], rtol=1e-13)
+    # the adjoint is the transpose of the (pinned) linear map: <g_w, W c> = <W^T g_w, c>
+    gw = rng.normal(0, 1, (200, R))
+    lhs = (gw * oracle_mod.temporal_weights(c, t0, dt, times)).sum()
+    rhs = (oracle_mod.temporal_weights_bwd(Ct, t0, dt, times, gw) * c).sum()
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
