@@ -72,7 +72,7 @@ static int64_t default_capacity(int n, int T) { return (int64_t)16 * n * T + 409
 bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
                const digs_tuning *tuning, WsLayout *L)
 {
-    if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0) return false;
+    if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0 || n > DIGS_MAX_GAUSSIANS) return false;
     memset(L, 0, sizeof(*L));
     const DevGeom G = make_dev_geom(geom);
     L->n = n;
@@ -183,7 +183,8 @@ static int prepare(const digs_geom *geom, const digs_grid *grid, const float *co
                    int T, const float *angles, const float *w, void *ws, size_t ws_bytes,
                    const digs_tuning *tuning, RenderArgs *a)
 {
-    if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0) return DIGS_EINVAL;
+    if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0 || n > DIGS_MAX_GAUSSIANS)
+        return DIGS_EINVAL;
     if (tuning && (tuning->capacity < 0 || !(tuning->cull_radius >= 0.0f) ||
                    (tuning->splat_waves != 0 && tuning->splat_waves != 1 &&
                     tuning->splat_waves != 4) ||

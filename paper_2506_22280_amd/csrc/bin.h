@@ -1,7 +1,7 @@
 // bin.h -- deterministic, atomics-free-in-global-memory binning of items into keyed lists.
 //
 // Each item (a Gaussian of one projection, or one key of a radix pass) contributes nkeys()
-// keys. k_bin_count builds per-wave key histograms in LDS (integer LDS atomics: exact counts)
+// keys; before its keys are placed, prepare() may load what emit() needs beyond the keys. k_bin_count builds per-wave key histograms in LDS (integer LDS atomics: exact counts)
 // and writes one count per (slice, key, item block). After an exclusive scan of those counts
 // in (slice, key, block) order, k_bin_fill recomputes the per-wave histograms, turns them into
 // per-wave running offsets, and places every (item, key) pair: the rank among equal keys in
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
         const int item = base + step * DIGS_WAVE + lane;
         const bool valid = item < src.items;
         typename Src::Item it = src.load(slice, valid ? item : 0);
+        if (valid) src.prepare(slice, item, it);
         const int nk = valid ? it.nkeys() : 0;
         for (int k = 0;; ++k) {
             const bool active = k < nk;

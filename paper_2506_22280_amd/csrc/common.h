@@ -13,15 +13,14 @@
 #define DIGS_REC_FLOATS 16           // per-(t,n) projected record, 64 bytes
 #define DIGS_PART_FLOATS 12          // per-instance backward partial sums, 48 bytes
 
-// Record layout (per projection t and Gaussian n), all float32 unless stated:
+// Record layout (per projection t and Gaussian n), all float32:
 //  0 us, 1 vs          footprint centre in pixel-index coordinates (column, row)
 //  2 Huu', 3 Huv', 4 Hvv'   c2*H~uu, 2*c2*H~uv, c2*H~vv with c2 = -log2(e)/2 (exp2 argument)
 //  5 gu2, 6 gv2        2*g~u, 2*g~v
 //  7 Guu, 8 Guv2, 9 Gvv    G~uu, 2*G~uv, G~vv
-//  10 amp              rho*sqrt(2 pi / Q*); 11 unused
-//  12 (int) x0 | x1<<16    inclusive pixel bounding box of the cut-off footprint, columns
-//  13 (int) y0 | y1<<16    rows; an empty box has x0 > x1
-//  14..15 unused
+//  10 amp              rho*sqrt(2 pi / Q*)
+//  11 a00, 12 a01, 13 a11, 14 cx, 15 cy    the cut-off footprint as the ellipse
+//                      (p - c)^T A (p - c) <= 1 in pixel-index coordinates (A = 0: not an ellipse)
 // The per-pixel value is |e_ij| * amp * q^-1/2 * 2^(E' / q) with
 // q = 1 + gu2 du + gv2 dv + Guu du^2 + Guv2 du dv + Gvv dv^2 and E' = Huu' du^2 + Huv' du dv
 // + Hvv' dv^2, du = i - us, dv = j - vs.

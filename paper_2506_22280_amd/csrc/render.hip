@@ -197,17 +197,23 @@ __device__ __forceinline__ void setup_forward(const DevGeom &G, const float *mu0
            isfinite(f.amp) && isfinite(f.gu) && isfinite(f.gv);
 }
 
-// Bounding box (inclusive pixel ranges, clamped to the detector) of the cut-off footprint
-// {delta : E/q <= r^2} = {delta^T (H - r^2 G) delta - 2 r^2 g.delta - r^2 <= 0}.
-// Returns false when the conic is not an ellipse (then the box is the whole detector).
+// The cut-off footprint {delta : E/q <= r^2} = {delta^T (H - r^2 G) delta - 2 r^2 g.delta - r^2 <= 0}
+// in centred, normalised form (p - c)^T A (p - c) <= 1 (p in pixel-index coordinates), and its
+// bounding box (inclusive pixel ranges, clamped to the detector). Returns false when the conic is
+// not an ellipse: then the box is the whole detector and A = 0 (every block is kept).
+struct Footprint {
+    float cx, cy, a00, a01, a11;
+};
+
 __device__ __forceinline__ bool footprint_box(const DevGeom &G, const SetupFwd &f, float r,
-                                              int &x0, int &x1, int &y0, int &y1)
+                                              int &x0, int &x1, int &y0, int &y1, Footprint &fp)
 {
     const float r2 = r * r;
     const float b00 = f.Huu - r2 * f.Guu, b01 = f.Huv - r2 * f.Guv, b11 = f.Hvv - r2 * f.Gvv;
     const float det = b00 * b11 - b01 * b01;
     if (!(b00 > 0.0f && det > 0.0f)) {
         x0 = 0; x1 = G.nu - 1; y0 = 0; y1 = G.nv - 1;
+        fp.cx = f.us; fp.cy = f.vs; fp.a00 = fp.a01 = fp.a11 = 0.0f;
         return false;
     }
     const float id = 1.0f / det;
@@ -215,8 +221,15 @@ __device__ __forceinline__ bool footprint_box(const DevGeom &G, const SetupFwd &
     const float cu = r2 * (i00 * f.gu + i01 * f.gv), cv = r2 * (i01 * f.gu + i11 * f.gv);
     const float k2 = r2 + (f.gu * cu + f.gv * cv) * r2;
     const float hu = sqrtf(fmaxf(k2 * i00, 0.0f)), hv = sqrtf(fmaxf(k2 * i11, 0.0f));
-    const float lo_u = f.us + cu - hu - 1e-3f, hi_u = f.us + cu + hu + 1e-3f;
-    const float lo_v = f.vs + cv - hv - 1e-3f, hi_v = f.vs + cv + hv + 1e-3f;
+    const float ik = 1.0f / k2;
+    fp.cx = f.us + cu;
+    fp.cy = f.vs + cv;
+    fp.a00 = b00 * ik;
+    fp.a01 = b01 * ik;
+    fp.a11 = b11 * ik;
+    if (!(k2 > 0.0f) || !isfinite(ik)) fp.a00 = fp.a01 = fp.a11 = 0.0f;
+    const float lo_u = fp.cx - hu - 1e-3f, hi_u = fp.cx + hu + 1e-3f;
+    const float lo_v = fp.cy - hv - 1e-3f, hi_v = fp.cy + hv + 1e-3f;
     // clamp in float before converting (boxes far off the detector stay empty)
     x0 = (int)ceilf(fminf(fmaxf(lo_u, -1.0f), (float)G.nu));
     x1 = (int)floorf(fminf(fmaxf(hi_u, -1.0f), (float)G.nu));
@@ -225,6 +238,41 @@ __device__ __forceinline__ bool footprint_box(const DevGeom &G, const SetupFwd &
     x0 = max(x0, 0); y0 = max(y0, 0);
     x1 = min(x1, G.nu - 1); y1 = min(y1, G.nv - 1);
     return true;
+}
+
+// Does the ellipse (p - c)^T A (p - c) <= 1 meet the rectangle [x0, x1] x [y0, y1]? Exact for
+// the continuous rectangle (so never false for a rectangle holding a pixel centre inside the
+// ellipse): the quadratic is convex, so if its centre lies outside the rectangle its minimum over
+// the rectangle lies on an edge, where it is a 1-D quadratic minimised at a clamped vertex.
+// A = 0 (a footprint that is not an ellipse) meets everything.
+__device__ __forceinline__ bool ellipse_meets_rect(float cx, float cy, float a00, float a01,
+                                                   float a11, float x0, float x1, float y0,
+                                                   float y1)
+{
+    if (!(a00 > 0.0f) || (cx >= x0 && cx <= x1 && cy >= y0 && cy <= y1)) return true;
+    const float ia00 = 1.0f / a00, ia11 = 1.0f / a11;
+    float best;
+    {
+        const float dy = y0 - cy;
+        const float dx = fminf(fmaxf(cx - a01 * dy * ia00, x0), x1) - cx;
+        best = fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy));
+    }
+    {
+        const float dy = y1 - cy;
+        const float dx = fminf(fmaxf(cx - a01 * dy * ia00, x0), x1) - cx;
+        best = fminf(best, fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy)));
+    }
+    {
+        const float dx = x0 - cx;
+        const float dy = fminf(fmaxf(cy - a01 * dx * ia11, y0), y1) - cy;
+        best = fminf(best, fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy)));
+    }
+    {
+        const float dx = x1 - cx;
+        const float dy = fminf(fmaxf(cy - a01 * dx * ia11, y0), y1) - cy;
+        best = fminf(best, fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy)));
+    }
+    return best <= 1.0f + 1e-5f;
 }
 
 template <int NR>
@@ -279,6 +327,7 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
         SetupFwd f;
         setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
         int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+        Footprint fp = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         bool ok = inputs_ok && f.ok;
         if (valid) {
             if (!inputs_ok || !(isfinite(f.detK) && f.detK != 0.0f))
@@ -290,7 +339,7 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
             if (ok && f.detK <= 0.0f) atomicAdd(&diag->folded, 1u);
         }
         if (ok) {
-            if (!footprint_box(G, f, cull, x0, x1, y0, y1) && valid)
+            if (!footprint_box(G, f, cull, x0, x1, y0, y1, fp) && valid)
                 atomicAdd(&diag->wide, 1u);
         }
         uint32_t count = 0;
@@ -309,14 +358,15 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
             if (ok) {
                 rec[o * 4 + 0] = make_float4(f.us, f.vs, C2_EXP2 * f.Huu, 2.0f * C2_EXP2 * f.Huv);
                 rec[o * 4 + 1] = make_float4(C2_EXP2 * f.Hvv, 2.0f * f.gu, 2.0f * f.gv, f.Guu);
-                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, f.Gvv, f.amp, 0.0f);
+                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, f.Gvv, f.amp, fp.a00);
+                rec[o * 4 + 3] = make_float4(fp.a01, fp.a11, fp.cx, fp.cy);
             } else {   // keep the record finite
-                rec[o * 4 + 0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                rec[o * 4 + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                rec[o * 4 + 2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                rec[o * 4 + 0] = z;
+                rec[o * 4 + 1] = z;
+                rec[o * 4 + 2] = z;
+                rec[o * 4 + 3] = z;
             }
-            rec[o * 4 + 3] = make_float4(__int_as_float(x0 | (x1 << 16)),
-                                         __int_as_float(y0 | (y1 << 16)), 0.0f, 0.0f);
             rect[o] = rr;
             gcount[o] = count;
         }
@@ -334,15 +384,22 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
 }
 
 // ------------------------------------------------------------------------------------------
-// a4: binning sources
+// a4: binning sources. A tile list entry is the Gaussian's index in the low 28 bits and, in the
+// top 4 bits, which of the tile's four 8x8 pixel blocks the cut-off footprint ellipse meets
+// (bit b: block column b & 1, block row b >> 1); the splats evaluate only those blocks.
+#define LIST_INDEX_MASK 0x0FFFFFFFu
+#define LIST_BLOCK_SHIFT 28
+
 struct TileSrc {
     const int2 *rect;        // [T][N]
+    const float4 *rec;       // [T][N][4] projected records (footprint conic in rec[2].w, rec[3])
     uint32_t *list;
     size_t cap;
     int items;               // N
     int tiles_x;
     struct Item {
         int tx0, ty0, w, cnt, tiles_x;
+        float cx, cy, a00, a01, a11;
         __device__ int nkeys() const { return cnt; }
         __device__ int key(int k) const { return (ty0 + k / w) * tiles_x + tx0 + k % w; }
     };
@@ -357,11 +414,33 @@ struct TileSrc {
         it.w = tx1 - it.tx0 + 1;
         it.cnt = (tx1 >= it.tx0 && ty1 >= it.ty0) ? it.w * (ty1 - it.ty0 + 1) : 0;
         it.tiles_x = tiles_x;
+        it.cx = it.cy = it.a00 = it.a01 = it.a11 = 0.0f;
         return it;
     }
-    __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
+    __device__ void prepare(int t, int item, Item &it) const
     {
-        if (pos < cap) list[pos] = (uint32_t)item;
+        const float4 *r = rec + ((size_t)t * items + item) * 4;
+        const float4 c = r[2], d = r[3];
+        it.a00 = c.w;
+        it.a01 = d.x;
+        it.a11 = d.y;
+        it.cx = d.z;
+        it.cy = d.w;
+    }
+    __device__ void emit(int, int item, const Item &it, int k, uint32_t pos) const
+    {
+        if (pos >= cap) return;
+        const int key = it.key(k);
+        const float x0 = (float)((key % tiles_x) * DIGS_TILE), y0 = (float)((key / tiles_x) * DIGS_TILE);
+        uint32_t m = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float bx = x0 + (float)((b & 1) * 8), by = y0 + (float)((b >> 1) * 8);
+            if (ellipse_meets_rect(it.cx, it.cy, it.a00, it.a01, it.a11, bx, bx + 7.0f, by,
+                                   by + 7.0f))
+                m |= 1u << b;
+        }
+        list[pos] = (uint32_t)item | (m << LIST_BLOCK_SHIFT);
     }
 };
 
@@ -381,6 +460,7 @@ struct RadixSrc {
         it.k = (keys_in[item] >> shift) & 255u;
         return it;
     }
+    __device__ void prepare(int, int, Item &) const {}
     __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
     {
         if (pos < (uint32_t)items) {
@@ -391,13 +471,31 @@ struct RadixSrc {
 };
 
 // ------------------------------------------------------------------------------------------
-// a5: forward splat. One workgroup per (projection, tile), one wave per 8x8 pixel block (with
+// Workgroup -> (view, tile). The hardware hands consecutive workgroups of a launch to the 8 XCDs
+// in turn (b mod 8). When T is a multiple of 8, XCD x is given the views t = x (mod 8) one after
+// another, tile by tile in row-major order, so the records and lists one XCD reads at a time
+// belong to a band of tile rows of one view and stay in that XCD's L2.
+__device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int &tile)
+{
+    if ((T & 7) == 0) {
+        const int x = b & 7, k = b >> 3, q = k / ntiles;
+        t = x + 8 * q;
+        tile = k - q * ntiles;
+    } else {
+        t = b / ntiles;
+        tile = b - t * ntiles;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a5: forward splat. One workgroup per (view, tile), one wave per 8x8 pixel block (with
 // WAVES == 1 a single wave takes the tile's four blocks in turn). The wave walks the tile's list
-// in chunks of 64 entries, keeps the Gaussians whose footprint box meets its block (ballot and
-// compaction in LDS) and evaluates them 8 at a time: lane = (Gaussian slot, column), each lane
-// running down the 8 rows of its column with forward differences of the two quadratic forms
-// (two adds each per row). The per-lane row sums are reduced over the 8 slots at the end in a
-// fixed order, and every pixel is written once.
+// in chunks of 64 entries, keeps the Gaussians whose footprint meets its block (bit of the list
+// entry; compaction in LDS) and evaluates them 8 at a time: lane = (Gaussian slot, column), each
+// lane running down the 8 rows of its column with forward differences of the two quadratic forms
+// (two adds each per row). The records of the next 8 Gaussians are loaded while the current 8
+// are evaluated. The per-lane row sums are reduced over the 8 slots at the end in a fixed order,
+// and every pixel is written once.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
                                                           const float4 *__restrict__ rec,
@@ -407,7 +505,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
                                                           float *__restrict__ proj)
 {
     __shared__ uint32_t ids[WAVES][DIGS_WAVE];
-    const int t = blockIdx.y, tile = blockIdx.x;
+    int t, tile;
+    map_block(blockIdx.x, G.ntiles, T, t, tile);
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
     const int gslot = lane >> 3, col = lane & 7;
@@ -429,13 +528,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
             uint32_t g = 0;
             bool hit = false;
             if (k < end) {
-                g = list[k];
-                if (g < (uint32_t)n) {
-                    const float4 b = rt[(size_t)g * 4 + 3];
-                    const int bxr = __float_as_int(b.x), byr = __float_as_int(b.y);
-                    hit = !((bxr >> 16) < bx || (bxr & 0xffff) > bx + 7 || (byr >> 16) < by ||
-                            (byr & 0xffff) > by + 7);
-                }
+                const uint32_t e = list[k];
+                g = e & LIST_INDEX_MASK;
+                hit = g < (uint32_t)n && ((e >> (LIST_BLOCK_SHIFT + blkid)) & 1u);
             }
             const unsigned long long m = __ballot(hit);
             const int ns = __popcll(m);
@@ -443,14 +538,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float4 n0 = zero4, n1 = zero4, n2 = zero4;
+            if (gslot < ns) {
+                const size_t gg = ids[wave][gslot];
+                n0 = rt[gg * 4 + 0];
+                n1 = rt[gg * 4 + 1];
+                n2 = rt[gg * 4 + 2];
+            }
             for (int j = 0; j < ns; j += 8) {
-                const int s = j + gslot;
-                float4 r0 = zero4, r1 = zero4, r2 = zero4;
-                if (s < ns) {
-                    const size_t gg = ids[wave][s];
-                    r0 = rt[gg * 4 + 0];
-                    r1 = rt[gg * 4 + 1];
-                    r2 = rt[gg * 4 + 2];
+                const float4 r0 = n0, r1 = n1, r2 = n2;
+                const int sn = j + 8 + gslot;
+                n0 = zero4; n1 = zero4; n2 = zero4;
+                if (sn < ns) {
+                    const size_t gg = ids[wave][sn];
+                    n0 = rt[gg * 4 + 0];
+                    n1 = rt[gg * 4 + 1];
+                    n2 = rt[gg * 4 + 2];
                 }
                 // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu), r2 = (Guv2, Gvv, amp, -)
                 const float du = fi - r0.x, dv0 = fby - r0.y;
@@ -500,7 +603,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
 }
 
 // Measurement only: the pairs inside each footprint and on the detector, and the pairs the forward
-// and backward splats evaluate (64 per 8x8 block that a footprint box touches, in both).
+// and backward splats evaluate (64 per 8x8 block that a footprint ellipse meets, in both).
 __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, float cull,
                                                      const float *__restrict__ rec,
                                                      const uint32_t *__restrict__ list,
@@ -510,7 +613,8 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
     __shared__ unsigned long long tot[3];
     if (threadIdx.x < 3) tot[threadIdx.x] = 0;
     __syncthreads();
-    const int t = blockIdx.y, tile = blockIdx.x;
+    int t, tile;
+    map_block(blockIdx.x, G.ntiles, T, t, tile);
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
     const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
@@ -523,12 +627,10 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
     const float c2r2 = (-0.72134752044448170f) * cull * cull;   // exp2 argument at the cut-off
     unsigned long long in_fp = 0, eval_f = 0;
     for (uint32_t k = begin; k < end; ++k) {
-        const uint32_t g = uniform(list[k]);
-        if (g >= (uint32_t)n) continue;
+        const uint32_t ent = uniform(list[k]);
+        const uint32_t g = ent & LIST_INDEX_MASK;
+        if (g >= (uint32_t)n || !((ent >> (LIST_BLOCK_SHIFT + wave)) & 1u)) continue;
         const float *r = rec + ((size_t)t * n + g) * DIGS_REC_FLOATS;
-        const int bxr = __float_as_int(r[12]), byr = __float_as_int(r[13]);
-        const int x0 = bxr & 0xffff, x1 = bxr >> 16, y0 = byr & 0xffff, y1 = byr >> 16;
-        if (x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7) continue;
         eval_f += 64;
         const float du = (float)px - r[0], dv = (float)py - r[1];
         const float q = fmaf(du, fmaf(r[7], du, fmaf(r[8], dv, r[5])),
@@ -554,7 +656,7 @@ __global__ void k_stat_reset(DiagBlock *d) { d->stat[0] = d->stat[1] = d->stat[2
 hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stat_reset, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *));
-    hipLaunchKernelGGL(k_count_pairs, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, a.n,
+    hipLaunchKernelGGL(k_count_pairs, dim3(a.geom.ntiles * a.T), dim3(256), 0, s, a.geom, a.n,
                        a.T, a.cull, WS(a, rec, const float *), WS(a, list, const uint32_t *),
                        WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
                        WS(a, diag, DiagBlock *));
@@ -564,7 +666,7 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // ------------------------------------------------------------------------------------------
 // a6: backward splat. One workgroup per (projection, tile); the tile's dL/dI (times |e|) is staged
 // in LDS (row stride 18 keeps the four 8x8 blocks in distinct banks). Each wave takes chunks of
-// 64 list entries, compacts the (entry, 8x8 block) pairs whose footprint box meets the block into
+// 64 list entries, compacts the (entry, 8x8 block) pairs whose footprint ellipse meets the block into
 // a pair list (block-major), and gives each lane one pair: the lane runs over the block's 64
 // pixels with forward differences along each row and accumulates twelve moment sums, which are
 // added into the entry's LDS slot in block order (fixed order, no atomics) and written as the
@@ -589,7 +691,8 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
     __shared__ float gpx[DIGS_TILE * GPX_STRIDE];
     __shared__ uint32_t pairs[4][4 * DIGS_WAVE];
     __shared__ float accS[4][DIGS_WAVE][13];
-    const int t = blockIdx.y, tile = blockIdx.x;
+    int t, tile;
+    map_block(blockIdx.x, G.ntiles, T, t, tile);
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
     {
@@ -616,21 +719,15 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
     for (uint32_t c0 = begin + wave * DIGS_WAVE; c0 < end; c0 += 4 * DIGS_WAVE) {
         const uint32_t k = c0 + lane;
         bool valid = k < end;
-        uint32_t g = valid ? list[k] : 0u;
+        const uint32_t ent = valid ? list[k] : 0u;
+        const uint32_t g = ent & LIST_INDEX_MASK;
         valid = valid && g < (uint32_t)n;
-        int bx0 = 1, bx1 = 0, by0 = 1, by1 = 0;
-        if (valid) {
-            const float4 b = rt[(size_t)g * 4 + 3];
-            const int bxr = __float_as_int(b.x), byr = __float_as_int(b.y);
-            bx0 = bxr & 0xffff; bx1 = bxr >> 16; by0 = byr & 0xffff; by1 = byr >> 16;
-        }
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = 0.0f;
         int np = 0;
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
-            const int bx = tx0 + (blk & 1) * 8, by = ty0 + (blk >> 1) * 8;
-            const bool hit = valid && !(bx1 < bx || bx0 > bx + 7 || by1 < by || by0 > by + 7);
+            const bool hit = valid && ((ent >> (LIST_BLOCK_SHIFT + blk)) & 1u);
             const unsigned long long m = __ballot(hit);
             if (hit) pairs[wave][np + __popcll(m & lanemask_lt())] = ((uint32_t)lane << 2) | blk;
             np += __popcll(m);
@@ -1239,6 +1336,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     if (e != hipSuccess) return e;
     TileSrc src;
     src.rect = WS(a, rect, const int2 *);
+    src.rec = WS(a, rec, const float4 *);
     src.list = WS(a, list, uint32_t *);
     src.cap = a.L.cap;
     src.items = a.n;
@@ -1252,7 +1350,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
 
 hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
 {
-    dim3 grid(a.geom.ntiles, a.T);
+    dim3 grid(a.geom.ntiles * a.T);
     const unsigned cap = (unsigned)a.L.cap;
     ProfScope ps(PS_SPLAT_FWD, s);
     if (a.splat_waves == 1)
@@ -1349,7 +1447,7 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
     // a6: per-instance moment sums
     {
         ProfScope ps(PS_SPLAT_BWD, s);
-        hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles, a.T), dim3(256), 0, s, a.geom, a.n,
+        hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles * a.T), dim3(256), 0, s, a.geom, a.n,
                            a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
                            WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *), grad_proj,
