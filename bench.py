@@ -9,6 +9,11 @@ view (FFD at the canonical means, the warp, the projected records, tile binning,
 gradient of the L2 projection loss against synthetic measured projections, and the hand-written
 backward to mu, scale, quaternion, density, FFD coefficients and the temporal weights.
 
+The timed steps run the batched path: a plan (digs_plan_*) over fixed device buffers, its launch
+shape and instance capacity chosen by the library's autotuner on the first batch, replayed as HIP
+graphs. Per-kernel durations come from a second pass over the same steps launched eagerly with the
+same tuning, each kernel stage bracketed by HIP events on its launch stream.
+
 Inputs (Gaussians, lattice, per-batch angles and weights, measured projections) are resident in
 HBM before the timed region. Prints one JSON line.
 """
@@ -127,18 +132,11 @@ def main():
         raise SystemExit("instance capacity exceeded while rendering the measured projections")
     n, G, Gd = p.n, p.geom, p.grid
     proj = torch.empty((B, G["nv"], G["nu"]), device=dev)
+    gradp = torch.empty_like(proj)
+    ang_buf, w_buf = ang[0].clone(), wts[0].clone()
     grads = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
                  g_quat=torch.empty((4, n), device=dev), g_rho=torch.empty((n,), device=dev),
                  g_coef=torch.empty_like(est["coef"]), g_w=torch.empty((B, Gd["R"]), device=dev))
-
-    def step(k):
-        kb = k % len(batches)
-        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
-                         ang[kb], wts[kb], ws, proj=proj)
-        proj.sub_(meas[kb])                       # dL/dI of L = 1/2 ||I - P||^2
-        _lib.project_bwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
-                         ang[kb], wts[kb], proj, ws, reuse_fwd=True, out=grads)
-
     if args.calib_copy_mb > 0:
         src = torch.ones(args.calib_copy_mb << 18, device=dev)
         dst = torch.empty_like(src)
@@ -146,32 +144,76 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ws.reset()
+
+    # the batched path: a plan over fixed buffers, autotuned on the first batch, replayed as HIP
+    # graphs; a step writes the batch's angles and weights into the plan's buffers, replays the
+    # forward, forms dL/dI = I - P of the L2 loss, and replays the backward
+    torch.sub(meas[0], meas[0], out=gradp)
+    plan = _lib.Plan(G, Gd, n, B, dict(est, angles=ang_buf, w=w_buf, proj=proj, grad_proj=gradp,
+                                       **grads))
+    tuning, tune_ms = plan.tuning()
+
+    def step(k):
+        kb = k % len(batches)
+        ang_buf.copy_(ang[kb])
+        w_buf.copy_(wts[kb])
+        plan.fwd()
+        torch.sub(proj, meas[kb], out=gradp)
+        plan.bwd()
+
     for k in range(args.warmup):
         step(k)
-    torch.cuda.synchronize()
-    # algorithmic pair counts of the batches the timed steps use
-    pairs = []
-    for k in range(args.steps):
-        kb = (args.warmup + k) % len(batches)
-        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
-                         ang[kb], wts[kb], ws, proj=proj)
-        pairs.append(_lib.count_pairs(G, Gd, n, B, ws))
-    torch.cuda.synchronize()
-
-    if not args.no_profile:
-        _lib.profile_enable(True)
-        _lib.profile_read(reset=True)
+    diag, resized = plan.check()
+    if resized:                      # the capacity grew: warm the re-captured graphs up again
+        for k in range(args.warmup):
+            step(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(args.warmup + k)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    diag, resized = plan.check()
+    if resized or diag["overflow"] or diag["nonfinite"]:
+        raise SystemExit("diagnostics report a problem in the timed steps: %s" % diag)
+    plan.close()
+
+    # per-kernel timing: the same steps, launched eagerly with the plan's tuning, every kernel
+    # stage bracketed by HIP events on its launch stream
+    eager_tuning = dict(splat_waves=tuning["splat_waves"], persistent=tuning["persistent"],
+                        capacity=tuning["capacity"])
+
+    def eager_step(k):
+        kb = k % len(batches)
+        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], ws, tuning=eager_tuning, proj=proj)
+        torch.sub(proj, meas[kb], out=gradp)
+        _lib.project_bwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], gradp, ws, tuning=eager_tuning, reuse_fwd=True,
+                         out=grads)
+
+    ws.reset()
+    eager_step(0)
+    torch.cuda.synchronize()
     prof = {}
     if not args.no_profile:
+        _lib.profile_enable(True)
+        _lib.profile_read(reset=True)
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            eager_step(args.warmup + k)
+        torch.cuda.synchronize()
+        dt_eager = time.perf_counter() - t1
         prof = _lib.profile_read(reset=True)
         _lib.profile_enable(False)
+    # algorithmic pair counts of the batches the timed steps use
+    pairs = []
+    for k in range(args.steps):
+        kb = (args.warmup + k) % len(batches)
+        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], ws, tuning=eager_tuning, proj=proj)
+        pairs.append(_lib.count_pairs(G, Gd, n, B, ws, tuning=eager_tuning))
+    torch.cuda.synchronize()
     diag = ws.diagnostics()
     if diag["overflow"] or diag["nonfinite"]:
         raise SystemExit("diagnostics report a problem: %s" % diag)
@@ -187,11 +229,16 @@ def main():
                                   "views, rank-3 FFD on 29^3 (10 mm)",
                       "global_batch": B, "gaussians": n, "detector": [G["nu"], G["nv"]],
                       "parallelism": "single GPU"}}
+    out["tuning"] = {"chosen": {k: tuning[k] for k in ("splat_waves", "persistent", "capacity")},
+                     "candidates_fwd_bwd_ms": {"w%d_p%d" % (w_, p_): [round(x, 3) for x in ms]
+                                               for (w_, p_), ms in zip(((4, 0), (4, 1), (1, 0),
+                                                                        (1, 1)), tune_ms)}}
     out["hbm_roofline_end_to_end"] = {
         "algorithmic_bytes_per_projection": int(ALGO_BYTES_PER_PROJ),
         "achieved_GBs": round(value * ALGO_BYTES_PER_PROJ / 1e9, 3),
         "frac": round(value * ALGO_BYTES_PER_PROJ / 1e9 / HBM_PEAK_GBS, 6)}
     if prof:
+        out["eager_profiled_ms_per_step"] = round(dt_eager / args.steps * 1e3, 3)
         stages = {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items() if v[0]}
         totals = {k: v[1] for k, v in prof.items() if v[0]}
         out["stage_avg_ms_per_launch"] = stages

@@ -76,7 +76,9 @@ typedef struct digs_tuning {
     float cull_radius;       /* Mahalanobis cut-off of each Gaussian's footprint (default 5)   */
     int64_t capacity;        /* (Gaussian, tile) instances per call (default 16*N*T)           */
     int splat_waves;         /* forward splat: waves per 16x16 tile, 4 (8x8 each) or 1 (default 4) */
-    int bwd_waves;           /* backward splat: waves per workgroup, 1..4 (default 4)          */
+    int bwd_waves;           /* reserved (0 or 4)                                              */
+    int persistent;          /* 1: splats run as persistent kernels over per-XCD work queues of
+                                (view, tile) items; 0: one workgroup per item (default 0)      */
 } digs_tuning;
 
 /* Diagnostics counted by the kernels (read after the work has run). */
@@ -161,6 +163,44 @@ int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, const float *
                      float *g_w, void *ws, size_t ws_bytes, const digs_tuning *tuning, int flags,
                      void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Plans: the batched path. A plan fixes the shapes (geometry, lattice, N, T) and the device
+ * buffers below; it owns its workspace and replays the forward and the backward as HIP graphs
+ * (captured on first use). Inputs are read at replay time, so the caller updates a batch by
+ * writing new contents (views' angles and weights, parameters) into the same buffers.
+ *
+ * digs_plan_create: tuning != NULL fixes the launch tuning; tuning == NULL runs the autotuner,
+ * which renders the buffers' current contents (they must hold valid inputs, and grad_proj valid
+ * dL/dproj if given) to size the instance capacity (1.25 x the measured need + 4096), then times
+ * each of DIGS_TUNE_CANDIDATES launch shapes (forward splat 4 or 1 waves per tile x persistent or
+ * one-workgroup-per-item splats; all give bitwise-identical results) and keeps the fastest
+ * forward + backward. Synchronises its own stream; allocates the workspace (hipMalloc).
+ * digs_plan_fwd / digs_plan_bwd: replay on `stream` (bwd reuses the last fwd's binning).
+ * digs_plan_check: synchronises `stream`, returns the diagnostics; if an instance overflow
+ * happened it grows the workspace, sets *resized = 1 and the caller must repeat the call.
+ * digs_plan_get_tuning: the tuning in use and, if tune_ms != NULL, the autotuner's timings
+ * tune_ms[c][0] (forward) and tune_ms[c][1] (backward) in ms per candidate c.
+ * Errors: DIGS_EINVAL, DIGS_ENOMEM, DIGS_EHIP. */
+#define DIGS_TUNE_CANDIDATES 4
+
+typedef struct digs_plan digs_plan;
+
+typedef struct digs_plan_buffers {
+    const float *coef, *mu, *scale, *quat, *rho;   /* as digs_project_fwd                    */
+    const float *angles, *w;                       /* [T], [T][R]                             */
+    float *proj;                                   /* [T][nv][nu] forward output              */
+    const float *grad_proj;                        /* [T][nv][nu] dL/dproj (NULL: no backward) */
+    float *g_mu, *g_scale, *g_quat, *g_rho, *g_coef, *g_w;   /* backward outputs            */
+} digs_plan_buffers;
+
+int digs_plan_create(const digs_geom *geom, const digs_grid *grid, int n, int T,
+                     const digs_tuning *tuning, const digs_plan_buffers *bufs, digs_plan **out);
+int digs_plan_fwd(digs_plan *plan, void *stream);
+int digs_plan_bwd(digs_plan *plan, void *stream);
+int digs_plan_check(digs_plan *plan, digs_diag *out, int *resized, void *stream);
+int digs_plan_get_tuning(const digs_plan *plan, digs_tuning *out, float *tune_ms);
+int digs_plan_destroy(digs_plan *plan);
+
 /* Diagnostics of a workspace: digs_read_diagnostics synchronises `stream` and copies the block
  * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). */
 int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);
@@ -174,7 +214,9 @@ int digs_reset_diagnostics(void *ws, void *stream);
  * splat evaluates (8x8 pixel blocks touched by a footprint box), out[2] the pairs the backward
  * splat evaluates (the same blocks). Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP.
  * digs_profile_enable / digs_profile_read: when enabled, every kernel stage launched by the
- * library is bracketed by two HIP events recorded on its launch stream; digs_profile_read
+ * library is bracketed by two HIP events recorded on its launch stream (plans switch this off
+ * while they record their graphs); digs_profile_enable(on) returns the previous state, and
+ * on < 0 only queries it; digs_profile_read
  * waits for the recorded events and returns, per stage, the launches and summed milliseconds
  * (reset != 0 clears the sums). Single-threaded use only. Returns the number of entries. */
 typedef struct digs_profile_entry {

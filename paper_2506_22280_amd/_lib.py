@@ -40,7 +40,8 @@ class Grid(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cull_radius", ctypes.c_float), ("capacity", ctypes.c_int64),
-                ("splat_waves", ctypes.c_int), ("bwd_waves", ctypes.c_int)]
+                ("splat_waves", ctypes.c_int), ("bwd_waves", ctypes.c_int),
+                ("persistent", ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -53,6 +54,13 @@ class Diag(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class PlanBuffers(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in (
+        "coef", "mu", "scale", "quat", "rho", "angles", "w", "proj", "grad_proj", "g_mu",
+        "g_scale", "g_quat", "g_rho", "g_coef", "g_w")]
+
+
+TUNE_CANDIDATES = 4
 _VP = ctypes.c_void_p
 _lib = None
 
@@ -85,6 +93,15 @@ _SIGS = {
     "digs_temporal_weights_bwd": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_float,
                                                  ctypes.c_float, ctypes.c_int, _VP, _VP, _VP,
                                                  _VP]),
+    "digs_plan_create": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(Tuning),
+                                        ctypes.POINTER(PlanBuffers), ctypes.POINTER(_VP)]),
+    "digs_plan_fwd": (ctypes.c_int, [_VP, _VP]),
+    "digs_plan_bwd": (ctypes.c_int, [_VP, _VP]),
+    "digs_plan_check": (ctypes.c_int, [_VP, ctypes.POINTER(Diag), ctypes.POINTER(ctypes.c_int),
+                                       _VP]),
+    "digs_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning), _VP]),
+    "digs_plan_destroy": (ctypes.c_int, [_VP]),
     "digs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "digs_last_hip_error": (ctypes.c_int, []),
 }
@@ -142,6 +159,7 @@ def make_tuning(t: dict | None):
     T.capacity = int(t.get("capacity", 0))
     T.splat_waves = int(t.get("splat_waves", 0))
     T.bwd_waves = int(t.get("bwd_waves", 0))
+    T.persistent = int(t.get("persistent", 0))
     return T
 
 
@@ -326,3 +344,58 @@ def count_pairs(geom: dict, grid: dict, n: int, T: int, ws: Workspace,
         ctypes.byref(G), ctypes.byref(R), n, T, _ptr(ws.buf), ws.buf.numel(), _byref(Tu), out,
         _stream(stream)))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+class Plan:
+    """The batched path (digs_plan_*): fixed shapes and buffers, its own workspace, the forward
+    and backward replayed as HIP graphs. ``buffers`` maps the digs_plan_buffers names to device
+    tensors; the plan keeps references to them, and a new batch is given by writing into them.
+    tuning=None runs the library's autotuner on the buffers' current contents."""
+
+    def __init__(self, geom: dict, grid: dict, n: int, T: int, buffers: dict,
+                 tuning: dict | None = None):
+        self.buffers = dict(buffers)
+        B = PlanBuffers()
+        for k, _ in PlanBuffers._fields_:
+            t = self.buffers.get(k)
+            setattr(B, k, _ptr(t).value if t is not None else None)
+        G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+        h = ctypes.c_void_p()
+        _check("digs_plan_create", load().digs_plan_create(
+            ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu), ctypes.byref(B), ctypes.byref(h)))
+        self._h = h
+
+    def fwd(self, stream=None):
+        _check("digs_plan_fwd", load().digs_plan_fwd(self._h, _stream(stream)))
+
+    def bwd(self, stream=None):
+        _check("digs_plan_bwd", load().digs_plan_bwd(self._h, _stream(stream)))
+
+    def check(self, stream=None):
+        """(diagnostics dict, resized): after resized, repeat the calls since the last check."""
+        d = Diag()
+        r = ctypes.c_int(0)
+        _check("digs_plan_check", load().digs_plan_check(self._h, ctypes.byref(d),
+                                                         ctypes.byref(r), _stream(stream)))
+        return d.as_dict(), bool(r.value)
+
+    def tuning(self):
+        """(tuning dict, autotuner timings [candidate][fwd ms, bwd ms])."""
+        t = Tuning()
+        ms = (ctypes.c_float * (2 * TUNE_CANDIDATES))()
+        _check("digs_plan_get_tuning", load().digs_plan_get_tuning(
+            self._h, ctypes.byref(t), ctypes.cast(ms, ctypes.c_void_p)))
+        d = {k: getattr(t, k) for k, _ in Tuning._fields_}
+        return d, [[ms[2 * c], ms[2 * c + 1]] for c in range(TUNE_CANDIDATES)]
+
+    def close(self):
+        """Free the plan (its workspace and graphs); call before the process ends."""
+        if getattr(self, "_h", None):
+            load().digs_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

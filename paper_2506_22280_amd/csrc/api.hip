@@ -101,6 +101,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
         return o;
     };
     L->diag = take(sizeof(DiagBlock));
+    L->queue = take(8 * sizeof(uint32_t));
     L->uv = take(sizeof(float) * 12 * grid->R * N);
     L->rec = take(sizeof(float) * DIGS_REC_FLOATS * TN);
     L->rect = take(sizeof(int) * 2 * TN);
@@ -188,7 +189,8 @@ static int prepare(const digs_geom *geom, const digs_grid *grid, const float *co
     if (tuning && (tuning->capacity < 0 || !(tuning->cull_radius >= 0.0f) ||
                    (tuning->splat_waves != 0 && tuning->splat_waves != 1 &&
                     tuning->splat_waves != 4) ||
-                   tuning->bwd_waves < 0 || tuning->bwd_waves > 4))
+                   tuning->bwd_waves < 0 || tuning->bwd_waves > 4 || tuning->persistent < 0 ||
+                   tuning->persistent > 1))
         return DIGS_EINVAL;
     if (T > 0 && n > 0 && (!coef || !mu || !scale || !quat || !rho || !angles || !w))
         return DIGS_EINVAL;
@@ -208,6 +210,7 @@ static int prepare(const digs_geom *geom, const digs_grid *grid, const float *co
     a->cull = (tuning && tuning->cull_radius > 0.0f) ? tuning->cull_radius : 5.0f;
     a->splat_waves = (tuning && tuning->splat_waves) ? tuning->splat_waves : 4;
     a->bwd_waves = (tuning && tuning->bwd_waves) ? tuning->bwd_waves : 4;
+    a->persistent = tuning ? tuning->persistent : 0;
     a->ws = (char *)ws;
     return DIGS_OK;
 }

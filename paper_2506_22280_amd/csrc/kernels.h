@@ -7,6 +7,7 @@
 // Workspace layout of digs_project_fwd / digs_project_bwd (byte offsets, 256-byte aligned).
 struct WsLayout {
     size_t diag;       // DiagBlock
+    size_t queue;      // [8] u32 work-queue counters of the persistent splats
     size_t uv;         // [3R + 9R][N] f32: per-rank u_r(mu), grad u_r(mu) at the canonical means
     size_t rec;        // [T][N][16] f32 projected records
     size_t rect;       // [T][N] int2 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
@@ -57,7 +58,7 @@ struct RenderArgs {
     const float *coef, *mu, *scale, *quat, *rho, *angles, *w;
     int n, T;
     float cull;
-    int splat_waves, bwd_waves;
+    int splat_waves, bwd_waves, persistent;
     char *ws;
     WsLayout L;
 };
@@ -68,3 +69,4 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
                            float *g_w, hipStream_t s);                   // a6-a8
 hipError_t render_zero(float *p, size_t count, hipStream_t s);
 hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s);   // measurement only
+void render_prepare_launch_shapes();

@@ -1,0 +1,302 @@
+// plan.hip -- a prepared renderer for fixed shapes and fixed device buffers (the batched path):
+// it owns its workspace, holds the launch tuning (given by the caller, or chosen by timing the
+// candidate launch shapes on the caller's data), and captures the forward and the backward launch
+// sequences once each as HIP graphs that later calls replay.
+//
+// The graphs hold kernel nodes only (every clear in the sequence is a fill kernel), so replays
+// are self-contained. An instance-capacity overflow is detected by digs_plan_check, which then
+// grows the workspace and drops the graphs; the next call re-captures them.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "kernels.h"
+
+struct digs_plan {
+    digs_geom geom;
+    digs_grid grid;
+    int n = 0, T = 0;
+    digs_tuning tuning;
+    digs_plan_buffers b;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t gf = nullptr, gb = nullptr;
+    hipGraphExec_t ef = nullptr, eb = nullptr;
+    float tune_ms[DIGS_TUNE_CANDIDATES][2];
+};
+
+static int hip_rc(hipError_t e) { return e == hipSuccess ? DIGS_OK : digs_set_hip_error(e); }
+
+static void drop_graphs(digs_plan *p)
+{
+    if (p->ef) (void)hipGraphExecDestroy(p->ef);
+    if (p->eb) (void)hipGraphExecDestroy(p->eb);
+    if (p->gf) (void)hipGraphDestroy(p->gf);
+    if (p->gb) (void)hipGraphDestroy(p->gb);
+    p->ef = p->eb = nullptr;
+    p->gf = p->gb = nullptr;
+}
+
+static int plan_alloc(digs_plan *p)
+{
+    const size_t need = digs_workspace_size(&p->geom, &p->grid, p->n, p->T, &p->tuning);
+    if (need == 0) return DIGS_EINVAL;
+    if (p->ws && p->ws_bytes >= need) return DIGS_OK;
+    drop_graphs(p);
+    if (p->ws) (void)hipFree(p->ws);
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+    if (hipMalloc(&p->ws, need) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ws = nullptr;
+        return DIGS_ENOMEM;
+    }
+    p->ws_bytes = need;
+    return digs_reset_diagnostics(p->ws, p->cap);
+}
+
+static int run_fwd(digs_plan *p, hipStream_t s)
+{
+    const digs_plan_buffers &b = p->b;
+    return digs_project_fwd(&p->geom, &p->grid, b.coef, p->n, b.mu, b.scale, b.quat, b.rho, p->T,
+                            b.angles, b.w, b.proj, p->ws, p->ws_bytes, &p->tuning, s);
+}
+
+static int run_bwd(digs_plan *p, hipStream_t s)
+{
+    const digs_plan_buffers &b = p->b;
+    return digs_project_bwd(&p->geom, &p->grid, b.coef, p->n, b.mu, b.scale, b.quat, b.rho,
+                            p->T, b.angles, b.w, b.grad_proj, b.g_mu, b.g_scale, b.g_quat,
+                            b.g_rho, b.g_coef, b.g_w, p->ws, p->ws_bytes, &p->tuning,
+                            DIGS_BWD_REUSE_FWD, s);
+}
+
+// Record one launch sequence on the plan's own stream as a graph (stage timing is switched off
+// while recording so that no event nodes enter the graph).
+static int capture(digs_plan *p, bool fwd)
+{
+    const int prof = digs_profile_enable(-1);
+    digs_profile_enable(0);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    int rc = hip_rc(e);
+    if (rc == DIGS_OK) {
+        rc = fwd ? run_fwd(p, p->cap) : run_bwd(p, p->cap);
+        e = hipStreamEndCapture(p->cap, &g);
+        if (rc == DIGS_OK) rc = hip_rc(e);
+    }
+    digs_profile_enable(prof);
+    if (rc != DIGS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return digs_set_hip_error(e);
+    }
+    if (fwd) {
+        p->gf = g;
+        p->ef = x;
+    } else {
+        p->gb = g;
+        p->eb = x;
+    }
+    return DIGS_OK;
+}
+
+static int read_diag(digs_plan *p, digs_diag *d) { return digs_read_diagnostics(p->ws, d, p->cap); }
+
+static int64_t capacity_for(uint64_t instances)
+{
+    return (int64_t)(instances + instances / 4 + 4096);
+}
+
+// Time fwd (+ bwd) of one tuning on the plan's stream: one warm-up, then the median of three.
+static int time_tuning(digs_plan *p, float *fwd_ms, float *bwd_ms)
+{
+    hipEvent_t ev[3];
+    for (int i = 0; i < 3; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) return digs_set_hip_error(hipGetLastError());
+    const bool bwd = p->b.grad_proj != nullptr;
+    float f[3], b[3];
+    int rc = DIGS_OK;
+    for (int rep = 0; rep < 4 && rc == DIGS_OK; ++rep) {
+        rc = hip_rc(hipEventRecord(ev[0], p->cap));
+        if (rc == DIGS_OK) rc = run_fwd(p, p->cap);
+        if (rc == DIGS_OK) rc = hip_rc(hipEventRecord(ev[1], p->cap));
+        if (rc == DIGS_OK && bwd) rc = run_bwd(p, p->cap);
+        if (rc == DIGS_OK) rc = hip_rc(hipEventRecord(ev[2], p->cap));
+        if (rc == DIGS_OK) rc = hip_rc(hipEventSynchronize(ev[2]));
+        if (rc == DIGS_OK && rep > 0) {
+            (void)hipEventElapsedTime(&f[rep - 1], ev[0], ev[1]);
+            b[rep - 1] = 0.0f;
+            if (bwd) (void)hipEventElapsedTime(&b[rep - 1], ev[1], ev[2]);
+        }
+    }
+    for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc != DIGS_OK) return rc;
+    std::sort(f, f + 3);
+    std::sort(b, b + 3);
+    *fwd_ms = f[1];
+    *bwd_ms = b[1];
+    return DIGS_OK;
+}
+
+// The autotuner: size the instance capacity from a measured forward, then time every candidate
+// launch shape (forward splat waves per tile x persistent or one-workgroup-per-item splats) on the
+// caller's data and keep the fastest forward + backward. All candidates compute bitwise-identical
+// results; only their speed differs.
+static int autotune(digs_plan *p)
+{
+    memset(&p->tuning, 0, sizeof(p->tuning));
+    int rc = plan_alloc(p);
+    if (rc != DIGS_OK) return rc;
+    if (p->n == 0 || p->T == 0) return DIGS_OK;
+    rc = run_fwd(p, p->cap);
+    digs_diag d;
+    if (rc == DIGS_OK) rc = read_diag(p, &d);
+    if (rc != DIGS_OK) return rc;
+    p->tuning.capacity = capacity_for(d.instances);
+    if (p->ws) (void)hipFree(p->ws);
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+    if ((rc = plan_alloc(p)) != DIGS_OK) return rc;
+    static const int kWaves[DIGS_TUNE_CANDIDATES] = {4, 4, 1, 1};
+    static const int kPersist[DIGS_TUNE_CANDIDATES] = {0, 1, 0, 1};
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int c = 0; c < DIGS_TUNE_CANDIDATES; ++c) {
+        p->tuning.splat_waves = kWaves[c];
+        p->tuning.persistent = kPersist[c];
+        rc = time_tuning(p, &p->tune_ms[c][0], &p->tune_ms[c][1]);
+        if (rc != DIGS_OK) return rc;
+        const float ms = p->tune_ms[c][0] + p->tune_ms[c][1];
+        if (c == 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    p->tuning.splat_waves = kWaves[best];
+    p->tuning.persistent = kPersist[best];
+    return digs_reset_diagnostics(p->ws, p->cap);
+}
+
+extern "C" int digs_plan_create(const digs_geom *geom, const digs_grid *grid, int n, int T,
+                                const digs_tuning *tuning, const digs_plan_buffers *bufs,
+                                digs_plan **out)
+{
+    if (!out || !geom || !grid || !bufs) return DIGS_EINVAL;
+    *out = nullptr;
+    if (digs_workspace_size(geom, grid, n, T, tuning) == 0) return DIGS_EINVAL;
+    const digs_plan_buffers &b = *bufs;
+    if (T > 0 && (!b.proj || !b.g_w || !b.g_coef)) return DIGS_EINVAL;
+    if (T > 0 && n > 0 &&
+        (!b.coef || !b.mu || !b.scale || !b.quat || !b.rho || !b.angles || !b.w || !b.g_mu ||
+         !b.g_scale || !b.g_quat || !b.g_rho))
+        return DIGS_EINVAL;
+    digs_plan *p = new (std::nothrow) digs_plan;
+    if (!p) return DIGS_ENOMEM;
+    p->geom = *geom;
+    p->grid = *grid;
+    p->n = n;
+    p->T = T;
+    p->b = b;
+    memset(p->tune_ms, 0, sizeof(p->tune_ms));
+    render_prepare_launch_shapes();
+    int rc = hip_rc(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    if (rc == DIGS_OK) {
+        if (tuning) {
+            p->tuning = *tuning;
+            rc = plan_alloc(p);
+        } else {
+            rc = autotune(p);
+        }
+    }
+    if (rc == DIGS_OK) rc = hip_rc(hipStreamSynchronize(p->cap));
+    if (rc != DIGS_OK) {
+        digs_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return DIGS_OK;
+}
+
+// The caller's stream waits for everything the plan's own stream has queued before a replay.
+static int order_after_plan_stream(digs_plan *p, hipStream_t s)
+{
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        return digs_set_hip_error(hipGetLastError());
+    hipError_t e = hipEventRecord(ev, p->cap);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    (void)hipEventDestroy(ev);
+    return hip_rc(e);
+}
+
+extern "C" int digs_plan_fwd(digs_plan *p, void *stream)
+{
+    if (!p) return DIGS_EINVAL;
+    if (p->T == 0) return DIGS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->ef) {
+        int rc = capture(p, true);
+        if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
+        if (rc != DIGS_OK) return rc;
+    }
+    return hip_rc(hipGraphLaunch(p->ef, s));
+}
+
+extern "C" int digs_plan_bwd(digs_plan *p, void *stream)
+{
+    if (!p) return DIGS_EINVAL;
+    if (p->T == 0 && p->n == 0) return DIGS_OK;
+    if (!p->b.grad_proj && p->n > 0 && p->T > 0) return DIGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->eb) {
+        int rc = capture(p, false);
+        if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
+        if (rc != DIGS_OK) return rc;
+    }
+    return hip_rc(hipGraphLaunch(p->eb, s));
+}
+
+extern "C" int digs_plan_check(digs_plan *p, digs_diag *out, int *resized, void *stream)
+{
+    if (!p || !out) return DIGS_EINVAL;
+    if (resized) *resized = 0;
+    int rc = hip_rc(hipStreamSynchronize((hipStream_t)stream));
+    if (rc == DIGS_OK) rc = read_diag(p, out);
+    if (rc != DIGS_OK || !out->overflow) return rc;
+    // grow the capacity past what the overflowing call needed; the graphs are re-captured
+    p->tuning.capacity = capacity_for(out->instances);
+    if (p->ws) (void)hipFree(p->ws);
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+    rc = plan_alloc(p);
+    if (rc == DIGS_OK) rc = hip_rc(hipStreamSynchronize(p->cap));
+    if (rc == DIGS_OK && resized) *resized = 1;
+    return rc;
+}
+
+extern "C" int digs_plan_get_tuning(const digs_plan *p, digs_tuning *out, float *tune_ms)
+{
+    if (!p || !out) return DIGS_EINVAL;
+    *out = p->tuning;
+    if (tune_ms) memcpy(tune_ms, p->tune_ms, sizeof(p->tune_ms));
+    return DIGS_OK;
+}
+
+extern "C" int digs_plan_destroy(digs_plan *p)
+{
+    if (!p) return DIGS_OK;
+    if (p->cap) (void)hipStreamSynchronize(p->cap);
+    drop_graphs(p);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+    return DIGS_OK;
+}

@@ -63,8 +63,9 @@ void prof_end(int stage, hipStream_t s)
 
 extern "C" int digs_profile_enable(int on)
 {
-    g_on = on != 0;
-    return DIGS_OK;
+    const int prev = g_on ? 1 : 0;
+    if (on >= 0) g_on = on != 0;
+    return prev;
 }
 
 extern "C" int digs_profile_read(digs_profile_entry *out, int max_entries, int reset)

@@ -497,16 +497,13 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 // are evaluated. The per-lane row sums are reduced over the 8 slots at the end in a fixed order,
 // and every pixel is written once.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
-                                                          const float4 *__restrict__ rec,
-                                                          const uint32_t *__restrict__ list,
-                                                          const uint32_t *__restrict__ cnt,
-                                                          int nblk, unsigned cap,
-                                                          float *__restrict__ proj)
+__device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, int tile,
+                                               const float4 *__restrict__ rec,
+                                               const uint32_t *__restrict__ list,
+                                               const uint32_t *__restrict__ cnt, int nblk,
+                                               unsigned cap, float *__restrict__ proj,
+                                               uint32_t (*ids)[DIGS_WAVE])
 {
-    __shared__ uint32_t ids[WAVES][DIGS_WAVE];
-    int t, tile;
-    map_block(blockIdx.x, G.ntiles, T, t, tile);
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
     const int gslot = lane >> 3, col = lane & 7;
@@ -602,6 +599,59 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
     }
 }
 
+// Work items of a persistent launch: with T a multiple of 8 there is one queue per XCD (queue x
+// holds the views t = x mod 8, tile by tile, like map_block); a workgroup takes items from the
+// queue of its XCD (workgroups of a launch start on XCD b mod 8) and, once that is empty, from the
+// others in turn. Returns -1 when every queue is empty, so every workgroup ends.
+__device__ __forceinline__ int next_item(uint32_t *__restrict__ queue, int home, int ntiles,
+                                         int T)
+{
+    const int nq = ((T & 7) == 0) ? 8 : 1;
+    const uint32_t per = (uint32_t)(T / nq) * (uint32_t)ntiles;
+    for (int k = 0; k < nq; ++k) {
+        const int x = (home + k) % nq;
+        const uint32_t j = atomicAdd(&queue[x], 1u);
+        if (j < per) return (nq == 8) ? (int)(j * 8u + (uint32_t)x) : (int)j;
+    }
+    return -1;
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
+                                                          const float4 *__restrict__ rec,
+                                                          const uint32_t *__restrict__ list,
+                                                          const uint32_t *__restrict__ cnt,
+                                                          int nblk, unsigned cap,
+                                                          float *__restrict__ proj)
+{
+    __shared__ uint32_t ids[WAVES][DIGS_WAVE];
+    int t, tile;
+    map_block(blockIdx.x, G.ntiles, T, t, tile);
+    splat_fwd_tile<WAVES>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
+}
+
+// Persistent variant: a grid sized to the machine loops over the work queues.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
+    DevGeom G, int n, int T, const float4 *__restrict__ rec, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ cnt, int nblk, unsigned cap, float *__restrict__ proj,
+    uint32_t *__restrict__ queue)
+{
+    __shared__ uint32_t ids[WAVES][DIGS_WAVE];
+    __shared__ int s_item;
+    const int home = blockIdx.x & 7;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = next_item(queue, home, G.ntiles, T);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item < 0) break;
+        int t, tile;
+        map_block(item, G.ntiles, T, t, tile);
+        splat_fwd_tile<WAVES>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
+    }
+}
+
 // Measurement only: the pairs inside each footprint and on the detector, and the pairs the forward
 // and backward splats evaluate (64 per 8x8 block that a footprint ellipse meets, in both).
 __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, float cull,
@@ -678,21 +728,24 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 //  7 S_qu, 8 S_qv, 9 S_q      sum A_q du, dv, 1
 //  10 S_Eu, 11 S_Ev           sum A_E du, dv
 #define GPX_STRIDE 18
-__global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
-                                                   const float4 *__restrict__ rec,
-                                                   const uint32_t *__restrict__ list,
-                                                   const uint32_t *__restrict__ cnt, int nblk,
-                                                   unsigned cap,
-                                                   const int2 *__restrict__ rect,
-                                                   const uint32_t *__restrict__ goff,
-                                                   const float *__restrict__ grad_proj,
-                                                   float4 *__restrict__ part)
+struct BwdShared {
+    float gpx[DIGS_TILE * GPX_STRIDE];
+    uint32_t pairs[4][4 * DIGS_WAVE];
+    float accS[4][DIGS_WAVE][13];
+};
+
+__device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, int tile,
+                                               const float4 *__restrict__ rec,
+                                               const uint32_t *__restrict__ list,
+                                               const uint32_t *__restrict__ cnt, int nblk,
+                                               unsigned cap, const int2 *__restrict__ rect,
+                                               const uint32_t *__restrict__ goff,
+                                               const float *__restrict__ grad_proj,
+                                               float4 *__restrict__ part, BwdShared &sh)
 {
-    __shared__ float gpx[DIGS_TILE * GPX_STRIDE];
-    __shared__ uint32_t pairs[4][4 * DIGS_WAVE];
-    __shared__ float accS[4][DIGS_WAVE][13];
-    int t, tile;
-    map_block(blockIdx.x, G.ntiles, T, t, tile);
+    float *gpx = sh.gpx;
+    uint32_t(*pairs)[4 * DIGS_WAVE] = sh.pairs;
+    float(*accS)[DIGS_WAVE][13] = sh.accS;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
     {
@@ -839,6 +892,47 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+__global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
+                                                   const float4 *__restrict__ rec,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint32_t *__restrict__ cnt, int nblk,
+                                                   unsigned cap, const int2 *__restrict__ rect,
+                                                   const uint32_t *__restrict__ goff,
+                                                   const float *__restrict__ grad_proj,
+                                                   float4 *__restrict__ part)
+{
+    __shared__ BwdShared sh;
+    int t, tile;
+    map_block(blockIdx.x, G.ntiles, T, t, tile);
+    splat_bwd_tile(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part, sh);
+}
+
+__global__ __launch_bounds__(256) void k_splat_bwd_persist(
+    DevGeom G, int n, int T, const float4 *__restrict__ rec, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ cnt, int nblk, unsigned cap, const int2 *__restrict__ rect,
+    const uint32_t *__restrict__ goff, const float *__restrict__ grad_proj,
+    float4 *__restrict__ part, uint32_t *__restrict__ queue)
+{
+    __shared__ BwdShared sh;
+    __shared__ int s_item;
+    const int home = blockIdx.x & 7;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = next_item(queue, home, G.ntiles, T);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item < 0) break;
+        int t, tile;
+        map_block(item, G.ntiles, T, t, tile);
+        splat_bwd_tile(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part, sh);
+    }
+}
+
+__global__ void k_queue_reset(uint32_t *q)
+{
+    if (threadIdx.x < 8) q[threadIdx.x] = 0u;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1348,19 +1442,84 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Workgroups of a persistent launch: enough to fill every CU at the kernel's occupancy, never more
+// than there are work items.
+// The device queries run once per kernel (the first launch happens before any graph capture).
+template <class K>
+static unsigned persistent_grid(K kernel, int threads, size_t items)
+{
+    static int cus = 0;
+    static const void *known[8];
+    static int known_per_cu[8];
+    static int nknown = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    int per_cu = 0;
+    for (int i = 0; i < nknown; ++i)
+        if (known[i] == (const void *)kernel) per_cu = known_per_cu[i];
+    if (per_cu == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1;
+        if (nknown < 8) {
+            known[nknown] = (const void *)kernel;
+            known_per_cu[nknown++] = per_cu;
+        }
+    }
+    const size_t g = (size_t)cus * (size_t)per_cu;
+    return (unsigned)(g < items ? g : items);
+}
+
+// Run the device queries of the persistent launches now (before any graph capture).
+void render_prepare_launch_shapes()
+{
+    (void)persistent_grid(k_splat_fwd_persist<1>, 64, 1);
+    (void)persistent_grid(k_splat_fwd_persist<4>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist, 256, 1);
+}
+
 hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
 {
-    dim3 grid(a.geom.ntiles * a.T);
+    const size_t items = (size_t)a.geom.ntiles * a.T;
     const unsigned cap = (unsigned)a.L.cap;
+    uint32_t *queue = WS(a, queue, uint32_t *);
+    if (a.persistent) {
+        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     ProfScope ps(PS_SPLAT_FWD, s);
-    if (a.splat_waves == 1)
-        hipLaunchKernelGGL(k_splat_fwd<1>, grid, dim3(64), 0, s, a.geom, a.n, a.T,
-                           WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
-                           WS(a, cnt, const uint32_t *), a.L.nblk, cap, proj);
-    else
-        hipLaunchKernelGGL(k_splat_fwd<4>, grid, dim3(256), 0, s, a.geom, a.n, a.T,
-                           WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
-                           WS(a, cnt, const uint32_t *), a.L.nblk, cap, proj);
+    if (a.splat_waves == 1) {
+        if (a.persistent)
+            hipLaunchKernelGGL(k_splat_fwd_persist<1>,
+                               dim3(persistent_grid(k_splat_fwd_persist<1>, 64, items)), dim3(64),
+                               0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
+                               a.L.nblk, cap, proj, queue);
+        else
+            hipLaunchKernelGGL(k_splat_fwd<1>, dim3((unsigned)items), dim3(64), 0, s, a.geom,
+                               a.n, a.T, WS(a, rec, const float4 *),
+                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
+                               a.L.nblk, cap, proj);
+    } else {
+        if (a.persistent)
+            hipLaunchKernelGGL(k_splat_fwd_persist<4>,
+                               dim3(persistent_grid(k_splat_fwd_persist<4>, 256, items)),
+                               dim3(256), 0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
+                               a.L.nblk, cap, proj, queue);
+        else
+            hipLaunchKernelGGL(k_splat_fwd<4>, dim3((unsigned)items), dim3(256), 0, s, a.geom,
+                               a.n, a.T, WS(a, rec, const float4 *),
+                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
+                               a.L.nblk, cap, proj);
+    }
     return hipGetLastError();
 }
 
@@ -1446,12 +1605,27 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
     hipError_t e;
     // a6: per-instance moment sums
     {
+        const size_t items = (size_t)a.geom.ntiles * a.T;
+        uint32_t *queue = WS(a, queue, uint32_t *);
+        if (a.persistent) {
+            hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         ProfScope ps(PS_SPLAT_BWD, s);
-        hipLaunchKernelGGL(k_splat_bwd, dim3(a.geom.ntiles * a.T), dim3(256), 0, s, a.geom, a.n,
-                           a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
-                           WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
-                           WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *), grad_proj,
-                           WS(a, part, float4 *));
+        if (a.persistent)
+            hipLaunchKernelGGL(k_splat_bwd_persist,
+                               dim3(persistent_grid(k_splat_bwd_persist, 256, items)), dim3(256),
+                               0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
+                               a.L.nblk, (unsigned)a.L.cap, WS(a, rect, const int2 *),
+                               WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
+                               queue);
+        else
+            hipLaunchKernelGGL(k_splat_bwd, dim3((unsigned)items), dim3(256), 0, s, a.geom, a.n,
+                               a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
+                               WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
+                               WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
+                               grad_proj, WS(a, part, float4 *));
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;

@@ -1,0 +1,115 @@
+"""The batched path (digs_plan_*): graph replays equal the eager calls bit for bit, also after
+eager work and synchronisations between replays and after new inputs are written into the plan's
+buffers; every autotuner candidate gives the same bits; an instance-capacity overflow is
+detected, the plan grows and the repeated call is complete."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_22280_amd import _lib, synth
+from gpu_helpers import dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _buffers(p, idx):
+    angles, w = p.views(idx)
+    T, n = len(idx), p.n
+    nv, nu = p.geom["nv"], p.geom["nu"]
+    rng = np.random.default_rng(5)
+    b = dict(coef=dev(p.coef), mu=dev(p.mu), scale=dev(p.scale), quat=dev(p.quat),
+             rho=dev(p.rho), angles=dev(angles), w=dev(w),
+             proj=torch.empty((T, nv, nu), device="cuda"),
+             grad_proj=dev(rng.normal(0, 1, (T, nv, nu))),
+             g_mu=torch.empty((3, n), device="cuda"), g_scale=torch.empty((3, n), device="cuda"),
+             g_quat=torch.empty((4, n), device="cuda"), g_rho=torch.empty((n,), device="cuda"),
+             g_coef=torch.empty_like(dev(p.coef)), g_w=torch.empty((T, p.grid["R"]), device="cuda"))
+    return b
+
+
+def _eager(p, b, tuning=None):
+    ws = _lib.Workspace()
+    proj = _lib.project_fwd(p.geom, p.grid, b["coef"], b["mu"], b["scale"], b["quat"], b["rho"],
+                            b["angles"], b["w"], ws, tuning=tuning)
+    g = _lib.project_bwd(p.geom, p.grid, b["coef"], b["mu"], b["scale"], b["quat"], b["rho"],
+                         b["angles"], b["w"], b["grad_proj"], ws, tuning=tuning, reuse_fwd=True)
+    torch.cuda.synchronize()
+    return proj, g
+
+
+_GRADS = ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef", "g_w")
+
+
+@pytest.mark.parametrize("nviews", [8, 6])
+def test_plan_replays_equal_eager(nviews):
+    _print("case: plan (autotuned) replays vs eager, small phantom, %d views" % nviews)
+    p = synth.small_phantom(n=2048, nviews=nviews, seed=4)
+    idx = np.arange(nviews)
+    b = _buffers(p, idx)
+    ref_proj, ref_g = _eager(p, b)
+    with _lib.Plan(p.geom, p.grid, p.n, nviews, b) as plan:
+        tuning, ms = plan.tuning()
+        _print("chosen", tuning, "timings", ms)
+        assert tuning["capacity"] > 0
+        for rep in range(3):
+            b["proj"].fill_(-1.0)
+            for k in _GRADS:
+                b[k].fill_(-1.0)
+            plan.fwd()
+            plan.bwd()
+            torch.cuda.synchronize()
+            assert torch.equal(b["proj"], ref_proj), rep
+            for k in _GRADS:
+                assert torch.equal(b[k], ref_g[k]), (rep, k)
+            # eager work of the program itself between replays
+            _eager(p, b)
+        # a new batch: other views written into the same buffers
+        p2 = synth.small_phantom(n=2048, nviews=2 * nviews, seed=4)
+        a2, w2 = p2.views(np.arange(nviews, 2 * nviews))
+        b["angles"].copy_(dev(a2))
+        b["w"].copy_(dev(w2))
+        plan.fwd()
+        plan.bwd()
+        diag, resized = plan.check()
+        assert not resized and diag["overflow"] == 0
+        got = b["proj"].clone()
+        gg = {k: b[k].clone() for k in _GRADS}
+        ref2_proj, ref2_g = _eager(p, b)
+        assert torch.equal(got, ref2_proj)
+        for k in _GRADS:
+            assert torch.equal(gg[k], ref2_g[k]), k
+
+
+def test_every_tuning_candidate_gives_the_same_bits():
+    _print("case: forward/backward under every launch shape the autotuner chooses from")
+    p = synth.small_phantom(n=2048, nviews=8, seed=6)
+    b = _buffers(p, np.arange(8))
+    ref_proj, ref_g = _eager(p, b)
+    for waves in (4, 1):
+        for persistent in (0, 1):
+            proj, g = _eager(p, b, tuning=dict(splat_waves=waves, persistent=persistent))
+            assert torch.equal(proj, ref_proj), (waves, persistent)
+            for k in _GRADS:
+                assert torch.equal(g[k], ref_g[k]), (waves, persistent, k)
+
+
+def test_plan_overflow_is_detected_and_recovered():
+    _print("case: plan with a far too small instance capacity; check, grow, repeat")
+    p = synth.small_phantom(n=2048, nviews=8, seed=7)
+    b = _buffers(p, np.arange(8))
+    ref_proj, ref_g = _eager(p, b)
+    with _lib.Plan(p.geom, p.grid, p.n, 8, b, tuning=dict(capacity=64, persistent=1)) as plan:
+        plan.fwd()
+        diag, resized = plan.check()
+        assert diag["overflow"] == 1 and resized and diag["instances"] > 64
+        plan.fwd()
+        plan.bwd()
+        diag, resized = plan.check()
+        assert diag["overflow"] == 0 and not resized
+        assert torch.equal(b["proj"], ref_proj)
+        for k in _GRADS:
+            assert torch.equal(b[k], ref_g[k]), k
