@@ -201,6 +201,45 @@ int digs_plan_check(digs_plan *plan, digs_diag *out, int *resized, void *stream)
 int digs_plan_get_tuning(const digs_plan *plan, digs_tuning *out, float *tune_ms);
 int digs_plan_destroy(digs_plan *plan);
 
+/* ---------------------------------------------------------------------------------------------
+ * The per-projection temporal-weight fit and its learned warm start. For a measured view P_t the
+ * plain fit finds the weights w_t of the low-rank motion model (Sec. 3.3, Eq. 9) minimising
+ * 1/2 ||I(w_t) - P_t||^2 by Levenberg-Marquardt (host loop: one batched digs_project_fwd of the
+ * base weights and R raised copies per step, then digs_lm_normal_eq). The warm start predicts w_t
+ * from the downsampled view and the gantry angle with a small MLP whose products run on the
+ * matrix cores (digs_gemm_bf16). Device pointers, float32, row-major; asynchronous on `stream`.
+ *
+ * digs_lm_normal_eq: imgs [T][R+1][npix] (base image, then the base with w_r raised by h[r]),
+ *   meas [T][npix], h [R] (device) -> out [T][R(R+1)/2 + R + 1]: J^T J (upper triangle, row-major),
+ *   J^T res, res.res with J_r = (I_r - I_0)/h_r, res = I_0 - P. Fixed-order sums.
+ * digs_gemm_bf16: C[M][N] = A . B with A [M][K] (lda; transA: stored [K][M]) and B [K][N] (ldb;
+ *   transB: stored [N][K]), FP32 in memory, BF16 operands on MFMA (v_mfma_f32_32x32x16_bf16), FP32
+ *   accumulate; then, in order, + C if accumulate, + bias[N] if bias, max(., 0) if relu, 0 where
+ *   gate[M][N] (leading dimension ldc) is <= 0 if gate.
+ * digs_colsum: out[N] = column sums of X [M][N] (ldx). digs_mse: mean of
+ *   (pred - (target - mean)/std)^2 over [B][R], its gradient dpred [B][R] and (if loss) the value.
+ * digs_adam: one Adam step (bias-corrected; step >= 1) on n FP32 weights with moments m, v.
+ * digs_downsample: out[t][0 .. (nv/fy)(nu/fx)) = scale x the fy x fx block means of proj
+ *   [T][nv][nu] (row-major), standardised per feature as (x - fmean[i]) * fistd[i] if fmean and
+ *   fistd are given (both or neither), then sin and cos of angles[t] if angles (ld_out per row).
+ * digs_standardize: X[i][j] = (X[i][j] - mean[j]) * istd[j] for j < N, in place.
+ * Errors: DIGS_EINVAL, DIGS_EHIP. */
+int digs_lm_normal_eq(int T, int R, int npix, const float *imgs, const float *meas,
+                      const float *h, float *out, void *stream);
+int digs_gemm_bf16(int M, int N, int K, const float *A, int lda, int transA, const float *B,
+                   int ldb, int transB, float *C, int ldc, const float *bias, const float *gate,
+                   int relu, int accumulate, void *stream);
+int digs_colsum(int M, int N, const float *X, int ldx, float *out, void *stream);
+int digs_mse(int B, int R, const float *pred, const float *target, const float *mean,
+             const float *stdv, float *dpred, float *loss, void *stream);
+int digs_adam(int n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2,
+              float eps, int step, void *stream);
+int digs_downsample(int T, int nv, int nu, int fy, int fx, const float *proj,
+                    const float *angles, float scale, const float *fmean, const float *fistd,
+                    float *out, int ld_out, void *stream);
+int digs_standardize(int M, int N, float *X, int ldx, const float *mean, const float *istd,
+                     void *stream);
+
 /* Diagnostics of a workspace: digs_read_diagnostics synchronises `stream` and copies the block
  * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). */
 int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);

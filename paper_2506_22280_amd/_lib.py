@@ -102,6 +102,20 @@ _SIGS = {
                                        _VP]),
     "digs_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning), _VP]),
     "digs_plan_destroy": (ctypes.c_int, [_VP]),
+    "digs_lm_normal_eq": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP,
+                                         _VP, _VP]),
+    "digs_gemm_bf16": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
+                                      ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int, _VP,
+                                      ctypes.c_int, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
+    "digs_colsum": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP, _VP]),
+    "digs_mse": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "digs_adam": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, ctypes.c_int, _VP]),
+    "digs_downsample": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, _VP, _VP, ctypes.c_float, _VP, _VP, _VP,
+                                       ctypes.c_int, _VP]),
+    "digs_standardize": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP, _VP,
+                                        _VP]),
     "digs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "digs_last_hip_error": (ctypes.c_int, []),
 }
@@ -399,3 +413,67 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------------------------------------------
+# Temporal-weight fit and learned warm start (kernels; the loops live in warmstart.py)
+def lm_normal_eq(imgs, meas, h, R: int, stream=None):
+    """[T][R(R+1)/2 + R + 1] normal-equation terms from imgs [T][R+1][npix], meas [T][npix]."""
+    T = meas.shape[0]
+    npix = meas[0].numel() if T else 0
+    out = torch.empty((T, R * (R + 1) // 2 + R + 1), device=meas.device)
+    _check("digs_lm_normal_eq", load().digs_lm_normal_eq(T, R, npix, _ptr(imgs), _ptr(meas),
+                                                         _ptr(h), _ptr(out), _stream(stream)))
+    return out
+
+
+def gemm_bf16(A, B, C, transA=False, transB=False, bias=None, gate=None, relu=False,
+              accumulate=False, stream=None):
+    """C = epilogue(op(A) . op(B)) on the matrix cores (BF16 operands, FP32 accumulate)."""
+    M = A.shape[1] if transA else A.shape[0]
+    K = A.shape[0] if transA else A.shape[1]
+    N = B.shape[0] if transB else B.shape[1]
+    _check("digs_gemm_bf16", load().digs_gemm_bf16(
+        M, N, K, _ptr(A), A.stride(0), int(transA), _ptr(B), B.stride(0), int(transB), _ptr(C),
+        C.stride(0), _ptr(bias), _ptr(gate), int(relu), int(accumulate), _stream(stream)))
+    return C
+
+
+def colsum(X, out, stream=None):
+    _check("digs_colsum", load().digs_colsum(X.shape[0], X.shape[1], _ptr(X), X.stride(0),
+                                             _ptr(out), _stream(stream)))
+    return out
+
+
+def mse(pred, target, mean, std, dpred, loss=None, stream=None):
+    _check("digs_mse", load().digs_mse(pred.shape[0], pred.shape[1], _ptr(pred), _ptr(target),
+                                       _ptr(mean), _ptr(std), _ptr(dpred), _ptr(loss),
+                                       _stream(stream)))
+
+
+def adam(w, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    _check("digs_adam", load().digs_adam(w.numel(), _ptr(w), _ptr(g), _ptr(m), _ptr(v),
+                                         float(lr), float(b1), float(b2), float(eps), int(step),
+                                         _stream(stream)))
+
+
+def downsample(proj, fy: int, fx: int, angles=None, scale=1.0, fmean=None, fistd=None, out=None,
+               stream=None):
+    """[T][(nv/fy)(nu/fx) (+2)] block means (x scale, standardised per feature if fmean/fistd are
+    given, + sin, cos of the angle) of proj [T][nv][nu]."""
+    T, nv, nu = proj.shape
+    nfeat = (nv // fy) * (nu // fx) + (2 if angles is not None else 0)
+    if out is None:
+        out = torch.empty((T, nfeat), device=proj.device)
+    _check("digs_downsample", load().digs_downsample(T, nv, nu, fy, fx, _ptr(proj), _ptr(angles),
+                                                     float(scale), _ptr(fmean), _ptr(fistd),
+                                                     _ptr(out), out.stride(0), _stream(stream)))
+    return out
+
+
+def standardize(X, mean, istd, ncols: int | None = None, stream=None):
+    """In place: X[:, :ncols] = (X - mean) * istd per column."""
+    N = X.shape[1] if ncols is None else ncols
+    _check("digs_standardize", load().digs_standardize(X.shape[0], N, _ptr(X), X.stride(0),
+                                                       _ptr(mean), _ptr(istd), _stream(stream)))
+    return X
