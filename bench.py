@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event stage timing (plain timed loop only)")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the learned-warm-start leg (speedup vs the plain fit)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, run a plain device-to-device copy of this many "
                          "MiB three times (the reference kernel for scaling HBM byte counters)")
@@ -260,6 +262,26 @@ def main():
             "in_footprint": int(in_fp / len(pairs) / B),
             "evaluated_fwd": int(sum(x[1] for x in pairs) / len(pairs) / B),
             "evaluated_bwd": int(sum(x[2] for x in pairs) / len(pairs) / B)}
+    if not args.no_warmstart:
+        # "speedup vs plain": the learned warm start against the plain per-projection fit, time
+        # to the same residual tolerance on views of unseen phantoms of the same family and size
+        # (a reduced training set: 6 phantoms x 320 views; the full 15 x 1320 configuration is
+        # `python -m paper_2506_22280_amd.warmstart`)
+        from paper_2506_22280_amd import warmstart
+        ws_out = warmstart.experiment(n, G["nu"], G["nv"], G["pitch_u"], len(p.angles),
+                                      Gd["spacing"][0], list(range(6)), [100, 101],
+                                      G["nv"] // 64, G["nu"] // 64, views_per_seed=320,
+                                      epochs=60, log=lambda m: print(m, file=sys.stderr,
+                                                                     flush=True))
+        out["speedup_vs_plain"] = {
+            "value": ws_out["wall_clock_speedup"],
+            "meaning": "plain-fit seconds / warm-started-fit seconds to RMS residual <= 1e-3 of "
+                       "the view, same GPU, views of 2 unseen phantoms",
+            "plain_s": ws_out["plain"]["seconds"], "warm_s": ws_out["warm"]["seconds"],
+            "images_per_view": [ws_out["plain"]["mean_images_per_view"],
+                                ws_out["warm"]["mean_images_per_view"]],
+            "test_views": ws_out["test_views"], "train_pairs": ws_out["train_pairs"],
+            "fallbacks": ws_out["warm"]["fallbacks"]}
     if not args.no_cpu_baseline:
         params = tuple(x.astype(np.float64) for x in est_np[:4]) + (est_np[4],)
         out["cpu_baseline"] = cpu_baseline(p, params, batches[0])

@@ -202,6 +202,30 @@ int digs_plan_get_tuning(const digs_plan *plan, digs_tuning *out, float *tune_ms
 int digs_plan_destroy(digs_plan *plan);
 
 /* ---------------------------------------------------------------------------------------------
+ * The dynamic volume at one time point (Sec. 3.2, Eq. 6; Sec. 3.3, Eq. 9), on a voxel grid whose
+ * voxel (i,j,k) centre sits at origin + (i,j,k)*spacing; volumes are stored [nz][ny][nx].
+ * digs_dvf_grid: dvf [3][nz][ny][nx] = sum_r w[r] u_r(x) at every voxel centre (w: device, [R]).
+ * digs_phi_grid: phi [nz][ny][nx] = sum_n rho_n exp(-(x - mu'_n)^T Sigma'_n^-1 (x - mu'_n) / 2)
+ *   with (mu', Sigma') the warp of Eq. 7-8 at weights w, each Gaussian cut off beyond Mahalanobis
+ *   radius `cull` along each axis (0: default 5). ws of digs_phi_workspace_size bytes (256-byte
+ *   aligned) with room for `capacity` (brick, Gaussian) pairs (0: 64 n + 4096); the number
+ *   needed and any overflow are reported by digs_read_diagnostics(ws).
+ * Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP. */
+typedef struct digs_vgrid {
+    int nx, ny, nz;          /* voxels per axis, 1..4096                                        */
+    float origin[3];         /* centre of voxel (0,0,0), mm                                     */
+    float spacing[3];        /* mm, > 0                                                         */
+} digs_vgrid;
+
+int digs_dvf_grid(const digs_grid *grid, const float *coef, const float *w, const digs_vgrid *vg,
+                  float *dvf, void *stream);
+size_t digs_phi_workspace_size(const digs_vgrid *vg, int n, int64_t capacity);
+int digs_phi_grid(const digs_grid *grid, const float *coef, int n, const float *mu,
+                  const float *scale, const float *quat, const float *rho, const float *w,
+                  const digs_vgrid *vg, float cull, int64_t capacity, float *phi, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * The per-projection temporal-weight fit and its learned warm start. For a measured view P_t the
  * plain fit finds the weights w_t of the low-rank motion model (Sec. 3.3, Eq. 9) minimising
  * 1/2 ||I(w_t) - P_t||^2 by Levenberg-Marquardt (host loop: one batched digs_project_fwd of the

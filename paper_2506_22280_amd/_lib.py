@@ -54,6 +54,20 @@ class Diag(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class VGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3)]
+
+
+def make_vgrid(v: dict) -> VGrid:
+    V = VGrid()
+    V.nx, V.ny, V.nz = int(v["nx"]), int(v["ny"]), int(v["nz"])
+    for a in range(3):
+        V.origin[a] = float(v["origin"][a])
+        V.spacing[a] = float(v["spacing"][a])
+    return V
+
+
 class PlanBuffers(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in (
         "coef", "mu", "scale", "quat", "rho", "angles", "w", "proj", "grad_proj", "g_mu",
@@ -102,6 +116,13 @@ _SIGS = {
                                        _VP]),
     "digs_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning), _VP]),
     "digs_plan_destroy": (ctypes.c_int, [_VP]),
+    "digs_dvf_grid": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.POINTER(VGrid), _VP,
+                                     _VP]),
+    "digs_phi_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(VGrid), ctypes.c_int,
+                                                  ctypes.c_int64]),
+    "digs_phi_grid": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.c_int, _VP, _VP, _VP, _VP,
+                                     _VP, ctypes.POINTER(VGrid), ctypes.c_float, ctypes.c_int64,
+                                     _VP, _VP, ctypes.c_size_t, _VP]),
     "digs_lm_normal_eq": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP,
                                          _VP, _VP]),
     "digs_gemm_bf16": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
@@ -477,3 +498,42 @@ def standardize(X, mean, istd, ncols: int | None = None, stream=None):
     _check("digs_standardize", load().digs_standardize(X.shape[0], N, _ptr(X), X.stride(0),
                                                        _ptr(mean), _ptr(istd), _stream(stream)))
     return X
+
+
+# ------------------------------------------------------------------------------------------------
+# The dynamic volume at one time point on a voxel grid
+def dvf_grid(grid: dict, coef, w, vgrid: dict, stream=None):
+    """dvf [3][nz][ny][nx] = sum_r w_r u_r(x) at the voxel centres (w: device [R])."""
+    V = make_vgrid(vgrid)
+    out = torch.empty((3, V.nz, V.ny, V.nx), device=coef.device)
+    G = make_grid(grid)
+    _check("digs_dvf_grid", load().digs_dvf_grid(ctypes.byref(G), _ptr(coef), _ptr(w),
+                                                 ctypes.byref(V), _ptr(out), _stream(stream)))
+    return out
+
+
+def phi_grid(grid: dict, coef, mu, scale, quat, rho, w, vgrid: dict, ws: "Workspace",
+             cull: float = 0.0, capacity: int = 0, out=None, grow: bool = True, stream=None):
+    """phi [nz][ny][nx]: the warped Gaussians (weights w, device [R]) summed at voxel centres.
+    With grow, an overflow of the (brick, Gaussian) capacity reported by the diagnostics makes
+    the call repeat with the capacity the diagnostics say is needed (this synchronises)."""
+    V, G = make_vgrid(vgrid), make_grid(grid)
+    n = mu.shape[1]
+    if out is None:
+        out = torch.empty((V.nz, V.ny, V.nx), device=mu.device)
+    while True:
+        nbytes = int(load().digs_phi_workspace_size(ctypes.byref(V), n, int(capacity)))
+        if nbytes == 0:
+            raise DigsError("digs_phi_workspace_size", -1)
+        buf = ws.get(nbytes)
+        _check("digs_phi_grid", load().digs_phi_grid(
+            ctypes.byref(G), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat), _ptr(rho), _ptr(w),
+            ctypes.byref(V), float(cull), int(capacity), _ptr(out), _ptr(buf), buf.numel(),
+            _stream(stream)))
+        ws.touched()
+        if not grow:
+            return out
+        d = ws.diagnostics(stream)
+        if not d["overflow"]:
+            return out
+        capacity = int(d["instances"] * 1.25) + 4096

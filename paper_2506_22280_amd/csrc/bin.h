@@ -11,6 +11,8 @@
 #pragma once
 
 #include "common.h"
+#include "kernels.h"
+#include "prof.h"
 
 #define BIN_THREADS 256
 #define BIN_WAVES (BIN_THREADS / DIGS_WAVE)
@@ -105,4 +107,90 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
             if (active) src.emit(slice, item, it, k, pos);
         }
     }
+}
+
+// Stable LSD radix pass source: 8 bits of 32-bit keys from `shift`, values carried along.
+struct RadixSrc {
+    const uint32_t *keys_in, *vals_in;
+    uint32_t *keys_out, *vals_out;
+    int items;
+    int shift;
+    struct Item {
+        uint32_t k;
+        __device__ int nkeys() const { return 1; }
+        __device__ int key(int) const { return (int)k; }
+    };
+    __device__ Item load(int, int item) const
+    {
+        Item it;
+        it.k = (keys_in[item] >> shift) & 255u;
+        return it;
+    }
+    __device__ void prepare(int, int, Item &) const {}
+    __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
+    {
+        if (pos < (uint32_t)items) {
+            keys_out[pos] = keys_in[item];
+            vals_out[pos] = vals_in[item];
+        }
+    }
+};
+
+// Count, scan and place (see above); the scan runs over (slice, key, block) counts.
+template <class Src>
+static inline hipError_t launch_binning(const Src &src, int slices, int nbins, int nblk, int nbits,
+                                 uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
+                                 hipStream_t s)
+{
+    const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
+    {
+        ProfScope ps(PS_BIN_COUNT, s);
+        hipLaunchKernelGGL(k_bin_count<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
+                           cnt, nbins, nblk);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(PS_SCAN, s);
+        e = launch_exclusive_scan(cnt, cnt_elems, scratch, s);
+    }
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(PS_BIN_FILL, s);
+        hipLaunchKernelGGL(k_bin_fill<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
+                           cnt, nbins, nblk, nbits);
+    }
+    return hipGetLastError();
+}
+
+static inline int bits_for(int nbins)
+{
+    int b = 0;
+    while ((1 << b) < nbins) ++b;
+    return b < 1 ? 1 : b;
+}
+
+
+// Stable sort of (key, value) pairs by the low `kbits` bits of the key, 8 bits per pass. The
+// pairs start in (ka, va); the sorted pairs end in (ka, va) if *swapped is false, else in
+// (kb, vb). rhist needs 256 * ceil(n / DIGS_BIN_ITEMS) words, scratch the scan's scratch.
+static inline hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+                                          int n, int kbits, uint32_t *rhist, uint32_t *scratch,
+                                          bool *swapped, hipStream_t s)
+{
+    *swapped = false;
+    const int nblk = (n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS;
+    for (int shift = 0; shift < kbits; shift += 8) {
+        RadixSrc src;
+        src.keys_in = *swapped ? kb : ka;
+        src.vals_in = *swapped ? vb : va;
+        src.keys_out = *swapped ? ka : kb;
+        src.vals_out = *swapped ? va : vb;
+        src.items = n;
+        src.shift = shift;
+        hipError_t e = launch_binning(src, 1, 256, nblk, 8, rhist, (size_t)256 * nblk, scratch, s);
+        if (e != hipSuccess) return e;
+        *swapped = !*swapped;
+    }
+    return hipSuccess;
 }

@@ -444,32 +444,6 @@ struct TileSrc {
     }
 };
 
-struct RadixSrc {
-    const uint32_t *keys_in, *vals_in;
-    uint32_t *keys_out, *vals_out;
-    int items;
-    int shift;
-    struct Item {
-        uint32_t k;
-        __device__ int nkeys() const { return 1; }
-        __device__ int key(int) const { return (int)k; }
-    };
-    __device__ Item load(int, int item) const
-    {
-        Item it;
-        it.k = (keys_in[item] >> shift) & 255u;
-        return it;
-    }
-    __device__ void prepare(int, int, Item &) const {}
-    __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
-    {
-        if (pos < (uint32_t)items) {
-            keys_out[pos] = keys_in[item];
-            vals_out[pos] = vals_in[item];
-        }
-    }
-};
-
 // ------------------------------------------------------------------------------------------
 // Workgroup -> (view, tile). The hardware hands consecutive workgroups of a launch to the 8 XCDs
 // in turn (b mod 8). When T is a multiple of 8, XCD x is given the views t = x (mod 8) one after
@@ -1348,39 +1322,6 @@ __global__ __launch_bounds__(256) void k_coef_grad(DevGrid g, const float *__res
 
 // ------------------------------------------------------------------------------------------
 // host orchestration
-template <class Src>
-static hipError_t launch_binning(const Src &src, int slices, int nbins, int nblk, int nbits,
-                                 uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
-                                 hipStream_t s)
-{
-    const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
-    {
-        ProfScope ps(PS_BIN_COUNT, s);
-        hipLaunchKernelGGL(k_bin_count<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
-                           cnt, nbins, nblk);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    {
-        ProfScope ps(PS_SCAN, s);
-        e = launch_exclusive_scan(cnt, cnt_elems, scratch, s);
-    }
-    if (e != hipSuccess) return e;
-    {
-        ProfScope ps(PS_BIN_FILL, s);
-        hipLaunchKernelGGL(k_bin_fill<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
-                           cnt, nbins, nblk, nbits);
-    }
-    return hipGetLastError();
-}
-
-static int bits_for(int nbins)
-{
-    int b = 0;
-    while ((1 << b) < nbins) ++b;
-    return b < 1 ? 1 : b;
-}
-
 template <int NR>
 static hipError_t setup_dispatch(const RenderArgs &a, hipStream_t s)
 {
