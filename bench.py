@@ -81,6 +81,82 @@ def cpu_baseline(p, params, batch_views, rows_every: int = 16):
                       "scales that to a whole view" % (rows_every, pj.size, dt)}
 
 
+def _time_ms(fn, reps: int):
+    """Average milliseconds per call of fn, HIP events on torch's current stream (the stream the
+    library launches on), after one untimed call."""
+    import torch
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def single_view_leg(dev):
+    """The single-projection forward path: 50k Gaussians, 256x256 at 1.6 mm, one view per call,
+    eagerly and as a plan replay (HIP graph)."""
+    import torch
+    from paper_2506_22280_amd import _lib, synth
+    p = synth.single_view(seed=0)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    t = dict(coef=d(p.coef), mu=d(p.mu), scale=d(p.scale), quat=d(p.quat), rho=d(p.rho))
+    ang, w = d(p.angles[:1]), d(p.w[:1])
+    ws = _lib.Workspace(dev)
+    proj = torch.empty((1, p.geom["nv"], p.geom["nu"]), device=dev)
+    eager = _time_ms(lambda: _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"],
+                                              t["quat"], t["rho"], ang, w, ws, proj=proj), 200)
+    grads = dict(g_mu=torch.empty((3, p.n), device=dev), g_scale=torch.empty((3, p.n), device=dev),
+                 g_quat=torch.empty((4, p.n), device=dev), g_rho=torch.empty((p.n,), device=dev),
+                 g_coef=torch.empty_like(t["coef"]), g_w=torch.empty((1, 3), device=dev))
+    plan = _lib.Plan(p.geom, p.grid, p.n, 1, dict(t, angles=ang, w=w, proj=proj, **grads))
+    graph = _time_ms(plan.fwd, 200)
+    tuning, _ = plan.tuning()
+    plan.close()
+    return {"ms_per_view_eager": round(eager, 4), "ms_per_view_graph": round(graph, 4),
+            "views_per_s_graph": round(1e3 / graph, 1),
+            "tuning": {k: tuning[k] for k in ("splat_waves", "persistent")}}
+
+
+def volume_leg(dev):
+    """The volume query at one time point: 500k-Gaussian phantom, rank-4 FFD at 5 mm, a 256^3
+    grid of 1 mm voxels: the displacement field (HBM-write-bound: 12 bytes per voxel) and phi."""
+    import torch
+    from paper_2506_22280_amd import _lib, synth
+    p = synth.large(seed=0)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    v = dict(nx=256, ny=256, nz=256, origin=[-127.5] * 3, spacing=[1.0] * 3)
+    coef, w = d(p.coef), d(p.w[1000])
+    mu, scale, quat, rho = d(p.mu), d(p.scale), d(p.quat), d(p.rho)
+    dvf = torch.empty((3, 256, 256, 256), device=dev)
+    import ctypes
+    G, V = _lib.make_grid(p.grid), _lib.make_vgrid(v)
+
+    def run_dvf():
+        _lib._check("digs_dvf_grid", _lib.load().digs_dvf_grid(
+            ctypes.byref(G), _lib._ptr(coef), _lib._ptr(w), ctypes.byref(V), _lib._ptr(dvf),
+            _lib._stream()))
+    dvf_ms = _time_ms(run_dvf, 20)
+    ws = _lib.Workspace(dev)
+    phi = _lib.phi_grid(p.grid, coef, mu, scale, quat, rho, w, v, ws)     # sizes the capacity
+    cap = int(ws.diagnostics()["instances"] * 1.25) + 4096
+    phi_ms = _time_ms(lambda: _lib.phi_grid(p.grid, coef, mu, scale, quat, rho, w, v, ws,
+                                            capacity=cap, out=phi, grow=False), 10)
+    dvf_bytes = 12 * 256 ** 3 + coef.numel() * 4
+    return {"dvf_ms": round(dvf_ms, 4),
+            "dvf_roofline": {"bound": "hbm", "achieved": round(dvf_bytes / dvf_ms / 1e6, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(dvf_bytes / dvf_ms / 1e6 / HBM_PEAK_GBS, 4)},
+            "phi_ms": round(phi_ms, 4), "phi_brick_pairs": int(ws.diagnostics()["instances"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +166,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event stage timing (plain timed loop only)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-view and volume-query legs")
     ap.add_argument("--no-warmstart", action="store_true",
                     help="skip the learned-warm-start leg (speedup vs the plain fit)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -262,6 +340,9 @@ def main():
             "in_footprint": int(in_fp / len(pairs) / B),
             "evaluated_fwd": int(sum(x[1] for x in pairs) / len(pairs) / B),
             "evaluated_bwd": int(sum(x[2] for x in pairs) / len(pairs) / B)}
+    if not args.no_extra:
+        out["single_view_50k"] = single_view_leg(dev)
+        out["volume_query_500k_256cubed"] = volume_leg(dev)
     if not args.no_warmstart:
         # "speedup vs plain": the learned warm start against the plain per-projection fit, time
         # to the same residual tolerance on views of unseen phantoms of the same family and size

@@ -777,13 +777,15 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
             // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu), r2 = (Guv2, Gvv, amp, -)
             const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8;
             const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
-            const float cA = -0.5f * r2.z;
             const float Cq = r1.w, CE = r0.z;
             const float s1 = fmaf(2.0f, du0, 1.0f);
-            const float qa = fmaf(Cq, du0, 0.0f), ea = CE * du0;
-            float S[12];
-#pragma unroll
-            for (int c = 0; c < 12; ++c) S[c] = 0.0f;
+            const float qa = Cq * du0, ea = CE * du0;
+            // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2, applied at the end)
+            // and b = a (1 + 2 ln2 x) (dL/dq likewise): a row accumulates a and b weighted by 1,
+            // c and c^2 (c = 0..7, the column inside the block, a compile-time constant); rows
+            // are folded with dv, dv^2, and the block's column offset du0 is applied at the end.
+            float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
+            float Q0 = 0.f, Q1 = 0.f, Q2 = 0.f, QV0 = 0.f, QV1 = 0.f, QW0 = 0.f;
             const float *gp = gpx + lby * GPX_STRIDE + lbx;
             for (int row = 0; row < 8; ++row) {
                 const float dv = dv0 + (float)row;
@@ -797,7 +799,6 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                 float ee = fmaf(du0, ea + BE, AE);
                 float de = fmaf(CE, s1, BE);
                 const float dde = 2.0f * CE;
-                float du = du0;
                 float e0 = 0.f, e1 = 0.f, e2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
@@ -805,37 +806,52 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                     const float rs = __builtin_amdgcn_rsqf(q);
                     const float r2s = rs * rs;
                     const float x = ee * r2s;
-                    const float gr = gval * rs * __builtin_amdgcn_exp2f(x);
-                    const float aE = gr * (cA * r2s);
-                    const float aq = aE * fmaf(2.0f * LN2, x, 1.0f);
-                    S[0] += gr;
-                    e0 += aE;
-                    const float tE = aE * du;
-                    e1 += tE;
-                    e2 = fmaf(tE, du, e2);
-                    q0 += aq;
-                    const float tq = aq * du;
-                    q1 += tq;
-                    q2 = fmaf(tq, du, q2);
-                    du += 1.0f;
+                    const float gr = (gval * rs) * __builtin_amdgcn_exp2f(x);
+                    const float a = gr * r2s;
+                    const float b = fmaf(a, (2.0f * LN2) * x, a);
+                    S0 += gr;
+                    e0 += a;
+                    q0 += b;
+                    if (c > 0) {
+                        e1 = fmaf((float)c, a, e1);
+                        e2 = fmaf((float)(c * c), a, e2);
+                        q1 = fmaf((float)c, b, q1);
+                        q2 = fmaf((float)(c * c), b, q2);
+                    }
                     q += dq;
                     dq += ddq;
                     ee += de;
                     de += dde;
                 }
                 const float dv2 = dv * dv;
-                S[1] += e2;
-                S[2] = fmaf(dv, e1, S[2]);
-                S[3] = fmaf(dv2, e0, S[3]);
-                S[4] += q2;
-                S[5] = fmaf(dv, q1, S[5]);
-                S[6] = fmaf(dv2, q0, S[6]);
-                S[7] += q1;
-                S[8] = fmaf(dv, q0, S[8]);
-                S[9] += q0;
-                S[10] += e1;
-                S[11] = fmaf(dv, e0, S[11]);
+                E0 += e0;
+                E1 += e1;
+                E2 += e2;
+                EV0 = fmaf(dv, e0, EV0);
+                EV1 = fmaf(dv, e1, EV1);
+                EW0 = fmaf(dv2, e0, EW0);
+                Q0 += q0;
+                Q1 += q1;
+                Q2 += q2;
+                QV0 = fmaf(dv, q0, QV0);
+                QV1 = fmaf(dv, q1, QV1);
+                QW0 = fmaf(dv2, q0, QW0);
             }
+            // the twelve moment sums (du = du0 + c), with the factor -amp/2
+            const float cA = -0.5f * r2.z;
+            float S[12];
+            S[0] = S0;
+            S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);    // sum dE du^2
+            S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
+            S[3] = cA * EW0;                                        // sum dE dv^2
+            S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
+            S[5] = cA * fmaf(du0, QV0, QV1);                        // sum dq du dv
+            S[6] = cA * QW0;                                        // sum dq dv^2
+            S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
+            S[8] = cA * QV0;                                        // sum dq dv
+            S[9] = cA * Q0;                                         // sum dq
+            S[10] = cA * fmaf(du0, E0, E1);                         // sum dE du
+            S[11] = cA * EV0;                                       // sum dE dv
             // add into the entry's slot, one block at a time (an entry appears once per block)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
