@@ -3,10 +3,10 @@
 // attenuation phi(x,t) = sum_n G_n(x | rho_n, mu'_n, Sigma'_n) of the warped Gaussians (Sec. 3.2,
 // Eq. 6-8).
 //
-// DVF: one workgroup per 64-voxel x 4-row segment of a z-slice. Along a row y and z are fixed,
-// so the y/z part of the tensor-product B-spline (and the sum over ranks) is applied once per
-// lattice column: L[i] = sum_r w_r sum_{m,n} B_m(y) B_n(z) d^r[i][.][.], staged in LDS; each
-// voxel then needs only its four x pieces. The kernel is bound by the 12 bytes it writes per voxel.
+// DVF: one workgroup per 64 x 16 voxel patch of a z-slice. The tensor-product B-spline is
+// applied one axis at a time through LDS (z pieces and rank weights per lattice column, then y
+// pieces per voxel row, then x pieces per voxel), so a voxel costs a few FMAs and the kernel is
+// bound by the 12 bytes it writes per voxel.
 //
 // phi: each Gaussian's cut-off box (Mahalanobis radius r_c per axis) is binned into 8x8x8-voxel
 // bricks by emitting (brick, Gaussian) pairs in Gaussian order and sorting them stably by brick;
@@ -60,73 +60,88 @@ __device__ __forceinline__ int lattice_floor(float q, int n)
 }
 
 // ------------------------------------------------------------------------------------------
+// One workgroup per 64 (x) x 16 (y) voxel patch of a z-slice. Stage 1 applies the z pieces (and
+// the rank weights) to every lattice column (i, j) the patch needs: P[j][i] = sum_r w_r sum_n
+// B_n(z) d^r[i][j][fz-1+n]; stage 2 the y pieces per voxel row: L[row][i] = sum_m B_m(y_row)
+// P[fy-1+m][i]; stage 3 the x pieces per voxel. All three stages use every thread.
 #define DVF_ROW 64
-#define DVF_ROWS 4
-#define DVF_LMAX 72
+#define DVF_ROWS 16
+#define DVF_LMAX 40
+#define DVF_JMAX 12
 
 __global__ __launch_bounds__(256) void k_dvf_rows(DevGrid g, const float *__restrict__ coef,
                                                   const float *__restrict__ w, DevVGrid v,
                                                   float *__restrict__ dvf)
 {
+    __shared__ float P[DVF_JMAX][DVF_LMAX][3];
     __shared__ float L[DVF_ROWS][DVF_LMAX][3];
     const int x0 = blockIdx.x * DVF_ROW, y0 = blockIdx.y * DVF_ROWS, z = blockIdx.z;
-    const int xl = min(x0 + DVF_ROW, v.nx) - 1;
+    const int xl = min(x0 + DVF_ROW, v.nx) - 1, yl = min(y0 + DVF_ROWS, v.ny) - 1;
     const int ilo = lattice_floor((v.ox + (float)x0 * v.sx - g.ox) / g.hx, g.nx) - 1;
     const int ihi = lattice_floor((v.ox + (float)xl * v.sx - g.ox) / g.hx, g.nx) + 2;
-    const int nL = min(ihi - ilo + 1, DVF_LMAX);
+    const int jlo = lattice_floor((v.oy + (float)y0 * v.sy - g.oy) / g.hy, g.ny) - 1;
+    const int jhi = lattice_floor((v.oy + (float)yl * v.sy - g.oy) / g.hy, g.ny) + 2;
+    const int nL = min(ihi - ilo + 1, DVF_LMAX), nJ = min(jhi - jlo + 1, DVF_JMAX);
     const float qz = (v.oz + (float)z * v.sz - g.oz) / g.hz;
     const int fz = lattice_floor(qz, g.nz);
     float Bz[4];
     bspline4(qz - floorf(qz), Bz);
     const size_t rank_stride = (size_t)g.nz * g.ny * g.nx * 3;
-    for (int e = threadIdx.x; e < DVF_ROWS * nL; e += 256) {
-        const int r = e / nL, i = e % nL, y = min(y0 + r, v.ny - 1);
+    // stage 1: z pieces and rank weights, one lattice column and component per thread-step
+    for (int e = threadIdx.x; e < nJ * nL * 3; e += 256) {
+        const int a = e % 3, i = (e / 3) % nL, j = e / (3 * nL);
+        const int ii = clampi(ilo + i, g.nx), jj = clampi(jlo + j, g.ny);
+        float acc = 0.0f;
+        for (int rk = 0; rk < g.R; ++rk) {
+            const float *base = coef + rk * rank_stride + ((size_t)jj * g.nx + ii) * 3 + a;
+            float t = 0.0f;
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+                t = fmaf(Bz[n], base[(size_t)clampi(fz - 1 + n, g.nz) * g.ny * g.nx * 3], t);
+            acc = fmaf(w[rk], t, acc);
+        }
+        P[j][i][a] = acc;
+    }
+    __syncthreads();
+    // stage 2: y pieces per voxel row
+    for (int e = threadIdx.x; e < DVF_ROWS * nL * 3; e += 256) {
+        const int a = e % 3, i = (e / 3) % nL, r = e / (3 * nL);
+        const int y = min(y0 + r, v.ny - 1);
         const float qy = (v.oy + (float)y * v.sy - g.oy) / g.hy;
         const int fy = lattice_floor(qy, g.ny);
         float By[4];
         bspline4(qy - floorf(qy), By);
-        const int ii = clampi(ilo + i, g.nx);
-        float acc[3] = {0.0f, 0.0f, 0.0f};
-        for (int rk = 0; rk < g.R; ++rk) {
-            const float wr = w[rk];
-            const float *base = coef + rk * rank_stride;
+        float acc = 0.0f;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const int kk = clampi(fz - 1 + n, g.nz);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int jj = clampi(fy - 1 + m, g.ny);
-                    const float wt = wr * By[m] * Bz[n];
-                    const float *d = base + (((size_t)kk * g.ny + jj) * g.nx + ii) * 3;
-                    acc[0] = fmaf(wt, d[0], acc[0]);
-                    acc[1] = fmaf(wt, d[1], acc[1]);
-                    acc[2] = fmaf(wt, d[2], acc[2]);
-                }
-            }
-        }
-        L[r][i][0] = acc[0];
-        L[r][i][1] = acc[1];
-        L[r][i][2] = acc[2];
+        for (int m = 0; m < 4; ++m) acc = fmaf(By[m], P[min(max(fy - 1 + m - jlo, 0), nJ - 1)][i][a], acc);
+        L[r][i][a] = acc;
     }
     __syncthreads();
-    const int r = threadIdx.x / DVF_ROW, x = x0 + (int)(threadIdx.x % DVF_ROW), y = y0 + r;
-    if (x >= v.nx || y >= v.ny) return;
+    // stage 3: x pieces; thread = column x, rows r, r + 4, r + 8, r + 12
+    const int x = x0 + (int)(threadIdx.x % DVF_ROW);
+    if (x >= v.nx) return;
     const float qx = (v.ox + (float)x * v.sx - g.ox) / g.hx;
     const int fx = lattice_floor(qx, g.nx);
     float Bx[4];
     bspline4(qx - floorf(qx), Bx);
-    float u[3] = {0.0f, 0.0f, 0.0f};
+    int li[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-        const int i = min(max(fx - 1 + l - ilo, 0), nL - 1);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) u[a] = fmaf(Bx[l], L[r][i][a], u[a]);
-    }
+    for (int l = 0; l < 4; ++l) li[l] = min(max(fx - 1 + l - ilo, 0), nL - 1);
     const size_t plane = (size_t)v.nz * v.ny * v.nx;
-    const size_t o = ((size_t)z * v.ny + y) * v.nx + x;
-    dvf[o] = u[0];
-    dvf[plane + o] = u[1];
-    dvf[2 * plane + o] = u[2];
+#pragma unroll
+    for (int k = 0; k < DVF_ROWS / 4; ++k) {
+        const int r = (int)(threadIdx.x / DVF_ROW) + 4 * k, y = y0 + r;
+        if (y >= v.ny) break;
+        float u[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) u[a] = fmaf(Bx[l], L[r][li[l]][a], u[a]);
+        const size_t o = ((size_t)z * v.ny + y) * v.nx + x;
+        dvf[o] = u[0];
+        dvf[plane + o] = u[1];
+        dvf[2 * plane + o] = u[2];
+    }
 }
 
 // Any voxel spacing: the full 64-point stencil per voxel.
@@ -159,8 +174,9 @@ extern "C" int digs_dvf_grid(const digs_grid *grid, const float *coef, const flo
     const DevGrid g = make_dev_grid(grid);
     const DevVGrid v = make_dev_vgrid(vg);
     hipStream_t s = (hipStream_t)stream;
-    // the row kernel's LDS holds the lattice columns of a 64-voxel segment
-    if ((double)(DVF_ROW - 1) * v.sx / g.hx + 5.0 <= (double)DVF_LMAX) {
+    // the patch kernel's LDS holds the lattice columns of a 64 x 16 voxel patch
+    if ((double)(DVF_ROW - 1) * v.sx / g.hx + 5.0 <= (double)DVF_LMAX &&
+        (double)(DVF_ROWS - 1) * v.sy / g.hy + 5.0 <= (double)DVF_JMAX) {
         const dim3 blocks((v.nx + DVF_ROW - 1) / DVF_ROW, (v.ny + DVF_ROWS - 1) / DVF_ROWS, v.nz);
         hipLaunchKernelGGL(k_dvf_rows, blocks, dim3(256), 0, s, g, coef, w, v, dvf);
     } else {
