@@ -89,23 +89,49 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
         }
     }
     __syncthreads();
+    // Emit: the step's (item, key) pairs are flattened in (lane, key) order and placed 64 at a time,
+    // so items with many keys do not leave the rest of the wave idle.
+    __shared__ int starts[BIN_WAVES][DIGS_WAVE];
+    __shared__ typename Src::Item items[BIN_WAVES][DIGS_WAVE];
     for (int step = 0; step < BIN_PER_WAVE / DIGS_WAVE; ++step) {
-        const int item = base + step * DIGS_WAVE + lane;
+        const int item0 = base + step * DIGS_WAVE;
+        const int item = item0 + lane;
         const bool valid = item < src.items;
         typename Src::Item it = src.load(slice, valid ? item : 0);
         if (valid) src.prepare(slice, item, it);
         const int nk = valid ? it.nkeys() : 0;
-        for (int k = 0;; ++k) {
-            const bool active = k < nk;
-            if (!__any(active)) break;
-            const unsigned key = active ? (unsigned)it.key(k) : 0u;
+        int incl = nk;
+#pragma unroll
+        for (int off = 1; off < DIGS_WAVE; off <<= 1) {
+            const int y = __shfl_up(incl, off, DIGS_WAVE);
+            if (lane >= off) incl += y;
+        }
+        const int total = __shfl(incl, DIGS_WAVE - 1, DIGS_WAVE);
+        starts[wave][lane] = incl - nk;
+        items[wave][lane] = it;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int c0 = 0; c0 < total; c0 += DIGS_WAVE) {
+            const int idx = c0 + lane;
+            const bool active = idx < total;
+            // owner: the last lane whose start is <= idx (it has at least one key)
+            int j = 0;
+#pragma unroll
+            for (int b = DIGS_WAVE / 2; b >= 1; b >>= 1)
+                if (starts[wave][j + b] <= idx) j += b;
+            const int k = idx - starts[wave][j];
+            const typename Src::Item o = items[wave][j];
+            const unsigned key = active ? (unsigned)o.key(k) : 0u;
             const unsigned long long peers = wave_match(key, active, nbits);
             uint32_t pos = 0;
             const int rank = __popcll(peers & lanemask_lt());
             if (active) pos = h[key] + (uint32_t)rank;
             if (active && rank == 0) h[key] = pos + (uint32_t)__popcll(peers);
-            if (active) src.emit(slice, item, it, k, pos);
+            if (active) src.emit(slice, item0 + j, o, k, pos);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

@@ -93,8 +93,16 @@ __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restri
     }
 }
 
+// element n of a 4-array without dynamic register indexing (selects, no scratch)
+template <class T>
+__device__ __forceinline__ T pick4(const T (&v)[4], int n)
+{
+    return n == 0 ? v[0] : (n == 1 ? v[1] : (n == 2 ? v[2] : v[3]));
+}
+
 // sum_{a,b} Q[3a+b] * d^2 u_a / dx_b dx_c for one rank (the term of dL/dmu through K(mu)),
-// accumulated into h[c].
+// accumulated into h[c]. The z and y loops stay rolled (registers); their per-index values are
+// selected.
 __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
                                                           const float *__restrict__ coef, int r,
                                                           const Stencil &s, const float Q[9],
@@ -103,9 +111,13 @@ __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
     const float *base = coef + (size_t)r * g.nz * g.ny * g.nx * 3;
 #pragma unroll 1
     for (int n = 0; n < 4; ++n) {
+        const int kk = pick4(s.kk, n);
+        const float Bz = pick4(s.Bz, n), dBz = pick4(s.dBz, n), d2Bz = pick4(s.d2Bz, n);
 #pragma unroll 1
         for (int m = 0; m < 4; ++m) {
-            const float *row = base + ((size_t)(s.kk[n] * g.ny + s.jj[m]) * g.nx) * 3;
+            const int jj = pick4(s.jj, m);
+            const float By = pick4(s.By, m), dBy = pick4(s.dBy, m), d2By = pick4(s.d2By, m);
+            const float *row = base + ((size_t)(kk * g.ny + jj) * g.nx) * 3;
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
                 const float *d = row + s.ii[l] * 3;
@@ -113,12 +125,12 @@ __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
                 float y[3];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) y[b] = Q[b] * d[0] + Q[3 + b] * d[1] + Q[6 + b] * d[2];
-                const float wxx = s.d2Bx[l] * s.By[m] * s.Bz[n];
-                const float wyy = s.Bx[l] * s.d2By[m] * s.Bz[n];
-                const float wzz = s.Bx[l] * s.By[m] * s.d2Bz[n];
-                const float wxy = s.dBx[l] * s.dBy[m] * s.Bz[n];
-                const float wxz = s.dBx[l] * s.By[m] * s.dBz[n];
-                const float wyz = s.Bx[l] * s.dBy[m] * s.dBz[n];
+                const float wxx = s.d2Bx[l] * By * Bz;
+                const float wyy = s.Bx[l] * d2By * Bz;
+                const float wzz = s.Bx[l] * By * d2Bz;
+                const float wxy = s.dBx[l] * dBy * Bz;
+                const float wxz = s.dBx[l] * By * dBz;
+                const float wyz = s.Bx[l] * dBy * dBz;
                 h[0] += wxx * y[0] + wxy * y[1] + wxz * y[2];
                 h[1] += wxy * y[0] + wyy * y[1] + wyz * y[2];
                 h[2] += wxz * y[0] + wyz * y[1] + wzz * y[2];

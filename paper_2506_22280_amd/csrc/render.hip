@@ -962,10 +962,25 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
         float S[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) S[c] = 0.0f;
-        const uint32_t base = goff[o];
-        for (int k = 0; k < cntk; ++k) {
-            const size_t p = (size_t)base + k;
-            if (p >= cap) break;
+        const size_t base = goff[o];
+        // the instances of (t, n) are contiguous; four are loaded at once (more loads in flight)
+        // and added in instance order
+        const int kend = (int)min((size_t)cntk, cap > base ? cap - base : (size_t)0);
+        int k = 0;
+        for (; k + 4 <= kend; k += 4) {
+            float4 v[12];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) v[j] = part[(base + k) * 3 + j];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 a = v[3 * j], b = v[3 * j + 1], c = v[3 * j + 2];
+                S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
+                S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
+                S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
+            }
+        }
+        for (; k < kend; ++k) {
+            const size_t p = base + k;
             const float4 a = part[p * 3 + 0], b = part[p * 3 + 1], c = part[p * 3 + 2];
             S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
             S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
@@ -1174,6 +1189,7 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     const float mu0[3] = {mu[i], mu[n + i], mu[2 * n + i]};
     Stencil st;
     make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
+#pragma unroll
     for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(grid, coef, r, st, Q[r], gmu);
     // R diag(s) -> s, R(q)
     const float s[3] = {scale[i], scale[n + i], scale[2 * n + i]};
