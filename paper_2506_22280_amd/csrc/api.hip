@@ -103,6 +103,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->diag = take(sizeof(DiagBlock));
     L->queue = take(8 * sizeof(uint32_t));
     L->uv = take(sizeof(float) * 12 * grid->R * N);
+    L->gsort = take(sizeof(float) * 11 * N);
     L->rec = take(sizeof(float) * DIGS_REC_FLOATS * TN);
     L->rect = take(sizeof(int) * 2 * TN);
     L->gcount = take(sizeof(uint32_t) * TN);
@@ -118,7 +119,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->rhist = take(sizeof(uint32_t) * 256 * (size_t)nblk_r);
     L->cell_start = take(sizeof(uint32_t) * ((size_t)L->ncells + 1));
     L->tnout = take(sizeof(float) * 22 * TN);
-    L->pos_of = take(sizeof(uint32_t) * N);
+    L->order = take(sizeof(uint32_t) * N);
     L->gq = take(sizeof(float) * L->gq_stride * N);
     L->total = off;
     return true;

@@ -9,6 +9,7 @@ struct WsLayout {
     size_t diag;       // DiagBlock
     size_t queue;      // [8] u32 work-queue counters of the persistent splats
     size_t uv;         // [3R + 9R][N] f32: per-rank u_r(mu), grad u_r(mu) at the canonical means
+    size_t gsort;      // [11][N] f32: mu, scale, quat, rho of the Gaussians in cell order
     size_t rec;        // [T][N][16] f32 projected records
     size_t rect;       // [T][N] int2 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
     size_t gcount;     // [T][N] u32 tiles per (t,n), scanned in place to instance offsets
@@ -21,7 +22,8 @@ struct WsLayout {
     size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
     size_t cell_start;                      // [ncells + 1] u32 first position of each cell
     size_t tnout;      // [22][T][N] f32 per-(t,n) adjoint results
-    size_t pos_of;     // [N] u32 position of Gaussian n in cell order
+    size_t order;      // [N] u32 the Gaussian at each position of cell order (per-Gaussian arrays
+                       //     of a call, records included, are laid out in cell order)
     size_t gq;         // [N][6 + 12R] f32 per-Gaussian coefficient-gradient sources, cell order
     size_t total;
     // derived sizes

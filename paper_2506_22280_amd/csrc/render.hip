@@ -86,15 +86,32 @@ static hipError_t fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s)
 }
 
 // ------------------------------------------------------------------------------------------
-// a1: FFD at the canonical means, uv = [U (R x 3) ; V (R x 9)] x N
+// a1: FFD at the canonical means, uv = [U (R x 3) ; V (R x 9)] x N, and the Gaussians' parameters
+// gs = [mu (3); scale (3); quat (4); rho] x N, both in cell order (entry i belongs to Gaussian
+// order[i])
 __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *__restrict__ coef,
                                                        int n, const float *__restrict__ mu,
-                                                       float *__restrict__ uv)
+                                                       const float *__restrict__ scale,
+                                                       const float *__restrict__ quat,
+                                                       const float *__restrict__ rho,
+                                                       const uint32_t *__restrict__ order,
+                                                       float *__restrict__ uv,
+                                                       float *__restrict__ gs)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const size_t src = order[i];
+    // the Gaussian's parameters, gathered once into cell order: mu (3), scale (3), quat (4), rho
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gs[(size_t)a * n + i] = mu[(size_t)a * n + src];
+        gs[(size_t)(3 + a) * n + i] = scale[(size_t)a * n + src];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gs[(size_t)(6 + a) * n + i] = quat[(size_t)a * n + src];
+    gs[(size_t)10 * n + i] = rho[src];
     Stencil st;
-    make_stencil(g, mu[i], mu[n + i], mu[2 * n + i], st, false);
+    make_stencil(g, mu[src], mu[n + src], mu[2 * n + src], st, false);
     float *U = uv, *V = uv + (size_t)3 * g.R * n;
     for (int r = 0; r < g.R; ++r) {
         float u[3], J[9];
@@ -277,10 +294,7 @@ __device__ __forceinline__ bool ellipse_meets_rect(float cx, float cy, float a00
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
-                                               const float *__restrict__ mu,
-                                               const float *__restrict__ scale,
-                                               const float *__restrict__ quat,
-                                               const float *__restrict__ rho,
+                                               const float *__restrict__ gs,
                                                const float *__restrict__ angles,
                                                const float *__restrict__ w,
                                                const float *__restrict__ uv, float cull,
@@ -290,22 +304,22 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
                                                DiagBlock *__restrict__ diag)
 {
     __shared__ unsigned long long wsum[4];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // position in cell order
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     float mu0[3], s[3], q[4], Rm[9], inv_s[3];
     float U[NR][3], V[NR][9];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        mu0[a] = mu[(size_t)a * n + ii];
-        s[a] = scale[(size_t)a * n + ii];
+        mu0[a] = gs[(size_t)a * n + ii];
+        s[a] = gs[(size_t)(3 + a) * n + ii];
         inv_s[a] = 1.0f / s[a];
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + ii];
+    for (int a = 0; a < 4; ++a) q[a] = gs[(size_t)(6 + a) * n + ii];
     const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     quat_to_rot(q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn, Rm);
-    const float rh = rho[ii];
+    const float rh = gs[(size_t)10 * n + ii];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
 #pragma unroll
@@ -936,10 +950,10 @@ __global__ void k_queue_reset(uint32_t *q)
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_tn_bwd(
-    DevGeom G, int n, int T, const float *__restrict__ mu, const float *__restrict__ scale,
-    const float *__restrict__ quat, const float *__restrict__ rho,
+    DevGeom G, int n, int T, const float *__restrict__ gs,
     const float *__restrict__ angles, const float *__restrict__ w, const float *__restrict__ uv,
-    const int2 *__restrict__ rect, const uint32_t *__restrict__ goff,
+    const int2 *__restrict__ rect,
+    const uint32_t *__restrict__ goff,
     const float4 *__restrict__ part, unsigned cap,
     float *__restrict__ tnout, float *__restrict__ gwpart, int nparts)
 {
@@ -989,15 +1003,15 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
         float mu0[3], s[3], inv_s[3], q[4], Rm[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            mu0[a] = mu[(size_t)a * n + ii];
-            s[a] = scale[(size_t)a * n + ii];
+            mu0[a] = gs[(size_t)a * n + ii];
+            s[a] = gs[(size_t)(3 + a) * n + ii];
             inv_s[a] = 1.0f / s[a];
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + ii];
+        for (int a = 0; a < 4; ++a) q[a] = gs[(size_t)(6 + a) * n + ii];
         const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
         quat_to_rot(q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn, Rm);
-        const float rh = rho[ii];
+        const float rh = gs[(size_t)10 * n + ii];
         float U[NR][3], V[NR][9], wt[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -1136,10 +1150,9 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_gauss_reduce(
-    DevGrid grid, int n, int T, const float *__restrict__ coef, const float *__restrict__ mu,
-    const float *__restrict__ scale, const float *__restrict__ quat,
+    DevGrid grid, int n, int T, const float *__restrict__ coef, const float *__restrict__ gpar,
     const float *__restrict__ w, const float *__restrict__ uv, const float *__restrict__ tnout,
-    const uint32_t *__restrict__ pos_of, float *__restrict__ g_mu, float *__restrict__ g_scale,
+    const uint32_t *__restrict__ order, float *__restrict__ g_mu, float *__restrict__ g_scale,
     float *__restrict__ g_quat, float *__restrict__ g_rho, float *__restrict__ gq, int gq_stride)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1186,16 +1199,17 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
             gmu[c] += V[c * (size_t)n] * P[r][0] + V[(3 + c) * (size_t)n] * P[r][1] +
                       V[(6 + c) * (size_t)n] * P[r][2];
         }
-    const float mu0[3] = {mu[i], mu[n + i], mu[2 * n + i]};
+    const size_t src = order[i];   // i is the position in cell order
+    const float mu0[3] = {gpar[i], gpar[(size_t)n + i], gpar[(size_t)2 * n + i]};
     Stencil st;
     make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
 #pragma unroll
     for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(grid, coef, r, st, Q[r], gmu);
     // R diag(s) -> s, R(q)
-    const float s[3] = {scale[i], scale[n + i], scale[2 * n + i]};
+    const float s[3] = {gpar[(size_t)3 * n + i], gpar[(size_t)4 * n + i], gpar[(size_t)5 * n + i]};
     float q[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) q[a] = quat[(size_t)a * n + i];
+    for (int a = 0; a < 4; ++a) q[a] = gpar[(size_t)(6 + a) * n + i];
     const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     const float qh[4] = {q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn};
     float Rm[9];
@@ -1212,16 +1226,14 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     const float dq = gqh[0] * qh[0] + gqh[1] * qh[1] + gqh[2] * qh[2] + gqh[3] * qh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        g_mu[(size_t)a * n + i] = gmu[a];
-        g_scale[(size_t)a * n + i] = gs[a];
+        g_mu[(size_t)a * n + src] = gmu[a];
+        g_scale[(size_t)a * n + src] = gs[a];
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) g_quat[(size_t)a * n + i] = (gqh[a] - dq * qh[a]) * qn;
-    g_rho[i] = grho;
+    for (int a = 0; a < 4; ++a) g_quat[(size_t)a * n + src] = (gqh[a] - dq * qh[a]) * qn;
+    g_rho[src] = grho;
     // sources of dL/dcoef in cell order: clamped cell, fraction, P_r, Q_r
-    const uint32_t slot = pos_of[i];
-    if (slot >= (uint32_t)n) return;
-    float *o = gq + (size_t)slot * gq_stride;
+    float *o = gq + (size_t)i * gq_stride;
     o[0] = __int_as_float(max(-2, min(st.fx, grid.nx + 1)));
     o[1] = __int_as_float(max(-2, min(st.fy, grid.ny + 1)));
     o[2] = __int_as_float(max(-2, min(st.fz, grid.nz + 1)));
@@ -1270,20 +1282,17 @@ __global__ void k_cell_keys(DevGrid g, int n, const float *__restrict__ mu,
 }
 
 // cell_start[k] = number of Gaussians whose cell key is below k (for every key 0..ncells);
-// pos_of[n] = position of Gaussian n in cell order
+// order[p] = the Gaussian at position p in cell order
 __global__ void k_cell_start(int n, int ncells, const uint32_t *__restrict__ keys,
                              const uint32_t *__restrict__ vals, uint32_t *__restrict__ cell_start,
-                             uint32_t *__restrict__ pos_of)
+                             uint32_t *__restrict__ order)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > n) return;
     const uint32_t hi = (p < n) ? min(keys[p], (uint32_t)ncells) : (uint32_t)ncells;
     const uint32_t lo = (p > 0) ? min(keys[p - 1], (uint32_t)ncells) + 1u : 0u;
     for (uint32_t k = lo; k <= hi; ++k) cell_start[k] = (uint32_t)p;
-    if (p < n) {
-        const uint32_t v = vals[p];
-        if (v < (uint32_t)n) pos_of[v] = (uint32_t)p;
-    }
+    if (p < n) order[p] = min(vals[p], (uint32_t)(n - 1));
 }
 
 // One wave per control point: for each (cz, cy) row of its candidate cells the Gaussians of
@@ -1359,10 +1368,44 @@ static hipError_t setup_dispatch(const RenderArgs &a, hipStream_t s)
 {
     const int n = a.n, T = a.T;
     dim3 grid((n + 255) / 256, (T + SETUP_TCHUNK - 1) / SETUP_TCHUNK);
-    hipLaunchKernelGGL(k_setup<NR>, grid, dim3(256), 0, s, a.geom, n, T, a.mu, a.scale, a.quat,
-                       a.rho, a.angles, a.w, WS(a, uv, const float *), a.cull,
+    hipLaunchKernelGGL(k_setup<NR>, grid, dim3(256), 0, s, a.geom, n, T,
+                       WS(a, gsort, const float *), a.angles, a.w, WS(a, uv, const float *), a.cull,
                        WS(a, rec, float4 *), WS(a, rect, int2 *), WS(a, gcount, uint32_t *),
                        WS(a, diag, DiagBlock *));
+    return hipGetLastError();
+}
+
+// Cell sort of the Gaussians by the lattice cell of their canonical mean (LSD radix, 8 bits per
+// pass): every per-Gaussian array of a call is laid out in this order, so that the records and
+// partials of Gaussians that are near each other in space (and hence on the detector) are near
+// each other in memory.
+static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
+{
+    hipError_t e;
+    const int n = a.n;
+    uint32_t *ka = WS(a, keys_a, uint32_t *), *va = WS(a, vals_a, uint32_t *);
+    uint32_t *kb = WS(a, keys_b, uint32_t *), *vb = WS(a, vals_b, uint32_t *);
+    hipLaunchKernelGGL(k_cell_keys, dim3((n + 255) / 256), dim3(256), 0, s, a.grid, n, a.mu, ka,
+                       va);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nblk_r = (n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS;
+    const int kbits = bits_for(a.L.ncells);
+    for (int shift = 0; shift < kbits; shift += 8) {
+        RadixSrc src;
+        src.keys_in = ka;
+        src.vals_in = va;
+        src.keys_out = kb;
+        src.vals_out = vb;
+        src.items = n;
+        src.shift = shift;
+        e = launch_binning(src, 1, 256, nblk_r, 8, WS(a, rhist, uint32_t *),
+                           (size_t)256 * nblk_r, WS(a, scratch, uint32_t *), s);
+        if (e != hipSuccess) return e;
+        uint32_t *t0 = ka; ka = kb; kb = t0;
+        t0 = va; va = vb; vb = t0;
+    }
+    hipLaunchKernelGGL(k_cell_start, dim3((n + 1 + 255) / 256), dim3(256), 0, s, n, a.L.ncells,
+                       ka, va, WS(a, cell_start, uint32_t *), WS(a, order, uint32_t *));
     return hipGetLastError();
 }
 
@@ -1374,10 +1417,12 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_diag_begin, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *),
                        (unsigned long long)a.L.cap, cnt + cnt_elems);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = cell_sort(a, s)) != hipSuccess) return e;
     {
         ProfScope ps(PS_FFD, s);
         hipLaunchKernelGGL(k_ffd_canonical, dim3((a.n + 255) / 256), dim3(256), 0, s, a.grid,
-                           a.coef, a.n, a.mu, WS(a, uv, float *));
+                           a.coef, a.n, a.mu, a.scale, a.quat, a.rho,
+                           WS(a, order, const uint32_t *), WS(a, uv, float *), WS(a, gsort, float *));
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
@@ -1507,17 +1552,18 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     hipError_t e;
     {
         ProfScope ps(PS_GAUSS_BWD, s);
-        hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, T), dim3(256), 0, s, a.geom, n, T, a.mu,
-                           a.scale, a.quat, a.rho, a.angles, a.w, WS(a, uv, const float *),
-                           WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
+        hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, T), dim3(256), 0, s, a.geom, n, T,
+                           WS(a, gsort, const float *), a.angles, a.w, WS(a, uv, const float *),
+                           WS(a, rect, const int2 *),
+                           WS(a, gcount, const uint32_t *),
                            WS(a, part, const float4 *),
                            (unsigned)a.L.cap, WS(a, tnout, float *), WS(a, gwpart, float *),
                            nparts);
         e = hipGetLastError();
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_gauss_reduce<NR>, dim3(nb), dim3(256), 0, s, a.grid, n, T,
-                               a.coef, a.mu, a.scale, a.quat, a.w, WS(a, uv, const float *),
-                               WS(a, tnout, const float *), WS(a, pos_of, const uint32_t *),
+                               a.coef, WS(a, gsort, const float *), a.w, WS(a, uv, const float *),
+                               WS(a, tnout, const float *), WS(a, order, const uint32_t *),
                                g_mu, g_scale, g_quat, g_rho, WS(a, gq, float *), a.L.gq_stride);
             e = hipGetLastError();
         }
@@ -1539,36 +1585,6 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
         e = hipGetLastError();
     }
     return e;
-}
-
-static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
-{
-    hipError_t e;
-    const int n = a.n;
-    uint32_t *ka = WS(a, keys_a, uint32_t *), *va = WS(a, vals_a, uint32_t *);
-    uint32_t *kb = WS(a, keys_b, uint32_t *), *vb = WS(a, vals_b, uint32_t *);
-    hipLaunchKernelGGL(k_cell_keys, dim3((n + 255) / 256), dim3(256), 0, s, a.grid, n, a.mu, ka,
-                       va);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nblk_r = (n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS;
-    const int kbits = bits_for(a.L.ncells);
-    for (int shift = 0; shift < kbits; shift += 8) {
-        RadixSrc src;
-        src.keys_in = ka;
-        src.vals_in = va;
-        src.keys_out = kb;
-        src.vals_out = vb;
-        src.items = n;
-        src.shift = shift;
-        e = launch_binning(src, 1, 256, nblk_r, 8, WS(a, rhist, uint32_t *),
-                           (size_t)256 * nblk_r, WS(a, scratch, uint32_t *), s);
-        if (e != hipSuccess) return e;
-        uint32_t *t0 = ka; ka = kb; kb = t0;
-        t0 = va; va = vb; vb = t0;
-    }
-    hipLaunchKernelGGL(k_cell_start, dim3((n + 1 + 255) / 256), dim3(256), 0, s, n, a.L.ncells,
-                       ka, va, WS(a, cell_start, uint32_t *), WS(a, pos_of, uint32_t *));
-    return hipGetLastError();
 }
 
 hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
@@ -1602,9 +1618,6 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    // cell sort of the Gaussians (LSD radix, 8 bits per pass); its binning stages are timed
-    // under their own names
-    if ((e = cell_sort(a, s)) != hipSuccess) return e;
     switch (a.grid.R) {
     case 1: return backward_dispatch<1>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
     case 2: return backward_dispatch<2>(a, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
