@@ -1,5 +1,6 @@
 // api.hip -- the extern "C" entry points of libdigs (declared in include/digs.h).
 #include <math.h>
+#include <algorithm>
 #include <string.h>
 
 #include "kernels.h"
@@ -82,6 +83,15 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->ntiles = G.ntiles;
     L->ncells = (grid->nx + 4) * (grid->ny + 4) * (grid->nz + 4);
     L->gq_stride = 6 + 12 * grid->R;
+    // the per-Gaussian adjoint runs one thread per (Gaussian, chunk of views): enough chunks for
+    // about 64k threads, a function of n and T alone so that the sums' order is fixed
+    {
+        const int Tp = T > 0 ? T : 1;
+        const int want = (int)std::min<int64_t>(Tp, std::max<int64_t>(1, (65536 + (int64_t)n - 1) /
+                                                                           std::max(n, 1)));
+        L->tpc = (Tp + want - 1) / want;
+        L->tchunks = (Tp + L->tpc - 1) / L->tpc;
+    }
     int64_t cap = (tuning && tuning->capacity > 0) ? tuning->capacity : default_capacity(n, T);
     if (cap > 0xFFFFFF00ll) cap = 0xFFFFFF00ll;   // list positions are 32-bit
     L->cap = (size_t)cap;
@@ -118,7 +128,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->vals_b = take(sizeof(uint32_t) * N);
     L->rhist = take(sizeof(uint32_t) * 256 * (size_t)nblk_r);
     L->cell_start = take(sizeof(uint32_t) * ((size_t)L->ncells + 1));
-    L->tnout = take(sizeof(float) * 22 * TN);
+    L->tacc = take(sizeof(float) * (13 + 12 * (size_t)grid->R) * L->tchunks * N);
     L->order = take(sizeof(uint32_t) * N);
     L->gq = take(sizeof(float) * L->gq_stride * N);
     L->total = off;

@@ -21,13 +21,14 @@ struct WsLayout {
     size_t keys_a, vals_a, keys_b, vals_b;  // [N] u32 cell sort ping-pong
     size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
     size_t cell_start;                      // [ncells + 1] u32 first position of each cell
-    size_t tnout;      // [22][T][N] f32 per-(t,n) adjoint results
+    size_t tacc;       // [13 + 12R][tchunks][N] f32 per-Gaussian adjoint sums over chunks of views
     size_t order;      // [N] u32 the Gaussian at each position of cell order (per-Gaussian arrays
                        //     of a call, records included, are laid out in cell order)
     size_t gq;         // [N][6 + 12R] f32 per-Gaussian coefficient-gradient sources, cell order
     size_t total;
     // derived sizes
     int n, T, R, nblk, ntiles, ncells, gq_stride;
+    int tpc, tchunks;  // views per chunk of the per-Gaussian adjoint, and the number of chunks
     size_t cap;
     size_t scratch_elems;
 };

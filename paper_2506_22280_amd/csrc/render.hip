@@ -6,17 +6,17 @@
 //                    the projected record of the Gaussian's exact line integral (see below),
 //                    its cut-off bounding box and the detector tiles it touches
 //   k_bin_count/fill per projection, lists of Gaussians per 16x16 tile (bin.h)
-//   k_splat_fwd      one workgroup per (projection, tile), one wave per 8x8 pixel block, one
-//                    lane per pixel; records are read with scalar loads; every pixel is written
-//                    once (no atomics)
+//   k_splat_fwd      one workgroup per (projection, tile), one wave per 8x8 pixel block; lane =
+//                    (Gaussian slot, column), eight Gaussians at a time, rows by forward
+//                    differences; every pixel is written once (no atomics)
 // Backward:
-//   k_splat_bwd      one lane per (Gaussian, tile) instance looping over the tile's 256 pixels,
-//                    accumulating 12 moment sums; written per instance (no atomics)
-//   k_tn_bwd         per (t, n): sums the instance partials and runs the set-up and warp adjoints;
-//                    per-wave partial sums of dL/dw
-//   k_gauss_reduce   per Gaussian, over the call's projections in order: reduces to the canonical
-//                    parameters (with the second-derivative term) and emits the sources of
-//                    dL/dcoef
+//   k_splat_bwd      one lane per (list entry, 8x8 block) pair, looping over the block's 64 pixels
+//                    and accumulating 12 moment sums; one partial per instance (no atomics)
+//   k_tn_bwd         per Gaussian and chunk of views: sums the instance partials, runs the set-up
+//                    and warp adjoints per view and folds them into per-Gaussian sums; per-wave
+//                    partial sums of dL/dw
+//   k_gauss_reduce   per Gaussian, over the chunks in order: reduces to the canonical parameters
+//                    (with the second-derivative term) and emits the sources of dL/dcoef
 //   k_cell_*         stable radix sort of the Gaussians by lattice cell
 //   k_coef_grad      each control point gathers from the Gaussians of its 4x4x4 cells
 //
@@ -128,6 +128,10 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
 struct ViewTrig {
     float ct, st;
 };
+
+// record part 2 of an idle Gaussian slot: with parts 0 and 1 zero, q = 1, E = 0 and
+// log2|amp| = -inf, so the slot adds exactly zero
+__device__ __forceinline__ float4 idle_rec2() { return make_float4(0.0f, 0.0f, -INFINITY, 0.0f); }
 
 struct SetupFwd {
     // deformation
@@ -257,41 +261,6 @@ __device__ __forceinline__ bool footprint_box(const DevGeom &G, const SetupFwd &
     return true;
 }
 
-// Does the ellipse (p - c)^T A (p - c) <= 1 meet the rectangle [x0, x1] x [y0, y1]? Exact for
-// the continuous rectangle (so never false for a rectangle holding a pixel centre inside the
-// ellipse): the quadratic is convex, so if its centre lies outside the rectangle its minimum over
-// the rectangle lies on an edge, where it is a 1-D quadratic minimised at a clamped vertex.
-// A = 0 (a footprint that is not an ellipse) meets everything.
-__device__ __forceinline__ bool ellipse_meets_rect(float cx, float cy, float a00, float a01,
-                                                   float a11, float x0, float x1, float y0,
-                                                   float y1)
-{
-    if (!(a00 > 0.0f) || (cx >= x0 && cx <= x1 && cy >= y0 && cy <= y1)) return true;
-    const float ia00 = 1.0f / a00, ia11 = 1.0f / a11;
-    float best;
-    {
-        const float dy = y0 - cy;
-        const float dx = fminf(fmaxf(cx - a01 * dy * ia00, x0), x1) - cx;
-        best = fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy));
-    }
-    {
-        const float dy = y1 - cy;
-        const float dx = fminf(fmaxf(cx - a01 * dy * ia00, x0), x1) - cx;
-        best = fminf(best, fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy)));
-    }
-    {
-        const float dx = x0 - cx;
-        const float dy = fminf(fmaxf(cy - a01 * dx * ia11, y0), y1) - cy;
-        best = fminf(best, fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy)));
-    }
-    {
-        const float dx = x1 - cx;
-        const float dy = fminf(fmaxf(cy - a01 * dx * ia11, y0), y1) - cy;
-        best = fminf(best, fmaf(a00 * dx, dx, fmaf(2.0f * a01 * dx, dy, a11 * dy * dy)));
-    }
-    return best <= 1.0f + 1e-5f;
-}
-
 template <int NR>
 __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
                                                const float *__restrict__ gs,
@@ -372,13 +341,15 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
             if (ok) {
                 rec[o * 4 + 0] = make_float4(f.us, f.vs, C2_EXP2 * f.Huu, 2.0f * C2_EXP2 * f.Huv);
                 rec[o * 4 + 1] = make_float4(C2_EXP2 * f.Hvv, 2.0f * f.gu, 2.0f * f.gv, f.Guu);
-                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, f.Gvv, f.amp, fp.a00);
+                // the splats take amp as log2|amp| (-inf for 0) with its sign on Gvv (>= +0)
+                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, copysignf(f.Gvv, f.amp),
+                                             log2f(fabsf(f.amp)), fp.a00);
                 rec[o * 4 + 3] = make_float4(fp.a01, fp.a11, fp.cx, fp.cy);
-            } else {   // keep the record finite
+            } else {   // an idle record: adds zero wherever it is evaluated
                 const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 rec[o * 4 + 0] = z;
                 rec[o * 4 + 1] = z;
-                rec[o * 4 + 2] = z;
+                rec[o * 4 + 2] = idle_rec2();
                 rec[o * 4 + 3] = z;
             }
             rect[o] = rr;
@@ -413,9 +384,36 @@ struct TileSrc {
     int tiles_x;
     struct Item {
         int tx0, ty0, w, cnt, tiles_x;
-        float cx, cy, a00, a01, a11;
+        float inv_w;
+        // the cut-off ellipse by horizontal chords (prepare): at y = cy + dy the chord is
+        // x in cx - s dy -+ sqrt((1 - D dy^2) ia), |dy| <= ry; its leftmost point is at dy = ryl
+        // and its rightmost at dy = -ryl (1 carries a slack of 1e-5)
+        float cx, cy, s, ia, D, ry, ryl;
+        bool ell;
         __device__ int nkeys() const { return cnt; }
-        __device__ int key(int k) const { return (ty0 + k / w) * tiles_x + tx0 + k % w; }
+        // k-th tile of the rectangle in row-major order (k / w in float: exact for k < 2^21)
+        __device__ void tile(int k, int &tx, int &ty) const
+        {
+            const int q = (int)(((float)k + 0.5f) * inv_w);
+            tx = tx0 + (k - __mul24(q, w));
+            ty = ty0 + q;
+        }
+        __device__ int key(int k) const
+        {
+            int tx, ty;
+            tile(k, tx, ty);
+            return __mul24(ty, tiles_x) + tx;
+        }
+        // x-extent [L, R] of the ellipse within the strip y in [ya, yb]; false if it misses
+        __device__ bool strip(float ya, float yb, float &L, float &R) const
+        {
+            const float lo = fmaxf(ya - cy, -ry), hi = fminf(yb - cy, ry);
+            if (!(lo <= hi)) return false;
+            const float dl = fminf(fmaxf(ryl, lo), hi), dr = fminf(fmaxf(-ryl, lo), hi);
+            L = cx - s * dl - __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dl, dl, 1.00001f)) * ia);
+            R = cx - s * dr + __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dr, dr, 1.00001f)) * ia);
+            return true;
+        }
     };
     __device__ Item load(int t, int item) const
     {
@@ -427,32 +425,48 @@ struct TileSrc {
         const int ty1 = r.y >> 16;
         it.w = tx1 - it.tx0 + 1;
         it.cnt = (tx1 >= it.tx0 && ty1 >= it.ty0) ? it.w * (ty1 - it.ty0 + 1) : 0;
+        it.inv_w = it.cnt > 0 ? 1.0f / (float)it.w : 0.0f;
         it.tiles_x = tiles_x;
-        it.cx = it.cy = it.a00 = it.a01 = it.a11 = 0.0f;
+        it.cx = it.cy = it.s = it.ia = it.D = it.ry = it.ryl = 0.0f;
+        it.ell = false;
         return it;
     }
     __device__ void prepare(int t, int item, Item &it) const
     {
         const float4 *r = rec + ((size_t)t * items + item) * 4;
         const float4 c = r[2], d = r[3];
-        it.a00 = c.w;
-        it.a01 = d.x;
-        it.a11 = d.y;
+        const float a00 = c.w, a01 = d.x, a11 = d.y;
         it.cx = d.z;
         it.cy = d.w;
+        const float D = a11 - a01 * (a01 / a00);
+        it.ell = a00 > 0.0f && D > 0.0f && isfinite(D);
+        if (it.ell) {
+            it.s = a01 / a00;
+            it.ia = 1.0f / a00;
+            it.D = D;
+            it.ry = sqrtf(1.00001f / D);
+            it.ryl = a01 / sqrtf(a00 * a11) * it.ry;
+        }
     }
+    // the entry: the Gaussian's index and the mask of the 8x8 blocks that its ellipse meets (a
+    // footprint that is not an ellipse meets all four)
     __device__ void emit(int, int item, const Item &it, int k, uint32_t pos) const
     {
         if (pos >= cap) return;
-        const int key = it.key(k);
-        const float x0 = (float)((key % tiles_x) * DIGS_TILE), y0 = (float)((key / tiles_x) * DIGS_TILE);
-        uint32_t m = 0;
+        int tx, ty;
+        it.tile(k, tx, ty);
+        uint32_t m = 0xFu;
+        if (it.ell) {
+            m = 0u;
+            const float x0 = (float)(tx * DIGS_TILE), y0 = (float)(ty * DIGS_TILE);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const float bx = x0 + (float)((b & 1) * 8), by = y0 + (float)((b >> 1) * 8);
-            if (ellipse_meets_rect(it.cx, it.cy, it.a00, it.a01, it.a11, bx, bx + 7.0f, by,
-                                   by + 7.0f))
-                m |= 1u << b;
+            for (int h = 0; h < 2; ++h) {
+                float L, R;
+                if (it.strip(y0 + (float)(8 * h), y0 + (float)(8 * h + 7), L, R)) {
+                    if (x0 <= R && x0 + 7.0f >= L) m |= 1u << (2 * h);
+                    if (x0 + 8.0f <= R && x0 + 15.0f >= L) m |= 2u << (2 * h);
+                }
+            }
         }
         list[pos] = (uint32_t)item | (m << LIST_BLOCK_SHIFT);
     }
@@ -478,19 +492,97 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 // ------------------------------------------------------------------------------------------
 // a5: forward splat. One workgroup per (view, tile), one wave per 8x8 pixel block (with
 // WAVES == 1 a single wave takes the tile's four blocks in turn). The wave walks the tile's list
-// in chunks of 64 entries, keeps the Gaussians whose footprint meets its block (bit of the list
-// entry; compaction in LDS) and evaluates them 8 at a time: lane = (Gaussian slot, column), each
-// lane running down the 8 rows of its column with forward differences of the two quadratic forms
-// (two adds each per row). The records of the next 8 Gaussians are loaded while the current 8
-// are evaluated. The per-lane row sums are reduced over the 8 slots at the end in a fixed order,
-// and every pixel is written once.
+// in chunks of 64 entries and appends the Gaussians whose footprint meets its block (bit of the
+// list entry) to a queue in LDS; it evaluates the queue 8 Gaussians at a time and carries the
+// remainder (fewer than 8) over to the next chunk, so that only the block's last group has idle
+// lanes. lane = (Gaussian slot, column); each lane runs down the 8 rows of its column with forward
+// differences of the two quadratic forms (two adds each per row). The records of the next 8
+// Gaussians are loaded while the current 8 are evaluated. The amplitude enters as log2|amp| added
+// to the exponent when the 8 Gaussians are all positive (one multiply less per pixel), as a
+// factor otherwise. The per-lane row sums are reduced over the 8 slots at the end in a fixed
+// order, and every pixel is written once.
+#define FWD_QUEUE (DIGS_WAVE + 8)
+
+// Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8, or the block's last group)
+// into the lane's 8 row sums.
+__device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
+                                                const uint32_t *__restrict__ qid, int ns,
+                                                int gslot, float fi, float fby, float *acc)
+{
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 n0 = zero4, n1 = zero4, n2 = idle_rec2();
+    if (gslot < ns) {
+        const size_t gg = qid[gslot];
+        n0 = rt[gg * 4 + 0];
+        n1 = rt[gg * 4 + 1];
+        n2 = rt[gg * 4 + 2];
+    }
+    for (int j = 0; j < ns; j += 8) {
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        const int sn = j + 8 + gslot;
+        n0 = zero4; n1 = zero4; n2 = idle_rec2();
+        if (sn < ns) {
+            const size_t gg = qid[sn];
+            n0 = rt[gg * 4 + 0];
+            n1 = rt[gg * 4 + 1];
+            n2 = rt[gg * 4 + 2];
+        }
+        // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
+        // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
+        const float du = fi - r0.x, dv0 = fby - r0.y;
+        const float Aq = fmaf(du, fmaf(r1.w, du, r1.y), 1.0f);
+        const float Bq = fmaf(r2.x, du, r1.z), Cq = fabsf(r2.y);
+        const float AE = r0.z * du * du, BE = r0.w * du, CE = r1.x;
+        const float s1 = fmaf(2.0f, dv0, 1.0f);
+        float q = fmaf(dv0, fmaf(Cq, dv0, Bq), Aq);
+        float dq = fmaf(Cq, s1, Bq);
+        const float ddq = 2.0f * Cq;
+        float e = fmaf(dv0, fmaf(CE, dv0, BE), AE);
+        float de = fmaf(CE, s1, BE);
+        const float dde = 2.0f * CE;
+        const float la = r2.z;
+        if (__ballot(signbit(r2.y)) == 0ull) {
+            // all eight amplitudes positive: amp rs 2^x = rs 2^(x + log2 amp)
+#pragma unroll
+            for (int row = 0; row < 8; ++row) {
+                const float rs = __builtin_amdgcn_rsqf(q);
+                const float x = fmaf(e, rs * rs, la);
+                acc[row] = fmaf(rs, __builtin_amdgcn_exp2f(x), acc[row]);
+                q += dq;
+                dq += ddq;
+                e += de;
+                de += dde;
+            }
+        } else {
+            const float amp = copysignf(exp2f(la), r2.y);
+#pragma unroll
+            for (int row = 0; row < 8; ++row) {
+                const float rs = __builtin_amdgcn_rsqf(q);
+                const float x = e * (rs * rs);
+                acc[row] = fmaf(amp * rs, __builtin_amdgcn_exp2f(x), acc[row]);
+                q += dq;
+                dq += ddq;
+                e += de;
+                de += dde;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int WAVES>
 __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ list,
                                                const uint32_t *__restrict__ cnt, int nblk,
                                                unsigned cap, float *__restrict__ proj,
-                                               uint32_t (*ids)[DIGS_WAVE])
+                                               uint32_t (*ids)[FWD_QUEUE])
 {
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
@@ -500,7 +592,7 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
     const float4 *rt = rec + (size_t)t * n * 4;
-    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t *qid = ids[wave];
     for (int pass = 0; pass < 4 / WAVES; ++pass) {
         const int blkid = (WAVES == 4) ? wave : pass;
         const int bx = tx * DIGS_TILE + (blkid & 1) * 8, by = ty * DIGS_TILE + (blkid >> 1) * 8;
@@ -508,6 +600,7 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
         float acc[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) acc[r] = 0.0f;
+        int pend = 0;   // queued Gaussians carried over from earlier chunks (fewer than 8)
         for (uint32_t c0 = begin; c0 < end; c0 += DIGS_WAVE) {
             const uint32_t k = c0 + lane;
             uint32_t g = 0;
@@ -518,55 +611,23 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
                 hit = g < (uint32_t)n && ((e >> (LIST_BLOCK_SHIFT + blkid)) & 1u);
             }
             const unsigned long long m = __ballot(hit);
-            const int ns = __popcll(m);
-            if (hit) ids[wave][__popcll(m & lanemask_lt())] = g;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            float4 n0 = zero4, n1 = zero4, n2 = zero4;
-            if (gslot < ns) {
-                const size_t gg = ids[wave][gslot];
-                n0 = rt[gg * 4 + 0];
-                n1 = rt[gg * 4 + 1];
-                n2 = rt[gg * 4 + 2];
+            if (hit) qid[pend + __popcll(m & lanemask_lt())] = g;
+            const int ns = pend + __popcll(m);
+            const int full = ns & ~7;
+            wave_sync_lds();
+            if (full > 0) {
+                splat_fwd_group(rt, qid, full, gslot, fi, fby, acc);
+                // move the remainder to the front of the queue
+                const int left = ns - full;
+                const uint32_t keep = (lane < left) ? qid[full + lane] : 0u;
+                wave_sync_lds();
+                if (lane < left) qid[lane] = keep;
+                wave_sync_lds();
             }
-            for (int j = 0; j < ns; j += 8) {
-                const float4 r0 = n0, r1 = n1, r2 = n2;
-                const int sn = j + 8 + gslot;
-                n0 = zero4; n1 = zero4; n2 = zero4;
-                if (sn < ns) {
-                    const size_t gg = ids[wave][sn];
-                    n0 = rt[gg * 4 + 0];
-                    n1 = rt[gg * 4 + 1];
-                    n2 = rt[gg * 4 + 2];
-                }
-                // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu), r2 = (Guv2, Gvv, amp, -)
-                const float du = fi - r0.x, dv0 = fby - r0.y;
-                const float Aq = fmaf(du, fmaf(r1.w, du, r1.y), 1.0f);
-                const float Bq = fmaf(r2.x, du, r1.z), Cq = r2.y;
-                const float AE = r0.z * du * du, BE = r0.w * du, CE = r1.x;
-                const float s1 = fmaf(2.0f, dv0, 1.0f);
-                float q = fmaf(dv0, fmaf(Cq, dv0, Bq), Aq);
-                float dq = fmaf(Cq, s1, Bq);
-                const float ddq = 2.0f * Cq;
-                float e = fmaf(dv0, fmaf(CE, dv0, BE), AE);
-                float de = fmaf(CE, s1, BE);
-                const float dde = 2.0f * CE;
-                const float amp = r2.z;
-#pragma unroll
-                for (int row = 0; row < 8; ++row) {
-                    const float rs = __builtin_amdgcn_rsqf(q);
-                    const float x = e * (rs * rs);
-                    acc[row] = fmaf(amp * rs, __builtin_amdgcn_exp2f(x), acc[row]);
-                    q += dq;
-                    dq += ddq;
-                    e += de;
-                    de += dde;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            pend = ns - full;
         }
+        if (pend > 0) splat_fwd_group(rt, qid, pend, gslot, fi, fby, acc);
+        wave_sync_lds();
         // sum over the 8 Gaussian slots (lane bits 3..5) in a fixed order
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -612,7 +673,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
                                                           int nblk, unsigned cap,
                                                           float *__restrict__ proj)
 {
-    __shared__ uint32_t ids[WAVES][DIGS_WAVE];
+    __shared__ uint32_t ids[WAVES][FWD_QUEUE];
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
     splat_fwd_tile<WAVES>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
@@ -625,7 +686,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
     const uint32_t *__restrict__ cnt, int nblk, unsigned cap, float *__restrict__ proj,
     uint32_t *__restrict__ queue)
 {
-    __shared__ uint32_t ids[WAVES][DIGS_WAVE];
+    __shared__ uint32_t ids[WAVES][FWD_QUEUE];
     __shared__ int s_item;
     const int home = blockIdx.x & 7;
     for (;;) {
@@ -672,7 +733,7 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
         eval_f += 64;
         const float du = (float)px - r[0], dv = (float)py - r[1];
         const float q = fmaf(du, fmaf(r[7], du, fmaf(r[8], dv, r[5])),
-                             fmaf(dv, fmaf(r[9], dv, r[6]), 1.0f));
+                             fmaf(dv, fmaf(fabsf(r[9]), dv, r[6]), 1.0f));
         const float e = fmaf(du, fmaf(r[2], du, r[3] * dv), r[4] * dv * dv);
         const bool inside = on_det && q > 0.0f && e >= c2r2 * q;
         in_fp += __popcll(__ballot(inside));
@@ -704,23 +765,167 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // ------------------------------------------------------------------------------------------
 // a6: backward splat. One workgroup per (projection, tile); the tile's dL/dI (times |e|) is staged
 // in LDS (row stride 18 keeps the four 8x8 blocks in distinct banks). Each wave takes chunks of
-// 64 list entries, compacts the (entry, 8x8 block) pairs whose footprint ellipse meets the block into
-// a pair list (block-major), and gives each lane one pair: the lane runs over the block's 64
+// 64 list entries and appends the (entry, 8x8 block) pairs whose footprint ellipse meets the block
+// (block-major) to a pair queue in LDS. The queue is evaluated 64 pairs at a time, one pair per
+// lane, and the remainder is carried over to the next chunk, so that lanes idle only when a chunk
+// must be finished early (below) and at the end of the tile. A lane runs over its block's 64
 // pixels with forward differences along each row and accumulates twelve moment sums, which are
-// added into the entry's LDS slot in block order (fixed order, no atomics) and written as the
-// instance's partial, at the instance's slot in Gaussian-major order (so that the per-Gaussian
-// reduction reads each Gaussian's partials contiguously):
+// added into the entry's LDS slot in block order (fixed order, no atomics). Entry slots belong to
+// two chunks in turn; once the pairs of a chunk are all evaluated (by the end of the next chunk's
+// step, with a partial group if no full one forms), its entries are written as the instances'
+// partials, at each instance's slot in Gaussian-major order (so that the per-Gaussian reduction
+// reads each Gaussian's partials contiguously):
 //  0 S_amp = sum g r 2^x      (dL/damp)
 //  1 S_Euu, 2 S_Euv, 3 S_Evv  sum A_E du^2, du dv, dv^2   (A_E = dL/dE, E natural)
 //  4 S_quu, 5 S_quv, 6 S_qvv  sum A_q du^2, du dv, dv^2   (A_q = dL/dq)
 //  7 S_qu, 8 S_qv, 9 S_q      sum A_q du, dv, 1
 //  10 S_Eu, 11 S_Ev           sum A_E du, dv
 #define GPX_STRIDE 18
+#define BWD_QUEUE (5 * DIGS_WAVE)   // carried (< 64) + one chunk's pairs (<= 256)
 struct BwdShared {
     float gpx[DIGS_TILE * GPX_STRIDE];
-    uint32_t pairs[4][4 * DIGS_WAVE];
-    float accS[4][DIGS_WAVE][13];
+    uint32_t pairs[4][BWD_QUEUE];          // (entry slot << 2) | block
+    uint32_t gid[4][2 * DIGS_WAVE];        // Gaussian of each entry slot
+    float accS[4][2 * DIGS_WAVE][13];      // moment sums of each entry slot
 };
+
+// Evaluates queued pairs [j0, j0 + cnt) of the wave (cnt <= 64), one per lane, and adds their
+// moment sums into the entries' slots.
+__device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
+                                                const uint32_t *__restrict__ pq,
+                                                const uint32_t *__restrict__ gid,
+                                                float (*accS)[13], const float *__restrict__ gpx,
+                                                int j0, int cnt, int tx0, int ty0)
+{
+    // products are not contracted into sums here: each product feeds several sums, and a
+    // contraction would compute it twice
+#pragma clang fp contract(off)
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int lane = lane_id();
+    const bool active = lane < cnt;
+    const uint32_t pr = active ? pq[j0 + lane] : 0u;
+    const int slot = (int)(pr >> 2), blk = (int)(pr & 3u);
+    float4 r0 = zero4, r1 = zero4, r2 = zero4;
+    if (active) {
+        const size_t ge = gid[slot];
+        r0 = rt[ge * 4 + 0];
+        r1 = rt[ge * 4 + 1];
+        r2 = rt[ge * 4 + 2];
+    }
+    // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
+    // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
+    const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8;
+    const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
+    const float Cq = r1.w, CE = r0.z, Gvv = fabsf(r2.y);
+    const float s1 = fmaf(2.0f, du0, 1.0f);
+    const float qa = Cq * du0, ea = CE * du0;
+    // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2, applied at the end), a row
+    // accumulates a and a x weighted by 1, c and c^2 (c = 0..7, the column inside the block, a
+    // compile-time constant); rows are folded with dv, dv^2, and the block's column offset du0 is
+    // applied at the end. dL/dq (up to the same factor) is b = a (1 + 2 ln2 x): its moments are
+    // those of a plus 2 ln2 times those of a x.
+    float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
+    float X0 = 0.f, X1 = 0.f, X2 = 0.f, XV0 = 0.f, XV1 = 0.f, XW0 = 0.f;
+    const float *gp = gpx + lby * GPX_STRIDE + lbx;
+    for (int row = 0; row < 8; ++row) {
+        const float dv = dv0 + (float)row;
+        // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
+        const float Bq = fmaf(r2.x, dv, r1.y);
+        const float Aq = fmaf(dv, fmaf(Gvv, dv, r1.z), 1.0f);
+        const float BE = r0.w * dv, AE = r1.x * dv * dv;
+        float q = fmaf(du0, qa + Bq, Aq);
+        float dq = fmaf(Cq, s1, Bq);
+        const float ddq = 2.0f * Cq;
+        float ee = fmaf(du0, ea + BE, AE);
+        float de = fmaf(CE, s1, BE);
+        const float dde = 2.0f * CE;
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float gval = gp[row * GPX_STRIDE + c];
+            const float rs = __builtin_amdgcn_rsqf(q);
+            const float r2s = rs * rs;
+            const float x = ee * r2s;
+            const float gr = (gval * rs) * __builtin_amdgcn_exp2f(x);
+            const float a = gr * r2s;
+            const float ax = a * x;
+            S0 += gr;
+            e0 += a;
+            x0 += ax;
+            if (c > 0) {
+                e1 = fmaf((float)c, a, e1);
+                e2 = fmaf((float)(c * c), a, e2);
+                x1 = fmaf((float)c, ax, x1);
+                x2 = fmaf((float)(c * c), ax, x2);
+            }
+            q += dq;
+            dq += ddq;
+            ee += de;
+            de += dde;
+        }
+        const float dv2 = dv * dv;
+        E0 += e0;
+        E1 += e1;
+        E2 += e2;
+        EV0 = fmaf(dv, e0, EV0);
+        EV1 = fmaf(dv, e1, EV1);
+        EW0 = fmaf(dv2, e0, EW0);
+        X0 += x0;
+        X1 += x1;
+        X2 += x2;
+        XV0 = fmaf(dv, x0, XV0);
+        XV1 = fmaf(dv, x1, XV1);
+        XW0 = fmaf(dv2, x0, XW0);
+    }
+    const float k2 = 2.0f * LN2;
+    const float Q0 = fmaf(k2, X0, E0), Q1 = fmaf(k2, X1, E1), Q2 = fmaf(k2, X2, E2);
+    const float QV0 = fmaf(k2, XV0, EV0), QV1 = fmaf(k2, XV1, EV1), QW0 = fmaf(k2, XW0, EW0);
+    // the twelve moment sums (du = du0 + c), with the factor -amp/2
+    const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
+    float S[12];
+    S[0] = S0;
+    S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);    // sum dE du^2
+    S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
+    S[3] = cA * EW0;                                        // sum dE dv^2
+    S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
+    S[5] = cA * fmaf(du0, QV0, QV1);                        // sum dq du dv
+    S[6] = cA * QW0;                                        // sum dq dv^2
+    S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
+    S[8] = cA * QV0;                                        // sum dq dv
+    S[9] = cA * Q0;                                         // sum dq
+    S[10] = cA * fmaf(du0, E0, E1);                         // sum dE du
+    S[11] = cA * EV0;                                       // sum dE dv
+    // add into the entry's slot, one block at a time (an entry has at most one pair per block)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if (active && blk == b) {
+            float *dst = accS[slot];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) dst[c] += S[c];
+        }
+        wave_sync_lds();
+    }
+}
+
+// Writes the partial of the entry in slot `slot` (Gaussian g of view t, this tile).
+__device__ __forceinline__ void splat_bwd_write(int n, int t, int tx, int ty, uint32_t g,
+                                                const float *acc, unsigned cap,
+                                                const int2 *__restrict__ rect,
+                                                const uint32_t *__restrict__ goff,
+                                                float4 *__restrict__ part)
+{
+    // instance slot of (t, g, this tile): the Gaussian's instances are contiguous, in row-major
+    // order over its tile rectangle
+    const size_t o = (size_t)t * n + g;
+    const int2 rr = rect[o];
+    const int rtx0 = rr.x & 0xffff, rtx1 = rr.x >> 16, rty0 = rr.y & 0xffff;
+    const size_t slot = (size_t)goff[o] + (size_t)((ty - rty0) * (rtx1 - rtx0 + 1) + (tx - rtx0));
+    if (slot < cap) {
+        part[slot * 3 + 0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        part[slot * 3 + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        part[slot * 3 + 2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
+    }
+}
 
 __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
@@ -732,8 +937,6 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                                                float4 *__restrict__ part, BwdShared &sh)
 {
     float *gpx = sh.gpx;
-    uint32_t(*pairs)[4 * DIGS_WAVE] = sh.pairs;
-    float(*accS)[DIGS_WAVE][13] = sh.accS;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
     {
@@ -754,148 +957,58 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
     const float4 *rt = rec + (size_t)t * n * 4;
-    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int tx0 = tx * DIGS_TILE, ty0 = ty * DIGS_TILE;
-    float *acc = &accS[wave][lane][0];
-    for (uint32_t c0 = begin + wave * DIGS_WAVE; c0 < end; c0 += 4 * DIGS_WAVE) {
+    uint32_t *pq = sh.pairs[wave];
+    uint32_t *gid = sh.gid[wave];
+    float(*accS)[13] = sh.accS[wave];
+    int pend = 0;              // queued pairs carried over (all of the previous chunk), < 64
+    int it = 0;
+    bool prev_valid = false;   // the previous chunk's entry of this lane
+    uint32_t prev_g = 0;
+    for (uint32_t c0 = begin + wave * DIGS_WAVE; c0 < end; c0 += 4 * DIGS_WAVE, ++it) {
+        const int ring = (it & 1) * DIGS_WAVE;
         const uint32_t k = c0 + lane;
         bool valid = k < end;
         const uint32_t ent = valid ? list[k] : 0u;
         const uint32_t g = ent & LIST_INDEX_MASK;
         valid = valid && g < (uint32_t)n;
+        gid[ring + lane] = g;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = 0.0f;
-        int np = 0;
+        for (int c = 0; c < 12; ++c) accS[ring + lane][c] = 0.0f;
+        int np = pend;
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
             const bool hit = valid && ((ent >> (LIST_BLOCK_SHIFT + blk)) & 1u);
             const unsigned long long m = __ballot(hit);
-            if (hit) pairs[wave][np + __popcll(m & lanemask_lt())] = ((uint32_t)lane << 2) | blk;
+            if (hit) pq[np + __popcll(m & lanemask_lt())] = ((uint32_t)(ring + lane) << 2) | blk;
             np += __popcll(m);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int j = 0; j < np; j += DIGS_WAVE) {
-            const int pidx = j + lane;
-            const bool active = pidx < np;
-            const uint32_t pr = active ? pairs[wave][pidx] : 0u;
-            const int e = (int)(pr >> 2), blk = (int)(pr & 3u);
-            const uint32_t ge = (uint32_t)__shfl((int)g, e, 64);
-            float4 r0 = zero4, r1 = zero4, r2 = zero4;
-            if (active) {
-                r0 = rt[(size_t)ge * 4 + 0];
-                r1 = rt[(size_t)ge * 4 + 1];
-                r2 = rt[(size_t)ge * 4 + 2];
-            }
-            // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu), r2 = (Guv2, Gvv, amp, -)
-            const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8;
-            const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
-            const float Cq = r1.w, CE = r0.z;
-            const float s1 = fmaf(2.0f, du0, 1.0f);
-            const float qa = Cq * du0, ea = CE * du0;
-            // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2, applied at the end)
-            // and b = a (1 + 2 ln2 x) (dL/dq likewise): a row accumulates a and b weighted by 1,
-            // c and c^2 (c = 0..7, the column inside the block, a compile-time constant); rows
-            // are folded with dv, dv^2, and the block's column offset du0 is applied at the end.
-            float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
-            float Q0 = 0.f, Q1 = 0.f, Q2 = 0.f, QV0 = 0.f, QV1 = 0.f, QW0 = 0.f;
-            const float *gp = gpx + lby * GPX_STRIDE + lbx;
-            for (int row = 0; row < 8; ++row) {
-                const float dv = dv0 + (float)row;
-                // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
-                const float Bq = fmaf(r2.x, dv, r1.y);
-                const float Aq = fmaf(dv, fmaf(r2.y, dv, r1.z), 1.0f);
-                const float BE = r0.w * dv, AE = r1.x * dv * dv;
-                float q = fmaf(du0, qa + Bq, Aq);
-                float dq = fmaf(Cq, s1, Bq);
-                const float ddq = 2.0f * Cq;
-                float ee = fmaf(du0, ea + BE, AE);
-                float de = fmaf(CE, s1, BE);
-                const float dde = 2.0f * CE;
-                float e0 = 0.f, e1 = 0.f, e2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const float gval = gp[row * GPX_STRIDE + c];
-                    const float rs = __builtin_amdgcn_rsqf(q);
-                    const float r2s = rs * rs;
-                    const float x = ee * r2s;
-                    const float gr = (gval * rs) * __builtin_amdgcn_exp2f(x);
-                    const float a = gr * r2s;
-                    const float b = fmaf(a, (2.0f * LN2) * x, a);
-                    S0 += gr;
-                    e0 += a;
-                    q0 += b;
-                    if (c > 0) {
-                        e1 = fmaf((float)c, a, e1);
-                        e2 = fmaf((float)(c * c), a, e2);
-                        q1 = fmaf((float)c, b, q1);
-                        q2 = fmaf((float)(c * c), b, q2);
-                    }
-                    q += dq;
-                    dq += ddq;
-                    ee += de;
-                    de += dde;
-                }
-                const float dv2 = dv * dv;
-                E0 += e0;
-                E1 += e1;
-                E2 += e2;
-                EV0 = fmaf(dv, e0, EV0);
-                EV1 = fmaf(dv, e1, EV1);
-                EW0 = fmaf(dv2, e0, EW0);
-                Q0 += q0;
-                Q1 += q1;
-                Q2 += q2;
-                QV0 = fmaf(dv, q0, QV0);
-                QV1 = fmaf(dv, q1, QV1);
-                QW0 = fmaf(dv2, q0, QW0);
-            }
-            // the twelve moment sums (du = du0 + c), with the factor -amp/2
-            const float cA = -0.5f * r2.z;
-            float S[12];
-            S[0] = S0;
-            S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);    // sum dE du^2
-            S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
-            S[3] = cA * EW0;                                        // sum dE dv^2
-            S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
-            S[5] = cA * fmaf(du0, QV0, QV1);                        // sum dq du dv
-            S[6] = cA * QW0;                                        // sum dq dv^2
-            S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
-            S[8] = cA * QV0;                                        // sum dq dv
-            S[9] = cA * Q0;                                         // sum dq
-            S[10] = cA * fmaf(du0, E0, E1);                         // sum dE du
-            S[11] = cA * EV0;                                       // sum dE dv
-            // add into the entry's slot, one block at a time (an entry appears once per block)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (active && blk == b) {
-                    float *dst = &accS[wave][e][0];
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) dst[c] += S[c];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+        wave_sync_lds();
+        // full groups; if pairs of the previous chunk are queued and no full group forms, they
+        // are evaluated now in a partial group (with everything queued) to finish that chunk
+        int done = np & ~(DIGS_WAVE - 1);
+        if (done == 0 && pend > 0) done = np;
+        for (int j = 0; j < done; j += DIGS_WAVE)
+            splat_bwd_group(rt, pq, gid, accS, gpx, j, min(DIGS_WAVE, done - j), tx0, ty0);
+        if (it > 0 && prev_valid)
+            splat_bwd_write(n, t, tx, ty, prev_g, accS[(ring ^ DIGS_WAVE) + lane], cap, rect, goff,
+                            part);
+        const int left = np - done;
+        if (done > 0 && left > 0) {
+            const uint32_t keep = (lane < left) ? pq[done + lane] : 0u;
+            wave_sync_lds();
+            if (lane < left) pq[lane] = keep;
         }
-        if (valid) {
-            // instance slot of (t, g, this tile): the Gaussian's instances are contiguous, in
-            // row-major order over its tile rectangle
-            const size_t o = (size_t)t * n + g;
-            const int2 rr = rect[o];
-            const int rtx0 = rr.x & 0xffff, rtx1 = rr.x >> 16, rty0 = rr.y & 0xffff;
-            const size_t slot =
-                (size_t)goff[o] + (size_t)((ty - rty0) * (rtx1 - rtx0 + 1) + (tx - rtx0));
-            if (slot < cap) {
-                part[slot * 3 + 0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-                part[slot * 3 + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-                part[slot * 3 + 2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        wave_sync_lds();
+        pend = left;
+        prev_valid = valid;
+        prev_g = g;
     }
+    if (pend > 0) splat_bwd_group(rt, pq, gid, accS, gpx, 0, pend, tx0, ty0);
+    if (it > 0 && prev_valid)
+        splat_bwd_write(n, t, tx, ty, prev_g, accS[((it - 1) & 1) * DIGS_WAVE + lane], cap, rect,
+                        goff, part);
+    wave_sync_lds();
 }
 
 __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
@@ -940,218 +1053,265 @@ __global__ void k_queue_reset(uint32_t *q)
 }
 
 // ------------------------------------------------------------------------------------------
-// a7: adjoint of the set-up and of the warp. k_tn_bwd runs one thread per (t, n): it sums the
-// instance partials of (t, n), recomputes the set-up, and back-propagates the record gradients to
-// dL/dmu', dL/dK, dL/d(R diag(s)) and dL/drho, which it stores per (t, n); it also forms the
-// per-(t, n) terms of dL/dw[t][r] and reduces them per wave in a fixed order. k_gauss_reduce then
-// runs one thread per Gaussian over the call's projections (fixed order), adds the term through
-// K(mu) (second derivatives of the B-spline), and finishes the chain to the canonical parameters.
-#define TN_FIELDS 22   // gmu' (3), gK (9), gRS (9), grho (1)
+// a7: adjoint of the set-up and of the warp. k_tn_bwd runs one thread per Gaussian and a chunk
+// of the call's views: for each view it sums the instance partials of (t, n), recomputes the
+// set-up, back-propagates the record gradients to dL/dmu', dL/dK, dL/d(R diag(s)) and dL/drho, and
+// folds them into per-Gaussian sums over the chunk's views (in view order) together with the
+// w-weighted sums that the B-spline term needs; it also forms the per-(t, n) terms of dL/dw[t][r]
+// and reduces them per wave in a fixed order. k_gauss_reduce then adds the chunks (fixed order),
+// adds the term through K(mu) (second derivatives of the B-spline), and finishes the chain to the
+// canonical parameters.
+#define TN_FIELDS 22   // per view: gmu' (3), gK (9), gRS (9), grho (1)
+// per Gaussian and chunk: sum gmu' (3), sum gRS (9), sum grho (1), then per rank r
+// P_r = sum_t w[t][r] gmu' (3) and Q_r = sum_t w[t][r] gK (9)
+#define TACC_FIELDS(R) (13 + 12 * (R))
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_tn_bwd(
-    DevGeom G, int n, int T, const float *__restrict__ gs,
+    DevGeom G, int n, int T, int tpc, const float *__restrict__ gs,
     const float *__restrict__ angles, const float *__restrict__ w, const float *__restrict__ uv,
     const int2 *__restrict__ rect,
     const uint32_t *__restrict__ goff,
     const float4 *__restrict__ part, unsigned cap,
-    float *__restrict__ tnout, float *__restrict__ gwpart, int nparts)
+    float *__restrict__ tacc, float *__restrict__ gwpart, int nparts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = blockIdx.y;
+    const int chunk = blockIdx.y, nch = gridDim.y;
+    const int t0 = chunk * tpc, t1 = min(T, t0 + tpc);
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     const int lane = lane_id(), wave = threadIdx.x / DIGS_WAVE;
-    const size_t o = (size_t)t * n + ii;
-    const int2 rr = rect[o];
-    const int tx0 = rr.x & 0xffff, tx1 = rr.x >> 16, ty0 = rr.y & 0xffff, ty1 = rr.y >> 16;
-    const int cntk = (valid && tx1 >= tx0 && ty1 >= ty0) ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
-    float out[TN_FIELDS];
+    // the Gaussian's canonical parameters and B-spline fields, once for all views
+    float mu0[3], s[3], inv_s[3], q[4], Rm[9];
 #pragma unroll
-    for (int c = 0; c < TN_FIELDS; ++c) out[c] = 0.0f;
-    float gwc[NR];
+    for (int a = 0; a < 3; ++a) {
+        mu0[a] = gs[(size_t)a * n + ii];
+        s[a] = gs[(size_t)(3 + a) * n + ii];
+        inv_s[a] = 1.0f / s[a];
+    }
 #pragma unroll
-    for (int r = 0; r < NR; ++r) gwc[r] = 0.0f;
-    if (cntk > 0) {
-        float S[12];
+    for (int a = 0; a < 4; ++a) q[a] = gs[(size_t)(6 + a) * n + ii];
+    const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    quat_to_rot(q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn, Rm);
+    const float rh = gs[(size_t)10 * n + ii];
+    float U[NR][3], V[NR][9];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) S[c] = 0.0f;
-        const size_t base = goff[o];
-        // the instances of (t, n) are contiguous; four are loaded at once (more loads in flight)
-        // and added in instance order
-        const int kend = (int)min((size_t)cntk, cap > base ? cap - base : (size_t)0);
-        int k = 0;
-        for (; k + 4 <= kend; k += 4) {
-            float4 v[12];
+    for (int r = 0; r < NR; ++r) {
 #pragma unroll
-            for (int j = 0; j < 12; ++j) v[j] = part[(base + k) * 3 + j];
+        for (int a = 0; a < 3; ++a) U[r][a] = uv[((size_t)r * 3 + a) * n + ii];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float4 a = v[3 * j], b = v[3 * j + 1], c = v[3 * j + 2];
+        for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
+    }
+    float gsum[3] = {0.f, 0.f, 0.f}, gRS[9], grho = 0.0f, P[NR][3], Q[NR][9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gRS[k] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P[r][a] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Q[r][k] = 0.0f;
+    }
+    for (int t = t0; t < t1; ++t) {
+        const size_t o = (size_t)t * n + ii;
+        const int2 rr = rect[o];
+        const int tx0 = rr.x & 0xffff, tx1 = rr.x >> 16, ty0 = rr.y & 0xffff, ty1 = rr.y >> 16;
+        const int cntk =
+            (valid && tx1 >= tx0 && ty1 >= ty0) ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
+        float gwc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gwc[r] = 0.0f;
+        if (cntk > 0) {
+            float S[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) S[c] = 0.0f;
+            const size_t base = goff[o];
+            // the instances of (t, n) are contiguous; four are loaded at once (more loads in
+            // flight) and added in instance order
+            const int kend = (int)min((size_t)cntk, cap > base ? cap - base : (size_t)0);
+            int k = 0;
+            for (; k + 4 <= kend; k += 4) {
+                float4 v[12];
+#pragma unroll
+                for (int j = 0; j < 12; ++j) v[j] = part[(base + k) * 3 + j];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 a = v[3 * j], b = v[3 * j + 1], c = v[3 * j + 2];
+                    S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
+                    S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
+                    S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
+                }
+            }
+            for (; k < kend; ++k) {
+                const size_t p = base + k;
+                const float4 a = part[p * 3 + 0], b = part[p * 3 + 1], c = part[p * 3 + 2];
                 S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
                 S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
                 S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
             }
-        }
-        for (; k < kend; ++k) {
-            const size_t p = base + k;
-            const float4 a = part[p * 3 + 0], b = part[p * 3 + 1], c = part[p * 3 + 2];
-            S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
-            S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
-            S[8] += c.x; S[9] += c.y; S[10] += c.z; S[11] += c.w;
-        }
-        float mu0[3], s[3], inv_s[3], q[4], Rm[9];
+            float wt[NR];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            mu0[a] = gs[(size_t)a * n + ii];
-            s[a] = gs[(size_t)(3 + a) * n + ii];
-            inv_s[a] = 1.0f / s[a];
-        }
+            for (int r = 0; r < NR; ++r) wt[r] = w[(size_t)t * NR + r];
+            ViewTrig vt;
+            sincosf(angles[t], &vt.st, &vt.ct);
+            SetupFwd f;
+            setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
+            float out[TN_FIELDS];
+            // record gradients from the moment sums
+            const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
+            const float gGuu = S[4], gGuv = 2.0f * S[5], gGvv = S[6];
+            const float ggu = 2.0f * S[7], ggv = 2.0f * S[8];
+            const float gamp = S[0];
+            const float gus = -2.0f * (f.Huu * S[10] + f.Huv * S[11] + f.gu * S[9] + f.Guu * S[7] +
+                                       f.Guv * S[8]);
+            const float gvs = -2.0f * (f.Huv * S[10] + f.Hvv * S[11] + f.gv * S[9] + f.Guv * S[7] +
+                                       f.Gvv * S[8]);
+            // reverse of the record formulas
+            const float sic = sqrtf(f.ic);
+            const float grho_t = gamp * SQRT_2PI * f.beta * sic;
+            float gbeta = gamp * rh * SQRT_2PI * sic;
+            float gc = -0.5f * gamp * f.amp * f.ic;
+            const float Duu = dot3(f.Du, f.Du), Duv = dot3(f.Du, f.Dv), Dvv = dot3(f.Dv, f.Dv);
+            float gkap = (gGuu * Duu + gGuv * Duv + gGvv * Dvv) * f.ic;
+            gc -= (gGuu * f.Guu + gGuv * f.Guv + gGvv * f.Gvv) * f.ic;
+            float gDu[3], gDv[3], gmw[3], gDup[3], gDvp[3];
+            const float kic = f.kap * f.ic;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) q[a] = gs[(size_t)(6 + a) * n + ii];
-        const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        quat_to_rot(q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn, Rm);
-        const float rh = gs[(size_t)10 * n + ii];
-        float U[NR][3], V[NR][9], wt[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            wt[r] = w[(size_t)t * NR + r];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) U[r][a] = uv[((size_t)r * 3 + a) * n + ii];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
-        }
-        ViewTrig vt;
-        sincosf(angles[t], &vt.st, &vt.ct);
-        SetupFwd f;
-        setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
-        // record gradients from the moment sums
-        const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
-        const float gGuu = S[4], gGuv = 2.0f * S[5], gGvv = S[6];
-        const float ggu = 2.0f * S[7], ggv = 2.0f * S[8];
-        const float gamp = S[0];
-        const float gus = -2.0f * (f.Huu * S[10] + f.Huv * S[11] + f.gu * S[9] + f.Guu * S[7] +
-                                   f.Guv * S[8]);
-        const float gvs = -2.0f * (f.Huv * S[10] + f.Hvv * S[11] + f.gv * S[9] + f.Guv * S[7] +
-                                   f.Gvv * S[8]);
-        // reverse of the record formulas
-        const float sic = sqrtf(f.ic);
-        const float grho = gamp * SQRT_2PI * f.beta * sic;
-        float gbeta = gamp * rh * SQRT_2PI * sic;
-        float gc = -0.5f * gamp * f.amp * f.ic;
-        const float Duu = dot3(f.Du, f.Du), Duv = dot3(f.Du, f.Dv), Dvv = dot3(f.Dv, f.Dv);
-        float gkap = (gGuu * Duu + gGuv * Duv + gGvv * Dvv) * f.ic;
-        gc -= (gGuu * f.Guu + gGuv * f.Guv + gGvv * f.Gvv) * f.ic;
-        float gDu[3], gDv[3], gmw[3], gDup[3], gDvp[3];
-        const float kic = f.kap * f.ic;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            gDu[a] = kic * (2.0f * gGuu * f.Du[a] + gGuv * f.Dv[a]);
-            gDv[a] = kic * (2.0f * gGvv * f.Dv[a] + gGuv * f.Du[a]);
-        }
-        gbeta -= ggu * f.pa + ggv * f.pb;
-        float gpa = -ggu * f.beta, gpb = -ggv * f.beta;
-        gkap += gHuu * dot3(f.Dup, f.Dup) + gHuv * dot3(f.Dup, f.Dvp) + gHvv * dot3(f.Dvp, f.Dvp);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            gDup[a] = f.kap * (2.0f * gHuu * f.Dup[a] + gHuv * f.Dvp[a]);
-            gDvp[a] = f.kap * (2.0f * gHvv * f.Dvp[a] + gHuv * f.Dup[a]);
-        }
-        gbeta += 2.0f * f.beta * gkap;
-        gpa -= dot3(gDup, f.mw);
-        gpb -= dot3(gDvp, f.mw);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            gDu[a] += gDup[a];
-            gDv[a] += gDvp[a];
-            gmw[a] = -f.pa * gDup[a] - f.pb * gDvp[a];
-        }
-        const float gdu = gpa * f.ic, gdv = gpb * f.ic;
-        gc -= (gpa * f.pa + gpb * f.pb) * f.ic;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            gmw[a] += gdu * f.Du[a] + gdv * f.Dv[a] + 2.0f * gc * f.mw[a];
-            gDu[a] += gdu * f.mw[a];
-            gDv[a] += gdv * f.mw[a];
-        }
-        float galpha = gbeta / G.sdd;
-        const float ia = 1.0f / f.alpha;
-        const float kuf = G.sdd * ia / G.pitch_u, kvf = G.sdd * ia / G.pitch_v;
-        const float gxu = -gus * kuf, gxv = -gvs * kvf;
-        galpha += gus * kuf * f.xu * ia + gvs * kvf * f.xv * ia;
-        // mw = W m, Du = pu W e_u, Dv = pv W e_v
-        const float eu[3] = {-vt.st, vt.ct, 0.0f};
-        float gW[9], gm[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                gW[3 * a + b] = gmw[a] * f.m[b] + G.pitch_u * gDu[a] * eu[b] +
-                                (b == 2 ? G.pitch_v * gDv[a] : 0.0f);
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            gm[b] = f.W[b] * gmw[0] + f.W[3 + b] * gmw[1] + f.W[6 + b] * gmw[2];
-        float gmup[3] = {-gm[0], -gm[1], -gm[2]};
-        gmup[0] += -vt.ct * galpha + vt.st * gxu;
-        gmup[1] += -vt.st * galpha - vt.ct * gxu;
-        gmup[2] += -gxv;
-        // W = M^-1: dL/dM = -W^T gW W^T
-        float T1[9], gM[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                T1[3 * a + b] = f.W[a] * gW[b] + f.W[3 + a] * gW[3 + b] + f.W[6 + a] * gW[6 + b];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                gM[3 * a + b] = -(T1[3 * a] * f.W[3 * b] + T1[3 * a + 1] * f.W[3 * b + 1] +
-                                  T1[3 * a + 2] * f.W[3 * b + 2]);
-        // M = K (R S): dL/dK = gM (RS)^T, dL/d(RS) = K^T gM
-        float RS[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) RS[3 * a + b] = Rm[3 * a + b] * s[b];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) out[a] = gmup[a];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                out[3 + 3 * a + b] = gM[3 * a] * RS[3 * b] + gM[3 * a + 1] * RS[3 * b + 1] +
-                                     gM[3 * a + 2] * RS[3 * b + 2];
-                out[12 + 3 * a + b] = f.K[a] * gM[b] + f.K[3 + a] * gM[3 + b] +
-                                      f.K[6 + a] * gM[6 + b];
+            for (int a = 0; a < 3; ++a) {
+                gDu[a] = kic * (2.0f * gGuu * f.Du[a] + gGuv * f.Dv[a]);
+                gDv[a] = kic * (2.0f * gGvv * f.Dv[a] + gGuv * f.Du[a]);
             }
-        out[21] = grho;
-        // per-(t, n) term of dL/dw[t][r] = u_r . dL/dmu' + grad u_r : dL/dK
+            gbeta -= ggu * f.pa + ggv * f.pb;
+            float gpa = -ggu * f.beta, gpb = -ggv * f.beta;
+            gkap += gHuu * dot3(f.Dup, f.Dup) + gHuv * dot3(f.Dup, f.Dvp) +
+                    gHvv * dot3(f.Dvp, f.Dvp);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gDup[a] = f.kap * (2.0f * gHuu * f.Dup[a] + gHuv * f.Dvp[a]);
+                gDvp[a] = f.kap * (2.0f * gHvv * f.Dvp[a] + gHuv * f.Dup[a]);
+            }
+            gbeta += 2.0f * f.beta * gkap;
+            gpa -= dot3(gDup, f.mw);
+            gpb -= dot3(gDvp, f.mw);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gDu[a] += gDup[a];
+                gDv[a] += gDvp[a];
+                gmw[a] = -f.pa * gDup[a] - f.pb * gDvp[a];
+            }
+            const float gdu = gpa * f.ic, gdv = gpb * f.ic;
+            gc -= (gpa * f.pa + gpb * f.pb) * f.ic;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gmw[a] += gdu * f.Du[a] + gdv * f.Dv[a] + 2.0f * gc * f.mw[a];
+                gDu[a] += gdu * f.mw[a];
+                gDv[a] += gdv * f.mw[a];
+            }
+            float galpha = gbeta / G.sdd;
+            const float ia = 1.0f / f.alpha;
+            const float kuf = G.sdd * ia / G.pitch_u, kvf = G.sdd * ia / G.pitch_v;
+            const float gxu = -gus * kuf, gxv = -gvs * kvf;
+            galpha += gus * kuf * f.xu * ia + gvs * kvf * f.xv * ia;
+            // mw = W m, Du = pu W e_u, Dv = pv W e_v
+            const float eu[3] = {-vt.st, vt.ct, 0.0f};
+            float gW[9], gm[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gW[3 * a + b] = gmw[a] * f.m[b] + G.pitch_u * gDu[a] * eu[b] +
+                                    (b == 2 ? G.pitch_v * gDv[a] : 0.0f);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                gm[b] = f.W[b] * gmw[0] + f.W[3 + b] * gmw[1] + f.W[6 + b] * gmw[2];
+            float gmup[3] = {-gm[0], -gm[1], -gm[2]};
+            gmup[0] += -vt.ct * galpha + vt.st * gxu;
+            gmup[1] += -vt.st * galpha - vt.ct * gxu;
+            gmup[2] += -gxv;
+            // W = M^-1: dL/dM = -W^T gW W^T
+            float T1[9], gM[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    T1[3 * a + b] =
+                        f.W[a] * gW[b] + f.W[3 + a] * gW[3 + b] + f.W[6 + a] * gW[6 + b];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gM[3 * a + b] = -(T1[3 * a] * f.W[3 * b] + T1[3 * a + 1] * f.W[3 * b + 1] +
+                                      T1[3 * a + 2] * f.W[3 * b + 2]);
+            // M = K (R S): dL/dK = gM (RS)^T, dL/d(RS) = K^T gM
+            float RS[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) RS[3 * a + b] = Rm[3 * a + b] * s[b];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) out[a] = gmup[a];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    out[3 + 3 * a + b] = gM[3 * a] * RS[3 * b] + gM[3 * a + 1] * RS[3 * b + 1] +
+                                         gM[3 * a + 2] * RS[3 * b + 2];
+                    out[12 + 3 * a + b] = f.K[a] * gM[b] + f.K[3 + a] * gM[3 + b] +
+                                          f.K[6 + a] * gM[6 + b];
+                }
+            out[21] = grho_t;
+            // per-(t, n) term of dL/dw[t][r] = u_r . dL/dmu' + grad u_r : dL/dK
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                float c = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) c = fmaf(U[r][a], out[a], c);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) c = fmaf(V[r][k], out[3 + k], c);
+                gwc[r] = c;
+            }
+            // per-Gaussian sums over the chunk's views, in view order
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gsum[a] += out[a];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) gRS[k] += out[12 + k];
+            grho += out[21];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) P[r][a] = fmaf(wt[r], out[a], P[r][a]);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) Q[r][k] = fmaf(wt[r], out[3 + k], Q[r][k]);
+            }
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            float c = 0.0f;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) c = fmaf(U[r][a], out[a], c);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) c = fmaf(V[r][k], out[3 + k], c);
-            gwc[r] = c;
+            const float sm = wave_sum(gwc[r]);
+            if (lane == 0) gwpart[((size_t)t * NR + r) * nparts + blockIdx.x * 4 + wave] = sm;
         }
     }
     if (valid) {
+        float *dst = tacc + (size_t)chunk * n + i;
+        const size_t fs = (size_t)nch * n;
 #pragma unroll
-        for (int c = 0; c < TN_FIELDS; ++c) tnout[((size_t)c * T + t) * n + i] = out[c];
-    }
+        for (int a = 0; a < 3; ++a) dst[a * fs] = gsum[a];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const float sm = wave_sum(gwc[r]);
-        if (lane == 0) gwpart[((size_t)t * NR + r) * nparts + blockIdx.x * 4 + wave] = sm;
+        for (int k = 0; k < 9; ++k) dst[(3 + k) * fs] = gRS[k];
+        dst[12 * fs] = grho;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) dst[(13 + 12 * r + a) * fs] = P[r][a];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) dst[(16 + 12 * r + k) * fs] = Q[r][k];
+        }
     }
 }
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_gauss_reduce(
-    DevGrid grid, int n, int T, const float *__restrict__ coef, const float *__restrict__ gpar,
-    const float *__restrict__ w, const float *__restrict__ uv, const float *__restrict__ tnout,
+    DevGrid grid, int n, int nch, const float *__restrict__ coef, const float *__restrict__ gpar,
+    const float *__restrict__ uv, const float *__restrict__ tacc,
     const uint32_t *__restrict__ order, float *__restrict__ g_mu, float *__restrict__ g_scale,
     float *__restrict__ g_quat, float *__restrict__ g_rho, float *__restrict__ gq, int gq_stride)
 {
@@ -1167,26 +1327,21 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
 #pragma unroll
         for (int k = 0; k < 9; ++k) Q[r][k] = 0.0f;
     }
-    const size_t TN = (size_t)T * n;
-    for (int t = 0; t < T; ++t) {
-        const float *src = tnout + (size_t)t * n + i;
-        float gmup[3], gK[9];
+    // the chunks of views, in order
+    const size_t fs = (size_t)nch * n;
+    for (int c = 0; c < nch; ++c) {
+        const float *src = tacc + (size_t)c * n + i;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) gmup[a] = src[a * TN];
+        for (int a = 0; a < 3; ++a) gsum[a] += src[a * fs];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) gK[k] = src[(3 + k) * TN];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) gRS[k] += src[(12 + k) * TN];
-        grho += src[21 * TN];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) gsum[a] += gmup[a];
+        for (int k = 0; k < 9; ++k) gRS[k] += src[(3 + k) * fs];
+        grho += src[12 * fs];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const float wr = w[(size_t)t * NR + r];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) P[r][a] = fmaf(wr, gmup[a], P[r][a]);
+            for (int a = 0; a < 3; ++a) P[r][a] += src[(13 + 12 * r + a) * fs];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) Q[r][k] = fmaf(wr, gK[k], Q[r][k]);
+            for (int k = 0; k < 9; ++k) Q[r][k] += src[(16 + 12 * r + k) * fs];
         }
     }
     // dL/dmu = sum_t dL/dmu' + sum_r V_r^T P_r + sum_r Q_r : d(grad u_r)/dmu
@@ -1249,15 +1404,21 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     }
 }
 
-__global__ void k_gw_final(int T, int R, const float *__restrict__ gwpart, int nparts,
-                           float *__restrict__ g_w)
+// One workgroup per (t, r): strided per-thread sums over the per-wave parts, then a fixed tree.
+__global__ __launch_bounds__(256) void k_gw_final(const float *__restrict__ gwpart, int nparts,
+                                                  float *__restrict__ g_w)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= T * R) return;
-    const float *p = gwpart + (size_t)idx * nparts;
-    float s = 0.0f;
-    for (int k = 0; k < nparts; ++k) s += p[k];
-    g_w[idx] = s;
+    __shared__ float red[256];
+    const float *p = gwpart + (size_t)blockIdx.x * nparts;
+    float v = 0.0f;
+    for (int k = threadIdx.x; k < nparts; k += 256) v += p[k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g_w[blockIdx.x] = red[0];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1281,17 +1442,22 @@ __global__ void k_cell_keys(DevGrid g, int n, const float *__restrict__ mu,
     vals[i] = (uint32_t)i;
 }
 
-// cell_start[k] = number of Gaussians whose cell key is below k (for every key 0..ncells);
-// order[p] = the Gaussian at position p in cell order
+// cell_start[k] = number of Gaussians whose cell key is below k (for every key 0..ncells), by a
+// binary search of the sorted keys per cell; order[p] = the Gaussian at position p in cell order
 __global__ void k_cell_start(int n, int ncells, const uint32_t *__restrict__ keys,
                              const uint32_t *__restrict__ vals, uint32_t *__restrict__ cell_start,
                              uint32_t *__restrict__ order)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > n) return;
-    const uint32_t hi = (p < n) ? min(keys[p], (uint32_t)ncells) : (uint32_t)ncells;
-    const uint32_t lo = (p > 0) ? min(keys[p - 1], (uint32_t)ncells) + 1u : 0u;
-    for (uint32_t k = lo; k <= hi; ++k) cell_start[k] = (uint32_t)p;
+    if (p <= ncells) {
+        int lo = 0, hi = n;   // first position whose key is >= p
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (keys[mid] < (uint32_t)p) lo = mid + 1;
+            else hi = mid;
+        }
+        cell_start[p] = (uint32_t)lo;
+    }
     if (p < n) order[p] = min(vals[p], (uint32_t)(n - 1));
 }
 
@@ -1404,7 +1570,9 @@ static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
         uint32_t *t0 = ka; ka = kb; kb = t0;
         t0 = va; va = vb; vb = t0;
     }
-    hipLaunchKernelGGL(k_cell_start, dim3((n + 1 + 255) / 256), dim3(256), 0, s, n, a.L.ncells,
+    const int cs_threads = std::max(n, a.L.ncells + 1);
+    hipLaunchKernelGGL(k_cell_start, dim3((cs_threads + 255) / 256), dim3(256), 0, s, n,
+                       a.L.ncells,
                        ka, va, WS(a, cell_start, uint32_t *), WS(a, order, uint32_t *));
     return hipGetLastError();
 }
@@ -1552,27 +1720,29 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     hipError_t e;
     {
         ProfScope ps(PS_GAUSS_BWD, s);
-        hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, T), dim3(256), 0, s, a.geom, n, T,
-                           WS(a, gsort, const float *), a.angles, a.w, WS(a, uv, const float *),
-                           WS(a, rect, const int2 *),
+        hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, a.L.tchunks), dim3(256), 0, s, a.geom, n, T,
+                           a.L.tpc, WS(a, gsort, const float *), a.angles, a.w,
+                           WS(a, uv, const float *), WS(a, rect, const int2 *),
                            WS(a, gcount, const uint32_t *),
                            WS(a, part, const float4 *),
-                           (unsigned)a.L.cap, WS(a, tnout, float *), WS(a, gwpart, float *),
+                           (unsigned)a.L.cap, WS(a, tacc, float *), WS(a, gwpart, float *),
                            nparts);
         e = hipGetLastError();
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_gauss_reduce<NR>, dim3(nb), dim3(256), 0, s, a.grid, n, T,
-                               a.coef, WS(a, gsort, const float *), a.w, WS(a, uv, const float *),
-                               WS(a, tnout, const float *), WS(a, order, const uint32_t *),
-                               g_mu, g_scale, g_quat, g_rho, WS(a, gq, float *), a.L.gq_stride);
+            hipLaunchKernelGGL(k_gauss_reduce<NR>, dim3(nb), dim3(256), 0, s, a.grid, n,
+                               a.L.tchunks, a.coef, WS(a, gsort, const float *),
+                               WS(a, uv, const float *), WS(a, tacc, const float *),
+                               WS(a, order, const uint32_t *), g_mu, g_scale, g_quat, g_rho,
+                               WS(a, gq, float *), a.L.gq_stride);
             e = hipGetLastError();
         }
     }
     if (e != hipSuccess) return e;
     {
         ProfScope ps(PS_OTHER, s);
-        hipLaunchKernelGGL(k_gw_final, dim3((T * NR + 63) / 64), dim3(64), 0, s, T, NR,
-                           WS(a, gwpart, const float *), nparts, g_w);
+        if (T * NR > 0)
+            hipLaunchKernelGGL(k_gw_final, dim3(T * NR), dim3(256), 0, s,
+                               WS(a, gwpart, const float *), nparts, g_w);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
