@@ -9,6 +9,8 @@ Functions mirror the product's entry points in argument meaning (not in precisio
   ffd_eval        Eq. 10-11   per-rank u_r(x) and grad u_r(x)
   deform          Eq. 7-9     mu' and Sigma' for every (t, n)
   project         Eq. 1,3,6   the closed-form line-integral sum at every pixel, no cut-off
+                  Eq. 4       or, with geom["model"] == "ewa", the sum of the 2D Gaussians of Eq. 4
+  ewa_gaussian    Eq. 4       one Gaussian's 2D mean, covariance and scaled density
   project_pixels              the same at a list of sampled pixels
   project_bwd                 reverse mode of ``project`` for a sparse dL/dI
   line_integral               one Gaussian along one line
@@ -50,7 +52,7 @@ class Geom(ctypes.Structure):
     _fields_ = [("sid", ctypes.c_double), ("sdd", ctypes.c_double), ("nu", ctypes.c_int),
                 ("nv", ctypes.c_int), ("pitch_u", ctypes.c_double),
                 ("pitch_v", ctypes.c_double), ("off_u", ctypes.c_double),
-                ("off_v", ctypes.c_double)]
+                ("off_v", ctypes.c_double), ("model", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +82,8 @@ def _load():
                                            ctypes.c_int, _IP, _IP, _IP, _P,
                                            _P, _P, _P, _P, _P, _P]
         lib.oracle_project_bwd.restype = ctypes.c_int
+        lib.oracle_ewa_gaussian.argtypes = [ctypes.POINTER(Geom), ctypes.c_double, _P, _P,
+                                            ctypes.c_double, _P]
         lib.oracle_line_integral.argtypes = [_P, _P, ctypes.c_double, _P, _P]
         lib.oracle_line_integral.restype = ctypes.c_double
         lib.oracle_dvf.argtypes = [ctypes.POINTER(Grid), _P, _P, ctypes.c_int, _P, _P]
@@ -117,6 +121,7 @@ def make_geom(geom: dict) -> Geom:
     G.nu, G.nv = int(geom["nu"]), int(geom["nv"])
     G.pitch_u, G.pitch_v = float(geom["pitch_u"]), float(geom["pitch_v"])
     G.off_u, G.off_v = float(geom.get("off_u", 0.0)), float(geom.get("off_v", 0.0))
+    G.model = {"exact": 0, "ewa": 1}[geom.get("model", "exact")]
     return G
 
 
@@ -200,6 +205,8 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
     pt, ppt = _i(pt); pj, ppj = _i(pj); pi, ppi = _i(pi); pg, ppg = _d(pg)
     out = dict(g_mu=np.zeros((3, n)), g_scale=np.zeros((3, n)), g_quat=np.zeros((4, n)),
                g_rho=np.zeros(n), g_coef=np.zeros_like(coef), g_w=np.zeros((T, g.R)))
+    if G.model != 0:
+        raise ValueError("the oracle's reverse mode covers the exact model only")
     rc = _load().oracle_project_bwd(
         ctypes.byref(G), ctypes.byref(g), pc, n, pm, ps, pq, pr, T, pa, pw, pt.shape[0], ppt,
         ppj, ppi, ppg, *[out[k].ctypes.data_as(_P) for k in
@@ -213,6 +220,17 @@ def line_integral(mu, cov6, rho, src, direction) -> float:
     """One Gaussian's integral along the whole line src + lambda * direction."""
     mu, pm = _d(mu); cov6, pc = _d(cov6); src, ps = _d(src); direction, pd = _d(direction)
     return float(_load().oracle_line_integral(pm, pc, float(rho), ps, pd))
+
+
+def ewa_gaussian(geom: dict, theta: float, mu, cov6, rho):
+    """Eq. 4's 2D Gaussian of one 3D Gaussian at view angle theta: (mean[2] in detector mm from
+    the detector centre, covariance [[uu, uv], [uv, vv]] in mm^2, scaled density rho~)."""
+    G = make_geom(geom)
+    mu, pm = _d(mu); cov6, pc = _d(cov6)
+    out = np.zeros(6)
+    _load().oracle_ewa_gaussian(ctypes.byref(G), float(theta), pm, pc, float(rho),
+                                out.ctypes.data_as(_P))
+    return out[:2].copy(), np.array([[out[2], out[3]], [out[3], out[4]]]), float(out[5])
 
 
 def dvf(grid: dict, coef, w_t, x):

@@ -38,7 +38,11 @@
  *     e_u = (-sin t, cos t, 0), e_v = (0,0,1); pixel (row j, column i) centre at
  *     detector centre + (x_i + off_u) e_u + (y_j + off_v) e_v, x_i = (i - (nu-1)/2) pitch_u,
  *     y_j = (j - (nv-1)/2) pitch_v; projections stored proj[t][j][i];
- *   - the projection value is point-sampled at the pixel centre, integrated over the whole line.
+ *   - the projection value is point-sampled at the pixel centre, integrated over the whole line;
+ *   - Eq. 4's integration-bias factor (defined in the cited R2-Gaussian work, not in the paper) is
+ *     taken as the factor that makes the 2D Gaussian's peak equal the 3D Gaussian's line integral
+ *     along the ray through its mean: rho~ = rho sqrt(2 pi / (d^T A d)), d the unit direction of
+ *     that ray.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -54,6 +58,7 @@ typedef struct {
     double sid, sdd;
     int nu, nv;
     double pitch_u, pitch_v, off_u, off_v;
+    int model;           /* 0: exact line integral; 1: the 2D-Gaussian approximation of Eq. 4 */
 } oracle_geom;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -373,6 +378,108 @@ double oracle_line_integral(const double mu[3], const double cov6[6], double rho
     return line_integral(A, m, d, rho);
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Sec. 3.1, Eq. 4: the cone-beam projection of a Gaussian approximated by a 2D Gaussian.
+ * The viewing transform W maps world points to the view frame of angle theta (origin at the
+ * source; axes e_u, e_v and n, n pointing from the source to the detector centre); the
+ * perspective map takes a view-frame point (x, y, z) to detector coordinates SDD (x/z, y/z)
+ * (mm, from the detector centre, along e_u and e_v); J is its Jacobian at the mean. The 2D
+ * covariance is J W Sigma' W^T J^T (the 2x2 that remains after dropping the third row and
+ * column of the 3x3 form), the 2D mean is the image of mu', and the density is scaled by the
+ * integration-bias factor (reading in the header). */
+typedef struct {
+    double m2[2];        /* projected mean (mm on the detector)  */
+    double C2[2][2];     /* 2D covariance (mm^2)                 */
+    double iC2[2][2];    /* its inverse                          */
+    double rho2;         /* rho~                                 */
+} ewa_gauss;
+
+static void view_frame(double theta, double W[3][3])
+{
+    const double ct = cos(theta), sn = sin(theta);
+    W[0][0] = -sn; W[0][1] = ct;  W[0][2] = 0.0;    /* e_u */
+    W[1][0] = 0.0; W[1][1] = 0.0; W[1][2] = 1.0;    /* e_v */
+    W[2][0] = -ct; W[2][1] = -sn; W[2][2] = 0.0;    /* n   */
+}
+
+static void ewa_project(const oracle_geom *G, double theta, const double mu_t[3],
+                        const double St[3][3], const double A[3][3], double rho, ewa_gauss *e)
+{
+    double s[3], W[3][3], xv[3] = {0, 0, 0};
+    source_position(G, theta, s);
+    view_frame(theta, W);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) xv[a] += W[a][b] * (mu_t[b] - s[b]);
+    const double x = xv[0], y = xv[1], z = xv[2], f = G->sdd;
+    e->m2[0] = f * x / z;
+    e->m2[1] = f * y / z;
+    /* J (its first two rows) of (x, y, z) -> f (x/z, y/z) */
+    const double J[2][3] = {{f / z, 0.0, -f * x / (z * z)}, {0.0, f / z, -f * y / (z * z)}};
+    double JW[2][3];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            JW[a][b] = 0.0;
+            for (int k = 0; k < 3; ++k) JW[a][b] += J[a][k] * W[k][b];
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double v = 0.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) v += JW[a][k] * St[k][l] * JW[b][l];
+            e->C2[a][b] = v;
+        }
+    const double det = e->C2[0][0] * e->C2[1][1] - e->C2[0][1] * e->C2[1][0];
+    e->iC2[0][0] = e->C2[1][1] / det;
+    e->iC2[1][1] = e->C2[0][0] / det;
+    e->iC2[0][1] = -e->C2[0][1] / det;
+    e->iC2[1][0] = -e->C2[1][0] / det;
+    /* integration-bias factor: the line integral along the ray through the mean */
+    double d[3], nd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        d[a] = mu_t[a] - s[a];
+        nd += d[a] * d[a];
+    }
+    nd = sqrt(nd);
+    double dAd = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) dAd += (d[a] / nd) * A[a][b] * (d[b] / nd);
+    e->rho2 = rho * sqrt(2.0 * M_PI / dAd);
+}
+
+static double ewa_value(const ewa_gauss *e, double u, double v)
+{
+    const double du = u - e->m2[0], dv = v - e->m2[1];
+    const double q = du * (e->iC2[0][0] * du + e->iC2[0][1] * dv) +
+                     dv * (e->iC2[1][0] * du + e->iC2[1][1] * dv);
+    return e->rho2 * exp(-0.5 * q);
+}
+
+/* Public: the 2D Gaussian of Eq. 4 for one 3D Gaussian (mean, packed covariance) and view:
+ * out[0..1] projected mean, out[2..4] covariance (uu, uv, vv), out[5] rho~. */
+void oracle_ewa_gaussian(const oracle_geom *G, double theta, const double mu[3],
+                         const double cov6[6], double rho, double out[6])
+{
+    double S[3][3] = {{cov6[0], cov6[1], cov6[2]}, {cov6[1], cov6[3], cov6[4]},
+                      {cov6[2], cov6[4], cov6[5]}};
+    double A[3][3];
+    mat_inverse(S, A);
+    ewa_gauss e;
+    ewa_project(G, theta, mu, S, A, rho, &e);
+    out[0] = e.m2[0];
+    out[1] = e.m2[1];
+    out[2] = e.C2[0][0];
+    out[3] = e.C2[0][1];
+    out[4] = e.C2[1][1];
+    out[5] = e.rho2;
+}
+
+/* detector coordinates (mm, from the detector centre) of pixel (j, i) */
+static void pixel_detector(const oracle_geom *G, int j, int i, double *u, double *v)
+{
+    *u = (i - 0.5 * (G->nu - 1)) * G->pitch_u + G->off_u;
+    *v = (j - 0.5 * (G->nv - 1)) * G->pitch_v + G->off_v;
+}
+
 static gauss_state *deform_all(const oracle_grid *g, const double *coef, int n, const double *mu,
                                const double *scale, const double *quat, int T, const double *w)
 {
@@ -389,6 +496,21 @@ static gauss_state *deform_all(const oracle_grid *g, const double *coef, int n, 
     return st;
 }
 
+/* Eq. 4's 2D Gaussian of every (t, n) */
+static ewa_gauss *ewa_all(const oracle_geom *G, const gauss_state *st, int n, const double *rho,
+                          int T, const double *angles)
+{
+    ewa_gauss *e = (ewa_gauss *)malloc(sizeof(ewa_gauss) * (size_t)T * n);
+    if (!e) return NULL;
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < n; ++i) {
+            const gauss_state *gs = &st[(size_t)t * n + i];
+            ewa_project(G, angles[t], gs->mu_t, gs->St, gs->A, rho[i], &e[(size_t)t * n + i]);
+        }
+    return e;
+}
+
 /* Public: the forward projection (Eq. 1, 3, 6-9): proj[T][nv][nu] = sum over all Gaussians of
  * the closed-form line integral along the ray from the source to each pixel centre. */
 int oracle_project(const oracle_geom *G, const oracle_grid *g, const double *coef, int n,
@@ -397,11 +519,23 @@ int oracle_project(const oracle_geom *G, const oracle_grid *g, const double *coe
 {
     gauss_state *st = deform_all(g, coef, n, mu, scale, quat, T, w);
     if (!st) return -1;
+    ewa_gauss *ew = NULL;
+    if (G->model == 1 && !(ew = ewa_all(G, st, n, rho, T, angles))) {
+        free(st);
+        return -1;
+    }
     const int npx = G->nu * G->nv;
 #pragma omp parallel for schedule(dynamic, 16) collapse(2)
     for (int t = 0; t < T; ++t)
         for (int p = 0; p < npx; ++p) {
             int j = p / G->nu, i = p % G->nu;
+            if (ew) {
+                double u, v, acc = 0.0;
+                pixel_detector(G, j, i, &u, &v);
+                for (int k = 0; k < n; ++k) acc += ewa_value(&ew[(size_t)t * n + k], u, v);
+                proj[(size_t)t * npx + p] = acc;
+                continue;
+            }
             double s[3], P[3], d[3];
             source_position(G, angles[t], s);
             pixel_centre(G, angles[t], j, i, P);
@@ -416,6 +550,7 @@ int oracle_project(const oracle_geom *G, const oracle_grid *g, const double *coe
             }
             proj[(size_t)t * npx + p] = acc;
         }
+    free(ew);
     free(st);
     return 0;
 }
@@ -428,9 +563,21 @@ int oracle_project_pixels(const oracle_geom *G, const oracle_grid *g, const doub
 {
     gauss_state *st = deform_all(g, coef, n, mu, scale, quat, T, w);
     if (!st) return -1;
+    ewa_gauss *ew = NULL;
+    if (G->model == 1 && !(ew = ewa_all(G, st, n, rho, T, angles))) {
+        free(st);
+        return -1;
+    }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int q = 0; q < npix; ++q) {
         int t = pt[q];
+        if (ew) {
+            double u, v, acc = 0.0;
+            pixel_detector(G, pj[q], pi[q], &u, &v);
+            for (int k = 0; k < n; ++k) acc += ewa_value(&ew[(size_t)t * n + k], u, v);
+            out[q] = acc;
+            continue;
+        }
         double s[3], P[3], d[3];
         source_position(G, angles[t], s);
         pixel_centre(G, angles[t], pj[q], pi[q], P);
@@ -445,6 +592,7 @@ int oracle_project_pixels(const oracle_geom *G, const oracle_grid *g, const doub
         }
         out[q] = acc;
     }
+    free(ew);
     free(st);
     return 0;
 }
@@ -468,6 +616,7 @@ int oracle_project_bwd(const oracle_geom *G, const oracle_grid *g, const double 
                        double *g_mu, double *g_scale, double *g_quat, double *g_rho,
                        double *g_coef, double *g_w)
 {
+    if (G->model != 0) return -2;   /* reverse mode of the exact model only */
     gauss_state *st = deform_all(g, coef, n, mu, scale, quat, T, w);
     gauss_grad *gg = (gauss_grad *)calloc((size_t)T * n, sizeof(gauss_grad));
     /* group the pixel entries by projection (order within a projection kept) */
