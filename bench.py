@@ -35,11 +35,13 @@ METRIC = "fwd+bwd projections/s @200k Gaussians 512×384 det; % HBM roofline; sp
 
 # Algorithmic FP32 work per (Gaussian, pixel) pair inside a cut-off footprint, in the splats'
 # forward-difference formulation (FMA = 2 FLOP, add/mul = 1, rsqrt/exp2 = 1), and the VALU issue
-# slots it needs: forward 4 adds (q, dq, E, dE) + 3 muls + 1 FMA + rsqrt + exp2; backward the same
-# evaluation plus the 12 moment sums of the adjoint (22 VALU ops + rsqrt + exp2). A transcendental
-# issues at half the FMA rate on gfx950 (measured), i.e. TRANS_SLOTS = 2 slots.
-FWD_FLOP, FWD_VALU, FWD_TRANS = 11, 8, 2
-BWD_FLOP, BWD_VALU, BWD_TRANS = 27, 22, 2
+# slots it needs: forward 4 adds (q, dq, E, dE), r^2, x = E r^2 + log2 amp (FMA), the sum (FMA),
+# rsqrt and exp2 (7 VALU ops, 2 transcendentals); backward the same evaluation (r^2, x, g r 2^x:
+# 3 muls; a = . r^2, a x: 2 muls) plus its moment sums (3 adds and 4 FMAs per pixel: 17 VALU ops,
+# 2 transcendentals). A transcendental issues at half the FMA rate on gfx950 (measured), i.e.
+# TRANS_SLOTS = 2 slots.
+FWD_FLOP, FWD_VALU, FWD_TRANS = 11, 7, 2
+BWD_FLOP, BWD_VALU, BWD_TRANS = 23, 17, 2
 TRANS_SLOTS = 2
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes per cycle x clock
 HBM_PEAK_GBS = 8000.0
@@ -155,6 +157,61 @@ def volume_leg(dev):
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(dvf_bytes / dvf_ms / 1e6 / HBM_PEAK_GBS, 4)},
             "phi_ms": round(phi_ms, 4), "phi_brick_pairs": int(ws.diagnostics()["instances"])}
+
+
+def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: float):
+    """The batched fwd+bwd step under the EWA model of Eq. 4 (same phantom, batches and plan
+    machinery, its own autotuned plan), and the model's deviation from the exact line integral:
+    max |I_EWA - I_exact| / max I_exact over the first batch of the reference phantom's views."""
+    import torch
+    from paper_2506_22280_amd import _lib
+    dev = ang[0].device
+    G, Gd, n, B = dict(p.geom, model="ewa"), p.grid, p.n, ang[0].shape[0]
+    ws = _lib.Workspace(dev)
+    exact = _lib.project_fwd(p.geom, Gd, ref["coef"], ref["mu"], ref["scale"], ref["quat"],
+                             ref["rho"], ang[0], wts[0], ws).clone()
+    ewa = _lib.project_fwd(G, Gd, ref["coef"], ref["mu"], ref["scale"], ref["quat"], ref["rho"],
+                           ang[0], wts[0], ws)
+    dev_max = float((ewa - exact).abs().max() / exact.abs().max())
+    del ws, ewa, exact
+    proj = torch.empty((B, G["nv"], G["nu"]), device=dev)
+    gradp = torch.zeros_like(proj)
+    ang_buf, w_buf = ang[0].clone(), wts[0].clone()
+    grads = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
+                 g_quat=torch.empty((4, n), device=dev), g_rho=torch.empty((n,), device=dev),
+                 g_coef=torch.empty_like(est["coef"]), g_w=torch.empty((B, Gd["R"]), device=dev))
+    plan = _lib.Plan(G, Gd, n, B, dict(est, angles=ang_buf, w=w_buf, proj=proj, grad_proj=gradp,
+                                       **grads))
+    tuning, _ = plan.tuning()
+
+    def step(k):
+        kb = k % len(ang)
+        ang_buf.copy_(ang[kb])
+        w_buf.copy_(wts[kb])
+        plan.fwd()
+        torch.sub(proj, meas[kb], out=gradp)
+        plan.bwd()
+
+    for k in range(warmup):
+        step(k)
+    _, resized = plan.check()
+    if resized:
+        for k in range(warmup):
+            step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(warmup + k)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    diag, resized = plan.check()
+    plan.close()
+    if resized or diag["overflow"] or diag["nonfinite"]:
+        raise SystemExit("EWA leg: diagnostics report a problem: %s" % diag)
+    return {"ms_per_step": round(dt * 1e3, 3), "projections_per_s": round(B / dt, 2),
+            "speedup_vs_exact": round(exact_ms / (dt * 1e3), 3),
+            "max_dev_vs_exact_rel_to_max": round(dev_max, 6),
+            "tuning": {k: tuning[k] for k in ("splat_waves", "persistent")}}
 
 
 def main():
@@ -341,6 +398,8 @@ def main():
             "evaluated_fwd": int(sum(x[1] for x in pairs) / len(pairs) / B),
             "evaluated_bwd": int(sum(x[2] for x in pairs) / len(pairs) / B)}
     if not args.no_extra:
+        out["ewa_model"] = ewa_leg(p, est, ang, wts, meas, max(5, args.steps // 2), args.warmup,
+                                   ref, dt / args.steps * 1e3)
         out["single_view_50k"] = single_view_leg(dev)
         out["volume_query_500k_256cubed"] = volume_leg(dev)
     if not args.no_warmstart:

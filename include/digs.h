@@ -59,7 +59,17 @@ typedef struct digs_geom {
     int nu, nv;              /* detector columns, rows (>0; ceil(nu/16)*ceil(nv/16) <= 4096)  */
     float pitch_u, pitch_v;  /* pixel pitch (mm, >0)                                           */
     float off_u, off_v;      /* detector offset along e_u, e_v (mm)                            */
+    int model;               /* projection model, DIGS_MODEL_EXACT (0) or DIGS_MODEL_EWA (1)   */
 } digs_geom;
+
+/* Projection models. EXACT: each Gaussian's line integral along the ray from the source to the
+ * pixel centre, in closed form (Eq. 2 integrated along the ray of Eq. 1; what Eq. 4 approximates).
+ * EWA: the 2D-Gaussian approximation of Sec. 3.1, Eq. 4: the Gaussian projected through the local
+ * affine approximation of the perspective map at its mean (covariance J W Sigma' W^T J^T, top-left
+ * 2x2), with density scaled so that the 2D Gaussian's peak equals the line integral along the ray
+ * through the mean, rho sqrt(2 pi / (d^T Sigma'^-1 d)) for the unit direction d of that ray. */
+#define DIGS_MODEL_EXACT 0
+#define DIGS_MODEL_EWA 1
 
 /* Uniform control lattice of the cubic B-spline FFD (Sec. 3.3, Eq. 10): control point (i,j,k)
  * of rank r sits at origin + (i,j,k)*spacing and stores d^r_ijk. Lattice index space is

@@ -29,7 +29,10 @@ class DigsError(RuntimeError):
 class Geom(ctypes.Structure):
     _fields_ = [("sid", ctypes.c_float), ("sdd", ctypes.c_float), ("nu", ctypes.c_int),
                 ("nv", ctypes.c_int), ("pitch_u", ctypes.c_float), ("pitch_v", ctypes.c_float),
-                ("off_u", ctypes.c_float), ("off_v", ctypes.c_float)]
+                ("off_u", ctypes.c_float), ("off_v", ctypes.c_float), ("model", ctypes.c_int)]
+
+
+MODELS = {"exact": 0, "ewa": 1}   # DIGS_MODEL_EXACT, DIGS_MODEL_EWA
 
 
 class Grid(ctypes.Structure):
@@ -174,6 +177,7 @@ def make_geom(g: dict) -> Geom:
     G.nu, G.nv = int(g["nu"]), int(g["nv"])
     G.pitch_u, G.pitch_v = float(g["pitch_u"]), float(g["pitch_v"])
     G.off_u, G.off_v = float(g.get("off_u", 0.0)), float(g.get("off_v", 0.0))
+    G.model = MODELS[g.get("model", "exact")]
     return G
 
 

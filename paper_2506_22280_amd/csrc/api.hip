@@ -29,7 +29,8 @@ static bool geom_ok(const digs_geom *g)
 {
     if (!g || !(g->sid > 0.0f) || !(g->sdd > g->sid) || g->nu <= 0 || g->nv <= 0 ||
         !(g->pitch_u > 0.0f) || !(g->pitch_v > 0.0f) || !isfinite(g->off_u) ||
-        !isfinite(g->off_v) || g->nu > 65535 || g->nv > 65535)
+        !isfinite(g->off_v) || g->nu > 65535 || g->nv > 65535 ||
+        (g->model != DIGS_MODEL_EXACT && g->model != DIGS_MODEL_EWA))
         return false;
     const long tx = (g->nu + DIGS_TILE - 1) / DIGS_TILE, ty = (g->nv + DIGS_TILE - 1) / DIGS_TILE;
     return tx * ty <= DIGS_MAX_TILES;
@@ -49,6 +50,7 @@ DevGeom make_dev_geom(const digs_geom *g)
     d.tiles_x = (g->nu + DIGS_TILE - 1) / DIGS_TILE;
     d.tiles_y = (g->nv + DIGS_TILE - 1) / DIGS_TILE;
     d.ntiles = d.tiles_x * d.tiles_y;
+    d.ewa = g->model == DIGS_MODEL_EWA ? 1 : 0;
     return d;
 }
 

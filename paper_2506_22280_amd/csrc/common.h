@@ -30,6 +30,7 @@ struct DevGeom {
     int nu, nv;
     float pitch_u, pitch_v, off_u, off_v;
     int tiles_x, tiles_y, ntiles;
+    int ewa;                 // projection model: 0 exact line integral, 1 EWA 2D approximation
 };
 
 struct DevGrid {

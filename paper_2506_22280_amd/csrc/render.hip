@@ -139,6 +139,7 @@ struct SetupFwd {
     // projection set-up
     float alpha, xu, xv, m[3], mw[3], Du[3], Dv[3], c, ic, pa, pb, Dup[3], Dvp[3], beta, kap;
     float Huu, Huv, Hvv, gu, gv, Guu, Guv, Gvv, amp, us, vs;
+    float ee;   // EWA: |e*|, the length of the ray through the mean to the detector; exact: 1
     bool ok;
 };
 
@@ -213,6 +214,13 @@ __device__ __forceinline__ void setup_forward(const DevGeom &G, const float *mu0
     f.Guv = f.kap * dot3(f.Du, f.Dv) * f.ic;
     f.Gvv = f.kap * dot3(f.Dv, f.Dv) * f.ic;
     f.amp = rho * SQRT_2PI * f.beta * sqrtf(f.ic);
+    // EWA (Eq. 4): the affine approximation at the mean drops the perspective terms (q = 1), and
+    // the 2D Gaussian's peak is the line integral along the ray through the mean, |e*| amp
+    f.ee = 1.0f;
+    if (G.ewa) {
+        f.ee = G.sdd * sqrtf(1.0f + (f.xu * f.xu + f.xv * f.xv) * (ia * ia));
+        f.gu = f.gv = f.Guu = f.Guv = f.Gvv = 0.0f;
+    }
     f.ok = f.ok && isfinite(f.us) && isfinite(f.vs) && isfinite(f.Huu) && isfinite(f.Huv) &&
            isfinite(f.Hvv) && isfinite(f.Guu) && isfinite(f.Guv) && isfinite(f.Gvv) &&
            isfinite(f.amp) && isfinite(f.gu) && isfinite(f.gv);
@@ -342,8 +350,9 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
                 rec[o * 4 + 0] = make_float4(f.us, f.vs, C2_EXP2 * f.Huu, 2.0f * C2_EXP2 * f.Huv);
                 rec[o * 4 + 1] = make_float4(C2_EXP2 * f.Hvv, 2.0f * f.gu, 2.0f * f.gv, f.Guu);
                 // the splats take amp as log2|amp| (-inf for 0) with its sign on Gvv (>= +0)
-                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, copysignf(f.Gvv, f.amp),
-                                             log2f(fabsf(f.amp)), fp.a00);
+                const float ampr = f.amp * f.ee;
+                rec[o * 4 + 2] = make_float4(2.0f * f.Guv, copysignf(f.Gvv, ampr),
+                                             log2f(fabsf(ampr)), fp.a00);
                 rec[o * 4 + 3] = make_float4(fp.a01, fp.a11, fp.cx, fp.cy);
             } else {   // an idle record: adds zero wherever it is evaluated
                 const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -504,7 +513,8 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 #define FWD_QUEUE (DIGS_WAVE + 8)
 
 // Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8, or the block's last group)
-// into the lane's 8 row sums.
+// into the lane's 8 row sums. EWA: q = 1, so a pixel costs one exp2 and the E recurrence.
+template <bool EWA>
 __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ qid, int ns,
                                                 int gslot, float fi, float fby, float *acc)
@@ -541,7 +551,25 @@ __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
         float de = fmaf(CE, s1, BE);
         const float dde = 2.0f * CE;
         const float la = r2.z;
-        if (__ballot(signbit(r2.y)) == 0ull) {
+        if constexpr (EWA) {
+            if (__ballot(signbit(r2.y)) == 0ull) {
+                e += la;   // amp 2^E = 2^(E + log2 amp)
+#pragma unroll
+                for (int row = 0; row < 8; ++row) {
+                    acc[row] += __builtin_amdgcn_exp2f(e);
+                    e += de;
+                    de += dde;
+                }
+            } else {
+                const float amp = copysignf(exp2f(la), r2.y);
+#pragma unroll
+                for (int row = 0; row < 8; ++row) {
+                    acc[row] = fmaf(amp, __builtin_amdgcn_exp2f(e), acc[row]);
+                    e += de;
+                    de += dde;
+                }
+            }
+        } else if (__ballot(signbit(r2.y)) == 0ull) {
             // all eight amplitudes positive: amp rs 2^x = rs 2^(x + log2 amp)
 #pragma unroll
             for (int row = 0; row < 8; ++row) {
@@ -576,7 +604,7 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int WAVES>
+template <int WAVES, bool EWA>
 __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ list,
@@ -616,7 +644,7 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
             const int full = ns & ~7;
             wave_sync_lds();
             if (full > 0) {
-                splat_fwd_group(rt, qid, full, gslot, fi, fby, acc);
+                splat_fwd_group<EWA>(rt, qid, full, gslot, fi, fby, acc);
                 // move the remainder to the front of the queue
                 const int left = ns - full;
                 const uint32_t keep = (lane < left) ? qid[full + lane] : 0u;
@@ -626,7 +654,7 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
             }
             pend = ns - full;
         }
-        if (pend > 0) splat_fwd_group(rt, qid, pend, gslot, fi, fby, acc);
+        if (pend > 0) splat_fwd_group<EWA>(rt, qid, pend, gslot, fi, fby, acc);
         wave_sync_lds();
         // sum over the 8 Gaussian slots (lane bits 3..5) in a fixed order
 #pragma unroll
@@ -640,10 +668,13 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
         for (int r = 1; r < 8; ++r) v = (gslot == r) ? acc[r] : v;
         const int px = bx + col, py = by + gslot;
         if (px < G.nu && py < G.nv) {
-            const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
-            const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
-            proj[((size_t)t * G.nv + py) * G.nu + px] =
-                v * sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+            // exact: times the pixel's ray length |e| (EWA: |e*| is in each amplitude)
+            if constexpr (!EWA) {
+                const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
+                const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
+                v *= sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+            }
+            proj[((size_t)t * G.nv + py) * G.nu + px] = v;
         }
     }
 }
@@ -665,7 +696,7 @@ __device__ __forceinline__ int next_item(uint32_t *__restrict__ queue, int home,
     return -1;
 }
 
-template <int WAVES>
+template <int WAVES, bool EWA>
 __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
                                                           const float4 *__restrict__ rec,
                                                           const uint32_t *__restrict__ list,
@@ -676,11 +707,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
     __shared__ uint32_t ids[WAVES][FWD_QUEUE];
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
-    splat_fwd_tile<WAVES>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
+    splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
 }
 
 // Persistent variant: a grid sized to the machine loops over the work queues.
-template <int WAVES>
+template <int WAVES, bool EWA>
 __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
     DevGeom G, int n, int T, const float4 *__restrict__ rec, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ cnt, int nblk, unsigned cap, float *__restrict__ proj,
@@ -697,7 +728,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
         if (item < 0) break;
         int t, tile;
         map_block(item, G.ntiles, T, t, tile);
-        splat_fwd_tile<WAVES>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
+        splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
     }
 }
 
@@ -790,7 +821,8 @@ struct BwdShared {
 };
 
 // Evaluates queued pairs [j0, j0 + cnt) of the wave (cnt <= 64), one per lane, and adds their
-// moment sums into the entries' slots.
+// moment sums into the entries' slots. EWA: q = 1 (no dL/dq moments), one exp2 per pixel.
+template <bool EWA>
 __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ pq,
                                                 const uint32_t *__restrict__ gid,
@@ -824,77 +856,116 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     // compile-time constant); rows are folded with dv, dv^2, and the block's column offset du0 is
     // applied at the end. dL/dq (up to the same factor) is b = a (1 + 2 ln2 x): its moments are
     // those of a plus 2 ln2 times those of a x.
-    float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
-    float X0 = 0.f, X1 = 0.f, X2 = 0.f, XV0 = 0.f, XV1 = 0.f, XW0 = 0.f;
-    const float *gp = gpx + lby * GPX_STRIDE + lbx;
-    for (int row = 0; row < 8; ++row) {
-        const float dv = dv0 + (float)row;
-        // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
-        const float Bq = fmaf(r2.x, dv, r1.y);
-        const float Aq = fmaf(dv, fmaf(Gvv, dv, r1.z), 1.0f);
-        const float BE = r0.w * dv, AE = r1.x * dv * dv;
-        float q = fmaf(du0, qa + Bq, Aq);
-        float dq = fmaf(Cq, s1, Bq);
-        const float ddq = 2.0f * Cq;
-        float ee = fmaf(du0, ea + BE, AE);
-        float de = fmaf(CE, s1, BE);
-        const float dde = 2.0f * CE;
-        float e0 = 0.f, e1 = 0.f, e2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float gval = gp[row * GPX_STRIDE + c];
-            const float rs = __builtin_amdgcn_rsqf(q);
-            const float r2s = rs * rs;
-            const float x = ee * r2s;
-            const float gr = (gval * rs) * __builtin_amdgcn_exp2f(x);
-            const float a = gr * r2s;
-            const float ax = a * x;
-            S0 += gr;
-            e0 += a;
-            x0 += ax;
-            if (c > 0) {
-                e1 = fmaf((float)c, a, e1);
-                e2 = fmaf((float)(c * c), a, e2);
-                x1 = fmaf((float)c, ax, x1);
-                x2 = fmaf((float)(c * c), ax, x2);
-            }
-            q += dq;
-            dq += ddq;
-            ee += de;
-            de += dde;
-        }
-        const float dv2 = dv * dv;
-        E0 += e0;
-        E1 += e1;
-        E2 += e2;
-        EV0 = fmaf(dv, e0, EV0);
-        EV1 = fmaf(dv, e1, EV1);
-        EW0 = fmaf(dv2, e0, EW0);
-        X0 += x0;
-        X1 += x1;
-        X2 += x2;
-        XV0 = fmaf(dv, x0, XV0);
-        XV1 = fmaf(dv, x1, XV1);
-        XW0 = fmaf(dv2, x0, XW0);
-    }
-    const float k2 = 2.0f * LN2;
-    const float Q0 = fmaf(k2, X0, E0), Q1 = fmaf(k2, X1, E1), Q2 = fmaf(k2, X2, E2);
-    const float QV0 = fmaf(k2, XV0, EV0), QV1 = fmaf(k2, XV1, EV1), QW0 = fmaf(k2, XW0, EW0);
-    // the twelve moment sums (du = du0 + c), with the factor -amp/2
-    const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
     float S[12];
-    S[0] = S0;
-    S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);    // sum dE du^2
-    S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
-    S[3] = cA * EW0;                                        // sum dE dv^2
-    S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
-    S[5] = cA * fmaf(du0, QV0, QV1);                        // sum dq du dv
-    S[6] = cA * QW0;                                        // sum dq dv^2
-    S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
-    S[8] = cA * QV0;                                        // sum dq dv
-    S[9] = cA * Q0;                                         // sum dq
-    S[10] = cA * fmaf(du0, E0, E1);                         // sum dE du
-    S[11] = cA * EV0;                                       // sum dE dv
+    if constexpr (EWA) {
+        // per pixel a = g 2^x (dL/dE up to the factor -amp/2); dL/damp = sum a
+        float E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
+        const float *gp = gpx + lby * GPX_STRIDE + lbx;
+        for (int row = 0; row < 8; ++row) {
+            const float dv = dv0 + (float)row;
+            const float BE = r0.w * dv, AE = r1.x * dv * dv;
+            float ee = fmaf(du0, ea + BE, AE);
+            float de = fmaf(CE, s1, BE);
+            const float dde = 2.0f * CE;
+            float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float a = gp[row * GPX_STRIDE + c] * __builtin_amdgcn_exp2f(ee);
+                e0 += a;
+                if (c > 0) {
+                    e1 = fmaf((float)c, a, e1);
+                    e2 = fmaf((float)(c * c), a, e2);
+                }
+                ee += de;
+                de += dde;
+            }
+            E0 += e0;
+            E1 += e1;
+            E2 += e2;
+            EV0 = fmaf(dv, e0, EV0);
+            EV1 = fmaf(dv, e1, EV1);
+            EW0 = fmaf(dv * dv, e0, EW0);
+        }
+        const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
+        S[0] = E0;
+        S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);
+        S[2] = cA * fmaf(du0, EV0, EV1);
+        S[3] = cA * EW0;
+        S[4] = S[5] = S[6] = S[7] = S[8] = S[9] = 0.0f;
+        S[10] = cA * fmaf(du0, E0, E1);
+        S[11] = cA * EV0;
+    } else {
+        float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
+        float X0 = 0.f, X1 = 0.f, X2 = 0.f, XV0 = 0.f, XV1 = 0.f, XW0 = 0.f;
+        const float *gp = gpx + lby * GPX_STRIDE + lbx;
+        for (int row = 0; row < 8; ++row) {
+            const float dv = dv0 + (float)row;
+            // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
+            const float Bq = fmaf(r2.x, dv, r1.y);
+            const float Aq = fmaf(dv, fmaf(Gvv, dv, r1.z), 1.0f);
+            const float BE = r0.w * dv, AE = r1.x * dv * dv;
+            float q = fmaf(du0, qa + Bq, Aq);
+            float dq = fmaf(Cq, s1, Bq);
+            const float ddq = 2.0f * Cq;
+            float ee = fmaf(du0, ea + BE, AE);
+            float de = fmaf(CE, s1, BE);
+            const float dde = 2.0f * CE;
+            float e0 = 0.f, e1 = 0.f, e2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float gval = gp[row * GPX_STRIDE + c];
+                const float rs = __builtin_amdgcn_rsqf(q);
+                const float r2s = rs * rs;
+                const float x = ee * r2s;
+                const float gr = (gval * rs) * __builtin_amdgcn_exp2f(x);
+                const float a = gr * r2s;
+                const float ax = a * x;
+                S0 += gr;
+                e0 += a;
+                x0 += ax;
+                if (c > 0) {
+                    e1 = fmaf((float)c, a, e1);
+                    e2 = fmaf((float)(c * c), a, e2);
+                    x1 = fmaf((float)c, ax, x1);
+                    x2 = fmaf((float)(c * c), ax, x2);
+                }
+                q += dq;
+                dq += ddq;
+                ee += de;
+                de += dde;
+            }
+            const float dv2 = dv * dv;
+            E0 += e0;
+            E1 += e1;
+            E2 += e2;
+            EV0 = fmaf(dv, e0, EV0);
+            EV1 = fmaf(dv, e1, EV1);
+            EW0 = fmaf(dv2, e0, EW0);
+            X0 += x0;
+            X1 += x1;
+            X2 += x2;
+            XV0 = fmaf(dv, x0, XV0);
+            XV1 = fmaf(dv, x1, XV1);
+            XW0 = fmaf(dv2, x0, XW0);
+        }
+        const float k2 = 2.0f * LN2;
+        const float Q0 = fmaf(k2, X0, E0), Q1 = fmaf(k2, X1, E1), Q2 = fmaf(k2, X2, E2);
+        const float QV0 = fmaf(k2, XV0, EV0), QV1 = fmaf(k2, XV1, EV1), QW0 = fmaf(k2, XW0, EW0);
+        // the twelve moment sums (du = du0 + c), with the factor -amp/2
+        const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
+        S[0] = S0;
+        S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);    // sum dE du^2
+        S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
+        S[3] = cA * EW0;                                        // sum dE dv^2
+        S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
+        S[5] = cA * fmaf(du0, QV0, QV1);                        // sum dq du dv
+        S[6] = cA * QW0;                                        // sum dq dv^2
+        S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
+        S[8] = cA * QV0;                                        // sum dq dv
+        S[9] = cA * Q0;                                         // sum dq
+        S[10] = cA * fmaf(du0, E0, E1);                         // sum dE du
+        S[11] = cA * EV0;                                       // sum dE dv
+    }
     // add into the entry's slot, one block at a time (an entry has at most one pair per block)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -927,6 +998,7 @@ __device__ __forceinline__ void splat_bwd_write(int n, int t, int tx, int ty, ui
     }
 }
 
+template <bool EWA>
 __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ list,
@@ -944,10 +1016,12 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         const int px = tx * DIGS_TILE + (p & 15), py = ty * DIGS_TILE + (p >> 4);
         float gv = 0.0f;
         if (px < G.nu && py < G.nv) {
-            const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
-            const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
-            gv = grad_proj[((size_t)t * G.nv + py) * G.nu + px] *
-                 sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+            gv = grad_proj[((size_t)t * G.nv + py) * G.nu + px];
+            if constexpr (!EWA) {   // times the pixel's ray length |e|
+                const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
+                const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
+                gv *= sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+            }
         }
         gpx[(p >> 4) * GPX_STRIDE + (p & 15)] = gv;
     }
@@ -989,7 +1063,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         int done = np & ~(DIGS_WAVE - 1);
         if (done == 0 && pend > 0) done = np;
         for (int j = 0; j < done; j += DIGS_WAVE)
-            splat_bwd_group(rt, pq, gid, accS, gpx, j, min(DIGS_WAVE, done - j), tx0, ty0);
+            splat_bwd_group<EWA>(rt, pq, gid, accS, gpx, j, min(DIGS_WAVE, done - j), tx0, ty0);
         if (it > 0 && prev_valid)
             splat_bwd_write(n, t, tx, ty, prev_g, accS[(ring ^ DIGS_WAVE) + lane], cap, rect, goff,
                             part);
@@ -1004,13 +1078,14 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         prev_valid = valid;
         prev_g = g;
     }
-    if (pend > 0) splat_bwd_group(rt, pq, gid, accS, gpx, 0, pend, tx0, ty0);
+    if (pend > 0) splat_bwd_group<EWA>(rt, pq, gid, accS, gpx, 0, pend, tx0, ty0);
     if (it > 0 && prev_valid)
         splat_bwd_write(n, t, tx, ty, prev_g, accS[((it - 1) & 1) * DIGS_WAVE + lane], cap, rect,
                         goff, part);
     wave_sync_lds();
 }
 
+template <bool EWA>
 __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                                                    const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ list,
@@ -1023,9 +1098,11 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
     __shared__ BwdShared sh;
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
-    splat_bwd_tile(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part, sh);
+    splat_bwd_tile<EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part,
+                        sh);
 }
 
+template <bool EWA>
 __global__ __launch_bounds__(256) void k_splat_bwd_persist(
     DevGeom G, int n, int T, const float4 *__restrict__ rec, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ cnt, int nblk, unsigned cap, const int2 *__restrict__ rect,
@@ -1043,7 +1120,8 @@ __global__ __launch_bounds__(256) void k_splat_bwd_persist(
         if (item < 0) break;
         int t, tile;
         map_block(item, G.ntiles, T, t, tile);
-        splat_bwd_tile(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part, sh);
+        splat_bwd_tile<EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj,
+                            part, sh);
     }
 }
 
@@ -1159,9 +1237,11 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
             float out[TN_FIELDS];
             // record gradients from the moment sums
             const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
-            const float gGuu = S[4], gGuv = 2.0f * S[5], gGvv = S[6];
-            const float ggu = 2.0f * S[7], ggv = 2.0f * S[8];
-            const float gamp = S[0];
+            // (EWA: g and G are the constant zero, and the record's amplitude is amp |e*|)
+            const float gGuu = G.ewa ? 0.0f : S[4], gGuv = G.ewa ? 0.0f : 2.0f * S[5];
+            const float gGvv = G.ewa ? 0.0f : S[6];
+            const float ggu = G.ewa ? 0.0f : 2.0f * S[7], ggv = G.ewa ? 0.0f : 2.0f * S[8];
+            const float gamp = S[0] * f.ee, gee = S[0] * f.amp;
             const float gus = -2.0f * (f.Huu * S[10] + f.Huv * S[11] + f.gu * S[9] + f.Guu * S[7] +
                                        f.Guv * S[8]);
             const float gvs = -2.0f * (f.Huv * S[10] + f.Hvv * S[11] + f.gv * S[9] + f.Guv * S[7] +
@@ -1210,8 +1290,14 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
             float galpha = gbeta / G.sdd;
             const float ia = 1.0f / f.alpha;
             const float kuf = G.sdd * ia / G.pitch_u, kvf = G.sdd * ia / G.pitch_v;
-            const float gxu = -gus * kuf, gxv = -gvs * kvf;
+            float gxu = -gus * kuf, gxv = -gvs * kvf;
             galpha += gus * kuf * f.xu * ia + gvs * kvf * f.xv * ia;
+            if (G.ewa) {   // |e*| = SDD sqrt(1 + (xu^2 + xv^2) / alpha^2)
+                const float k = gee * G.sdd * G.sdd * ia * ia / f.ee;
+                gxu += k * f.xu;
+                gxv += k * f.xv;
+                galpha -= k * (f.xu * f.xu + f.xv * f.xv) * ia;
+            }
             // mw = W m, Du = pu W e_u, Dv = pv W e_v
             const float eu[3] = {-vt.st, vt.ct, 0.0f};
             float gW[9], gm[3];
@@ -1665,15 +1751,36 @@ static unsigned persistent_grid(K kernel, int threads, size_t items)
 // Run the device queries of the persistent launches now (before any graph capture).
 void render_prepare_launch_shapes()
 {
-    (void)persistent_grid(k_splat_fwd_persist<1>, 64, 1);
-    (void)persistent_grid(k_splat_fwd_persist<4>, 256, 1);
-    (void)persistent_grid(k_splat_bwd_persist, 256, 1);
+    (void)persistent_grid(k_splat_fwd_persist<1, false>, 64, 1);
+    (void)persistent_grid(k_splat_fwd_persist<4, false>, 256, 1);
+    (void)persistent_grid(k_splat_fwd_persist<1, true>, 64, 1);
+    (void)persistent_grid(k_splat_fwd_persist<4, true>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<false>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<true>, 256, 1);
+}
+
+template <int WAVES, bool EWA>
+static void launch_splat_fwd(const RenderArgs &a, float *proj, uint32_t *queue, size_t items,
+                             hipStream_t s)
+{
+    const unsigned cap = (unsigned)a.L.cap;
+    if (a.persistent)
+        hipLaunchKernelGGL((k_splat_fwd_persist<WAVES, EWA>),
+                           dim3(persistent_grid(k_splat_fwd_persist<WAVES, EWA>, 64 * WAVES,
+                                                items)),
+                           dim3(64 * WAVES), 0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                           WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
+                           cap, proj, queue);
+    else
+        hipLaunchKernelGGL((k_splat_fwd<WAVES, EWA>), dim3((unsigned)items), dim3(64 * WAVES), 0, s,
+                           a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                           WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
+                           cap, proj);
 }
 
 hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
 {
     const size_t items = (size_t)a.geom.ntiles * a.T;
-    const unsigned cap = (unsigned)a.L.cap;
     uint32_t *queue = WS(a, queue, uint32_t *);
     if (a.persistent) {
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
@@ -1682,29 +1789,11 @@ hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
     }
     ProfScope ps(PS_SPLAT_FWD, s);
     if (a.splat_waves == 1) {
-        if (a.persistent)
-            hipLaunchKernelGGL(k_splat_fwd_persist<1>,
-                               dim3(persistent_grid(k_splat_fwd_persist<1>, 64, items)), dim3(64),
-                               0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
-                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
-                               a.L.nblk, cap, proj, queue);
-        else
-            hipLaunchKernelGGL(k_splat_fwd<1>, dim3((unsigned)items), dim3(64), 0, s, a.geom,
-                               a.n, a.T, WS(a, rec, const float4 *),
-                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
-                               a.L.nblk, cap, proj);
+        if (a.geom.ewa) launch_splat_fwd<1, true>(a, proj, queue, items, s);
+        else launch_splat_fwd<1, false>(a, proj, queue, items, s);
     } else {
-        if (a.persistent)
-            hipLaunchKernelGGL(k_splat_fwd_persist<4>,
-                               dim3(persistent_grid(k_splat_fwd_persist<4>, 256, items)),
-                               dim3(256), 0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
-                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
-                               a.L.nblk, cap, proj, queue);
-        else
-            hipLaunchKernelGGL(k_splat_fwd<4>, dim3((unsigned)items), dim3(256), 0, s, a.geom,
-                               a.n, a.T, WS(a, rec, const float4 *),
-                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
-                               a.L.nblk, cap, proj);
+        if (a.geom.ewa) launch_splat_fwd<4, true>(a, proj, queue, items, s);
+        else launch_splat_fwd<4, false>(a, proj, queue, items, s);
     }
     return hipGetLastError();
 }
@@ -1757,6 +1846,26 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     return e;
 }
 
+template <bool EWA>
+static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32_t *queue,
+                             size_t items, hipStream_t s)
+{
+    if (a.persistent)
+        hipLaunchKernelGGL(k_splat_bwd_persist<EWA>,
+                           dim3(persistent_grid(k_splat_bwd_persist<EWA>, 256, items)), dim3(256),
+                           0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                           WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
+                           (unsigned)a.L.cap, WS(a, rect, const int2 *),
+                           WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
+                           queue);
+    else
+        hipLaunchKernelGGL(k_splat_bwd<EWA>, dim3((unsigned)items), dim3(256), 0, s, a.geom, a.n,
+                           a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
+                           WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
+                           WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *), grad_proj,
+                           WS(a, part, float4 *));
+}
+
 hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
                            float *g_scale, float *g_quat, float *g_rho, float *g_coef,
                            float *g_w, hipStream_t s)
@@ -1771,20 +1880,8 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         ProfScope ps(PS_SPLAT_BWD, s);
-        if (a.persistent)
-            hipLaunchKernelGGL(k_splat_bwd_persist,
-                               dim3(persistent_grid(k_splat_bwd_persist, 256, items)), dim3(256),
-                               0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
-                               WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *),
-                               a.L.nblk, (unsigned)a.L.cap, WS(a, rect, const int2 *),
-                               WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
-                               queue);
-        else
-            hipLaunchKernelGGL(k_splat_bwd, dim3((unsigned)items), dim3(256), 0, s, a.geom, a.n,
-                               a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
-                               WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
-                               WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *),
-                               grad_proj, WS(a, part, float4 *));
+        if (a.geom.ewa) launch_splat_bwd<true>(a, grad_proj, queue, items, s);
+        else launch_splat_bwd<false>(a, grad_proj, queue, items, s);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;

@@ -51,6 +51,10 @@ def test_host_side_validation_and_sizes():
     assert lib.digs_workspace_size(ctypes.byref(bad_geom), ctypes.byref(R), 10, 1, None) == 0
     huge = _lib.make_geom(dict(p.geom, nu=2048, nv=2048))        # more than 4096 tiles
     assert lib.digs_workspace_size(ctypes.byref(huge), ctypes.byref(R), 10, 1, None) == 0
+    ewa = _lib.make_geom(dict(p.geom, model="ewa"))               # the EWA model: same layout
+    assert lib.digs_workspace_size(ctypes.byref(ewa), ctypes.byref(R), 4096, 16, None) == s1
+    ewa.model = 7                                                 # no such model
+    assert lib.digs_workspace_size(ctypes.byref(ewa), ctypes.byref(R), 10, 1, None) == 0
     # null pointers are rejected before any device work
     rc = lib.digs_project_fwd(ctypes.byref(G), ctypes.byref(R), None, 10, None, None, None, None,
                               1, None, None, None, None, 0, None, None)
