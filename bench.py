@@ -52,6 +52,33 @@ ALGO_BYTES_PER_PROJ = (2 * 200_000 * 44 + 3 * 29 ** 3 * 9 * 4 + 64 * 512 * 384 *
                        200_000 * 44) / 64.0
 
 
+# HBM bytes per launch of k_splat_bwd (the roofline kernel) from two rocprofv3 --pmc runs of this
+# bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
+# for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
+# library sources whose digest is given; reported only while the sources are unchanged
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2154893.1 * 2.0 * 1024,
+           "write_bytes": 7414265.5 * 1.0 * 1024,
+           "sources_sha256": "256693d2d5cafdcd85db4d1c411f6913f488a722687f5cd7273225974f9ebee2"}
+
+
+def sources_digest() -> str:
+    """sha256 over the library's HIP sources and headers, in name order."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2506_22280_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    if TRAFFIC["sources_sha256"] is None or TRAFFIC["sources_sha256"] != sources_digest():
+        return None
+    return int(TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"])
+
+
 def peak_tflops(flop, valu, trans):
     return LANE_OPS_PER_S * flop / (valu + TRANS_SLOTS * trans) / 1e12
 
@@ -159,21 +186,12 @@ def volume_leg(dev):
             "phi_ms": round(phi_ms, 4), "phi_brick_pairs": int(ws.diagnostics()["instances"])}
 
 
-def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: float):
-    """The batched fwd+bwd step under the EWA model of Eq. 4 (same phantom, batches and plan
-    machinery, its own autotuned plan), and the model's deviation from the exact line integral:
-    max |I_EWA - I_exact| / max I_exact over the first batch of the reference phantom's views."""
+def _plan_steps(G, Gd, n, est, ang, wts, meas, steps: int, warmup: int):
+    """Seconds per fwd+bwd step of an autotuned plan over the batches (ang, wts, meas), graph
+    replays between two synchronisations, and the plan's tuning."""
     import torch
     from paper_2506_22280_amd import _lib
-    dev = ang[0].device
-    G, Gd, n, B = dict(p.geom, model="ewa"), p.grid, p.n, ang[0].shape[0]
-    ws = _lib.Workspace(dev)
-    exact = _lib.project_fwd(p.geom, Gd, ref["coef"], ref["mu"], ref["scale"], ref["quat"],
-                             ref["rho"], ang[0], wts[0], ws).clone()
-    ewa = _lib.project_fwd(G, Gd, ref["coef"], ref["mu"], ref["scale"], ref["quat"], ref["rho"],
-                           ang[0], wts[0], ws)
-    dev_max = float((ewa - exact).abs().max() / exact.abs().max())
-    del ws, ewa, exact
+    dev, B = ang[0].device, ang[0].shape[0]
     proj = torch.empty((B, G["nv"], G["nu"]), device=dev)
     gradp = torch.zeros_like(proj)
     ang_buf, w_buf = ang[0].clone(), wts[0].clone()
@@ -207,7 +225,74 @@ def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: floa
     diag, resized = plan.check()
     plan.close()
     if resized or diag["overflow"] or diag["nonfinite"]:
-        raise SystemExit("EWA leg: diagnostics report a problem: %s" % diag)
+        raise SystemExit("diagnostics report a problem in a timed leg: %s" % diag)
+    return dt, tuning
+
+
+def _estimate(p, rng, d):
+    """The estimate being fitted: a perturbed copy of the reference phantom."""
+    return dict(mu=d(p.mu + rng.normal(0, 0.3, p.mu.shape)),
+                scale=d(p.scale * np.exp(rng.normal(0, 0.05, p.scale.shape))),
+                quat=d(p.quat + rng.normal(0, 0.05, p.quat.shape)),
+                rho=d(p.rho * (1 + rng.normal(0, 0.05, p.rho.shape))), coef=d(p.coef * 0.9))
+
+
+def large_leg(dev, steps: int, warmup: int):
+    """The large-volume configuration: 500k Gaussians, 1024x768 detector at 0.4 mm, rank-4 FFD at
+    5 mm, batches of 64 uneven-time views, fwd+bwd through an autotuned plan; with the volume
+    query (DVF and phi of a 256^3 grid) at every 10th projection, amortised per projection."""
+    from paper_2506_22280_amd import _lib, synth
+    p = synth.large(seed=0)
+    B = p.extra["batch"]
+    batches = [b for b in synth.batch_schedule(len(p.angles), B, 0) if len(b) == B][:4]
+
+    def d(a):
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+    ref = dict(coef=d(p.coef), mu=d(p.mu), scale=d(p.scale), quat=d(p.quat), rho=d(p.rho))
+    est = _estimate(p, np.random.default_rng(2), d)
+    ang = [d(p.angles[b]) for b in batches]
+    wts = [d(p.w[b]) for b in batches]
+    ws = _lib.Workspace(dev)
+    meas, tun, inst = [], None, 0
+    for k in range(len(batches)):
+        for _ in range(2):   # a second pass with the capacity the first one measured
+            img = _lib.project_fwd(p.geom, p.grid, ref["coef"], ref["mu"], ref["scale"],
+                                   ref["quat"], ref["rho"], ang[k], wts[k], ws, tuning=tun)
+            dg = ws.diagnostics()
+            if not dg["overflow"]:
+                break
+            tun = dict(capacity=int(dg["instances"] * 1.25) + 4096)
+            ws.reset()
+        if dg["overflow"]:
+            raise SystemExit("large leg: instance capacity exceeded")
+        meas.append(img.clone())
+        inst = max(inst, dg["instances"])
+    del ws
+    dt, tuning = _plan_steps(p.geom, p.grid, p.n, est, ang, wts, meas, steps, warmup)
+    return {"gaussians": p.n, "detector": [p.geom["nu"], p.geom["nv"]], "batch": B,
+            "ms_per_step": round(dt * 1e3, 3), "projections_per_s": round(B / dt, 2),
+            "instances_per_view": int(inst / B),
+            "tuning": {k: tuning[k] for k in ("splat_waves", "persistent", "capacity")}}
+
+
+def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: float):
+    """The batched fwd+bwd step under the EWA model of Eq. 4 (same phantom, batches and plan
+    machinery, its own autotuned plan), and the model's deviation from the exact line integral:
+    max |I_EWA - I_exact| / max I_exact over the first batch of the reference phantom's views."""
+    import torch
+    from paper_2506_22280_amd import _lib
+    dev = ang[0].device
+    G, Gd, n, B = dict(p.geom, model="ewa"), p.grid, p.n, ang[0].shape[0]
+    ws = _lib.Workspace(dev)
+    exact = _lib.project_fwd(p.geom, Gd, ref["coef"], ref["mu"], ref["scale"], ref["quat"],
+                             ref["rho"], ang[0], wts[0], ws).clone()
+    ewa = _lib.project_fwd(G, Gd, ref["coef"], ref["mu"], ref["scale"], ref["quat"], ref["rho"],
+                           ang[0], wts[0], ws)
+    dev_max = float((ewa - exact).abs().max() / exact.abs().max())
+    del ws, ewa, exact
+    dt, tuning = _plan_steps(G, Gd, n, est, ang, wts, meas, steps, warmup)
     return {"ms_per_step": round(dt * 1e3, 3), "projections_per_s": round(B / dt, 2),
             "speedup_vs_exact": round(exact_ms / (dt * 1e3), 3),
             "max_dev_vs_exact_rel_to_max": round(dev_max, 6),
@@ -250,13 +335,7 @@ def main():
     # reference phantom -> measured projections; the estimate being fitted is a perturbed copy
     rng = np.random.default_rng(args.seed + 1)
     ref = dict(coef=d(p.coef), mu=d(p.mu), scale=d(p.scale), quat=d(p.quat), rho=d(p.rho))
-    est_np = (p.mu + rng.normal(0, 0.3, p.mu.shape).astype(np.float32),
-              p.scale * np.exp(rng.normal(0, 0.05, p.scale.shape)).astype(np.float32),
-              p.quat + rng.normal(0, 0.05, p.quat.shape).astype(np.float32),
-              p.rho * (1 + rng.normal(0, 0.05, p.rho.shape)).astype(np.float32),
-              p.coef * np.float32(0.9))
-    est = dict(mu=d(est_np[0]), scale=d(est_np[1]), quat=d(est_np[2]), rho=d(est_np[3]),
-               coef=d(est_np[4]))
+    est = _estimate(p, rng, d)
     ang = [d(p.angles[b]) for b in batches]
     wts = [d(p.w[b]) for b in batches]
     ws = _lib.Workspace(dev)
@@ -366,6 +445,7 @@ def main():
                                   "views, rank-3 FFD on 29^3 (10 mm)",
                       "global_batch": B, "gaussians": n, "detector": [G["nu"], G["nv"]],
                       "parallelism": "single GPU"}}
+    out["sources_sha256"] = sources_digest()
     out["tuning"] = {"chosen": {k: tuning[k] for k in ("splat_waves", "persistent", "capacity")},
                      "candidates_fwd_bwd_ms": {"w%d_p%d" % (w_, p_): [round(x, 3) for x in ms]
                                                for (w_, p_), ms in zip(((4, 0), (4, 1), (1, 0),
@@ -389,7 +469,8 @@ def main():
         peak = peak_tflops(flop, valu, trans)
         out["roofline"] = {"kernel": "k_" + dom, "bound": "alu", "achieved": round(achieved, 3),
                            "peak": round(peak, 2), "unit": "TFLOP/s",
-                           "frac": round(achieved / peak, 4), "traffic": None,
+                           "frac": round(achieved / peak, 4),
+                           "traffic": traffic_bytes() if dom == "splat_bwd" else None,
                            "avg_launch_ms": round(avg_s * 1e3, 4),
                            "pairs_per_launch": int(per_launch_pairs),
                            "flop_per_pair": flop}
@@ -402,6 +483,11 @@ def main():
                                    ref, dt / args.steps * 1e3)
         out["single_view_50k"] = single_view_leg(dev)
         out["volume_query_500k_256cubed"] = volume_leg(dev)
+        lg = large_leg(dev, 5, 2)
+        vq = out["volume_query_500k_256cubed"]
+        lg["ms_per_projection_with_volume_query_every_10th"] = round(
+            lg["ms_per_step"] / lg["batch"] + (vq["dvf_ms"] + vq["phi_ms"]) / 10.0, 4)
+        out["large_500k_1024x768"] = lg
     if not args.no_warmstart:
         # "speedup vs plain": the learned warm start against the plain per-projection fit, time
         # to the same residual tolerance on views of unseen phantoms of the same family and size
@@ -423,7 +509,8 @@ def main():
             "test_views": ws_out["test_views"], "train_pairs": ws_out["train_pairs"],
             "fallbacks": ws_out["warm"]["fallbacks"]}
     if not args.no_cpu_baseline:
-        params = tuple(x.astype(np.float64) for x in est_np[:4]) + (est_np[4],)
+        params = tuple(est[k].double().cpu().numpy() for k in ("mu", "scale", "quat", "rho")) + (
+            est["coef"].double().cpu().numpy(),)
         out["cpu_baseline"] = cpu_baseline(p, params, batches[0])
     print(json.dumps(out), flush=True)
 
