@@ -277,6 +277,21 @@ def large_leg(dev, steps: int, warmup: int):
             "tuning": {k: tuning[k] for k in ("splat_waves", "persistent", "capacity")}}
 
 
+def recon_leg(iters: int = 3000):
+    """The reconstruction loop (Sec. 4.2) at the paper's acquisition (Sec. 4.1): 80k Gaussians,
+    310 noisy views of 512x512 at 0.8 mm, detector offset 116 mm, SDD 1536 mm, rank 2 on an 8 mm
+    lattice, one view per iteration, from a perturbed start without motion; time per iteration,
+    the projected time of the paper's 50K iterations, and the dynamic volume's PSNR/RMSE against
+    the ground truth before and after `iters` iterations."""
+    from paper_2506_22280_amd import recon, synth
+    p = synth.paper_case(seed=0)
+    out = recon.experiment(p, iters, motion="zero", noise=True, seed=0)
+    out["projected_50k_iterations_s"] = round(out["ms_per_iter"] * 50.0, 1)
+    out["workload"] = ("80k Gaussians, 310 views 512x512 at 0.8 mm, offset 116 mm, SDD 1536, "
+                       "rank 2 / 8 mm, 1 view per iteration, Poisson 1e8 + Gaussian 4 noise")
+    return out
+
+
 def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: float):
     """The batched fwd+bwd step under the EWA model of Eq. 4 (same phantom, batches and plan
     machinery, its own autotuned plan), and the model's deviation from the exact line integral:
@@ -488,6 +503,7 @@ def main():
         lg["ms_per_projection_with_volume_query_every_10th"] = round(
             lg["ms_per_step"] / lg["batch"] + (vq["dvf_ms"] + vq["phi_ms"]) / 10.0, 4)
         out["large_500k_1024x768"] = lg
+        out["reconstruction_paper_case"] = recon_leg()
     if not args.no_warmstart:
         # "speedup vs plain": the learned warm start against the plain per-projection fit, time
         # to the same residual tolerance on views of unseen phantoms of the same family and size

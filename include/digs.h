@@ -274,6 +274,22 @@ int digs_downsample(int T, int nv, int nu, int fy, int fx, const float *proj,
 int digs_standardize(int M, int N, float *X, int ldx, const float *mean, const float *istd,
                      void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * The reconstruction loop around the renderer (Sec. 4.2: the Gaussians and the space and time
+ * B-spline grids updated jointly by Adam on the L2 projection loss). Device pointers, float32;
+ * asynchronous on `stream`.
+ * digs_l2_residual: grad[i] = proj[i] - meas[i] for i < n (dL/dproj of L = 1/2 ||proj - meas||^2)
+ *   and, if loss is not NULL, loss[0] = L (one workgroup, fixed summation order).
+ * digs_adam_mapped: one bias-corrected Adam step (step >= 1) on n unconstrained parameters raw
+ *   given dL/dvalue, where value = map(raw): map 0 identity (value must equal raw), 1 exp (for
+ *   scales), 2 softplus (for densities); the chain rule is applied to the gradient, then raw is
+ *   updated and value rewritten from it. m, v: the moments (zero before step 1).
+ * Errors: DIGS_EINVAL, DIGS_EHIP. */
+int digs_l2_residual(int64_t n, const float *proj, const float *meas, float *grad, float *loss,
+                     void *stream);
+int digs_adam_mapped(int n, float *raw, float *value, const float *g_value, float *m, float *v,
+                     float lr, float b1, float b2, float eps, int step, int map, void *stream);
+
 /* Diagnostics of a workspace: digs_read_diagnostics synchronises `stream` and copies the block
  * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). */
 int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);

@@ -133,6 +133,10 @@ _SIGS = {
                                       ctypes.c_int, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
     "digs_colsum": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP, _VP]),
     "digs_mse": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "digs_l2_residual": (ctypes.c_int, [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]),
+    "digs_adam_mapped": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, _VP, _VP, ctypes.c_float,
+                                        ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_int, ctypes.c_int, _VP]),
     "digs_adam": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_int, _VP]),
     "digs_downsample": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -480,6 +484,23 @@ def adam(w, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
     _check("digs_adam", load().digs_adam(w.numel(), _ptr(w), _ptr(g), _ptr(m), _ptr(v),
                                          float(lr), float(b1), float(b2), float(eps), int(step),
                                          _stream(stream)))
+
+
+MAPS = {"identity": 0, "exp": 1, "softplus": 2}
+
+
+def l2_residual(proj, meas, grad, loss=None, stream=None):
+    """grad = proj - meas and (if loss, a device [1] tensor) loss[0] = 1/2 ||proj - meas||^2."""
+    _check("digs_l2_residual", load().digs_l2_residual(proj.numel(), _ptr(proj), _ptr(meas),
+                                                       _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def adam_mapped(raw, value, g_value, m, v, lr, step, mapping="identity", b1=0.9, b2=0.999,
+                eps=1e-8, stream=None):
+    """One Adam step on raw given dL/dvalue, value = mapping(raw) (rewritten)."""
+    _check("digs_adam_mapped", load().digs_adam_mapped(
+        raw.numel(), _ptr(raw), _ptr(value), _ptr(g_value), _ptr(m), _ptr(v), float(lr),
+        float(b1), float(b2), float(eps), int(step), MAPS[mapping], _stream(stream)))
 
 
 def downsample(proj, fy: int, fx: int, angles=None, scale=1.0, fmean=None, fistd=None, out=None,
