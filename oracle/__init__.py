@@ -13,6 +13,8 @@ Functions mirror the product's entry points in argument meaning (not in precisio
   ewa_gaussian    Eq. 4       one Gaussian's 2D mean, covariance and scaled density
   project_pixels              the same at a list of sampled pixels
   project_bwd                 reverse mode of ``project`` for a sparse dL/dI
+                  Sec. 4.3    with ``basis`` (project, project_pixels, project_bwd): the second
+                              ablation's motion model, a basis stored per Gaussian
   line_integral               one Gaussian along one line
   dvf, phi        Eq. 9, 6    displacement field and dynamic attenuation at query points
   temporal_weights            the 1-D cubic B-spline w_r(t) of the temporal control values, and
@@ -45,7 +47,7 @@ def build(force: bool = True) -> str:
 class Grid(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
                 ("nz", ctypes.c_int), ("origin", ctypes.c_double * 3),
-                ("spacing", ctypes.c_double * 3)]
+                ("spacing", ctypes.c_double * 3), ("basis", ctypes.POINTER(ctypes.c_double))]
 
 
 class Geom(ctypes.Structure):
@@ -157,9 +159,24 @@ def deform(grid: dict, coef, mu, scale, quat, w):
     return mu_t, cov_t
 
 
-def project(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w):
-    """proj[T][nv][nu]: the sum of every Gaussian's closed-form line integral (no cut-off)."""
+def _with_basis(g: Grid, basis, n):
+    """Point g at a per-Gaussian basis [R][12][n] (returns the array to keep alive)."""
+    if basis is None:
+        return None
+    b = np.ascontiguousarray(basis, dtype=np.float64)
+    assert b.shape == (g.R, 12, n), b.shape
+    g.basis = b.ctypes.data_as(_P)
+    return b
+
+
+def project(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, basis=None):
+    """proj[T][nv][nu]: the sum of every Gaussian's closed-form line integral (no cut-off).
+    basis [R][12][n]: the per-Gaussian motion basis of the second ablation instead of the FFD
+    (coef is then ignored and may be None)."""
     G, g = make_geom(geom), make_grid(grid)
+    keep = _with_basis(g, basis, np.shape(mu)[1])
+    if coef is None:
+        coef = np.zeros(1)
     coef, pc = _d(coef); mu, pm = _d(mu); scale, ps = _d(scale); quat, pq = _d(quat)
     rho, pr = _d(rho); angles, pa = _d(np.atleast_1d(angles)); w, pw = _d(np.atleast_2d(w))
     n, T = mu.shape[1], angles.shape[0]
@@ -167,6 +184,7 @@ def project(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w):
     out = np.zeros((T, G.nv, G.nu))
     rc = _load().oracle_project(ctypes.byref(G), ctypes.byref(g), pc, n, pm, ps, pq, pr, T, pa,
                                 pw, out.ctypes.data_as(_P))
+    del keep
     if rc != 0:
         raise MemoryError("oracle_project failed")
     return out
@@ -189,10 +207,14 @@ def project_pixels(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w
 
 
 def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, grad_proj=None,
-                pixels=None):
+                pixels=None, basis=None):
     """Gradients of L with dL/dI given densely (grad_proj[T][nv][nu]) or sparsely
-    (pixels = (pt, pj, pi, g)). Returns dict g_mu, g_scale, g_quat, g_rho, g_coef, g_w."""
+    (pixels = (pt, pj, pi, g)). Returns dict g_mu, g_scale, g_quat, g_rho, g_coef, g_w; with a
+    per-Gaussian basis [R][12][n], g_basis replaces g_coef."""
     G, g = make_geom(geom), make_grid(grid)
+    keep = _with_basis(g, basis, np.shape(mu)[1])
+    if coef is None:
+        coef = np.zeros(1)
     coef, pc = _d(coef); mu, pm = _d(mu); scale, ps = _d(scale); quat, pq = _d(quat)
     rho, pr = _d(rho); angles, pa = _d(np.atleast_1d(angles)); w, pw = _d(np.atleast_2d(w))
     n, T = mu.shape[1], angles.shape[0]
@@ -204,15 +226,19 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
         pt, pj, pi, pg = pixels
     pt, ppt = _i(pt); pj, ppj = _i(pj); pi, ppi = _i(pi); pg, ppg = _d(pg)
     out = dict(g_mu=np.zeros((3, n)), g_scale=np.zeros((3, n)), g_quat=np.zeros((4, n)),
-               g_rho=np.zeros(n), g_coef=np.zeros_like(coef), g_w=np.zeros((T, g.R)))
+               g_rho=np.zeros(n), g_coef=np.zeros_like(coef) if keep is None else
+               np.zeros((g.R, 12, n)), g_w=np.zeros((T, g.R)))
     if G.model != 0:
         raise ValueError("the oracle's reverse mode covers the exact model only")
     rc = _load().oracle_project_bwd(
         ctypes.byref(G), ctypes.byref(g), pc, n, pm, ps, pq, pr, T, pa, pw, pt.shape[0], ppt,
         ppj, ppi, ppg, *[out[k].ctypes.data_as(_P) for k in
                          ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef", "g_w")])
+    del keep
     if rc != 0:
         raise MemoryError("oracle_project_bwd failed")
+    if basis is not None:
+        out["g_basis"] = out.pop("g_coef")
     return out
 
 

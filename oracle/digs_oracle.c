@@ -52,6 +52,10 @@ typedef struct {
     int R, nx, ny, nz;
     double origin[3];
     double spacing[3];
+    /* NULL: the motion basis is the lattice's FFD (Eq. 10-11). Otherwise the paper's second
+     * ablation (Sec. 4.3): a basis stored per Gaussian, basis[R][12][n] with rows 0..2 the
+     * displacement u_{n,r} and rows 3..11 the matrix V_{n,r} (row-major) that replaces grad u_r */
+    const double *basis;
 } oracle_grid;
 
 typedef struct {
@@ -282,14 +286,34 @@ typedef struct {
     double A[3][3];      /* Sigma'^-1                                         */
 } gauss_state;
 
-static void deform_one(const oracle_grid *g, const double *coef, const double mu[3],
+/* rank r of the motion basis at Gaussian k (of n) with canonical mean mu: u_r, grad u_r and (if
+ * H is not NULL) its derivative; a per-Gaussian basis does not depend on mu (H = 0) */
+static void motion_point(const oracle_grid *g, const double *coef, int r, int k, int n,
+                         const double mu[3], double u[3], double J[3][3], double H[3][3][3])
+{
+    if (!g->basis) {
+        ffd_point(g, coef, r, mu, u, J, H);
+        return;
+    }
+    const double *b = g->basis + (size_t)r * 12 * n + k;
+    for (int a = 0; a < 3; ++a) {
+        u[a] = b[(size_t)a * n];
+        for (int c = 0; c < 3; ++c) {
+            J[a][c] = b[(size_t)(3 + 3 * a + c) * n];
+            if (H)
+                for (int e = 0; e < 3; ++e) H[a][c][e] = 0.0;
+        }
+    }
+}
+
+static void deform_one(const oracle_grid *g, const double *coef, int k, int n, const double mu[3],
                        const double s[3], const double q[4], const double *w_t, gauss_state *st)
 {
     double K[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     double mt[3] = {mu[0], mu[1], mu[2]};
     for (int r = 0; r < g->R; ++r) {
         double u[3], J[3][3];
-        ffd_point(g, coef, r, mu, u, J, NULL);
+        motion_point(g, coef, r, k, n, mu, u, J, NULL);
         for (int a = 0; a < 3; ++a) {
             mt[a] += w_t[r] * u[a];
             for (int b = 0; b < 3; ++b) K[a][b] += w_t[r] * J[a][b];
@@ -321,7 +345,7 @@ void oracle_deform(const oracle_grid *g, const double *coef, int n, const double
             double s[3] = {scale[i], scale[n + i], scale[2 * n + i]};
             double q[4] = {quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i]};
             gauss_state st;
-            deform_one(g, coef, m, s, q, w + (size_t)t * g->R, &st);
+            deform_one(g, coef, i, n, m, s, q, w + (size_t)t * g->R, &st);
             for (int a = 0; a < 3; ++a) mu_t[((size_t)t * 3 + a) * n + i] = st.mu_t[a];
             const int pk[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
             for (int c = 0; c < 6; ++c)
@@ -491,7 +515,7 @@ static gauss_state *deform_all(const oracle_grid *g, const double *coef, int n, 
             double m[3] = {mu[i], mu[n + i], mu[2 * n + i]};
             double s[3] = {scale[i], scale[n + i], scale[2 * n + i]};
             double q[4] = {quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i]};
-            deform_one(g, coef, m, s, q, w + (size_t)t * g->R, &st[(size_t)t * n + i]);
+            deform_one(g, coef, i, n, m, s, q, w + (size_t)t * g->R, &st[(size_t)t * n + i]);
         }
     return st;
 }
@@ -708,7 +732,7 @@ int oracle_project_bwd(const oracle_geom *G, const oracle_grid *g, const double 
         }
 
     /* step 2: through Sigma0 = R diag(s^2) R^T, the quaternion, and D(mu,t) of Eq. 9-11 */
-    memset(g_coef, 0, sizeof(double) * (size_t)g->R * g->nz * g->ny * g->nx * 3);
+    if (!g->basis) memset(g_coef, 0, sizeof(double) * (size_t)g->R * g->nz * g->ny * g->nx * 3);
     memset(g_w, 0, sizeof(double) * (size_t)T * g->R);
     for (int k = 0; k < n; ++k) {
         double m0[3] = {mu[k], mu[n + k], mu[2 * n + k]};
@@ -721,7 +745,7 @@ int oracle_project_bwd(const oracle_geom *G, const oracle_grid *g, const double 
         memset(P, 0, sizeof P);
         memset(Q, 0, sizeof Q);
         double U[8][3], J[8][3][3], H[8][3][3][3];
-        for (int r = 0; r < g->R; ++r) ffd_point(g, coef, r, m0, U[r], J[r], H[r]);
+        for (int r = 0; r < g->R; ++r) motion_point(g, coef, r, k, n, m0, U[r], J[r], H[r]);
         for (int t = 0; t < T; ++t) {
             const gauss_grad *gr = &gg[(size_t)t * n + k];
             const double *wt = w + (size_t)t * g->R;
@@ -743,17 +767,26 @@ int oracle_project_bwd(const oracle_geom *G, const oracle_grid *g, const double 
                 g_w[(size_t)t * g->R + r] += gw;
             }
         }
-        /* mu' = mu + sum_r w_r u_r(mu); K = I + sum_r w_r grad u_r(mu) */
-        for (int r = 0; r < g->R; ++r)
+        /* mu' = mu + sum_r w_r u_r(mu); K = I + sum_r w_r grad u_r(mu) (a per-Gaussian basis
+         * does not depend on mu: mu' - mu and K carry no further mu-dependence) */
+        for (int r = 0; r < g->R && !g->basis; ++r)
             for (int c = 0; c < 3; ++c)
                 for (int a = 0; a < 3; ++a) {
                     gmu[c] += J[r][a][c] * P[r][a];
                     for (int b = 0; b < 3; ++b) gmu[c] += Q[r][a][b] * H[r][a][b][c];
                 }
+        if (g->basis) {   /* dL/du_{n,r} = P_r, dL/dV_{n,r} = Q_r (written into g_coef) */
+            for (int r = 0; r < g->R; ++r)
+                for (int a = 0; a < 3; ++a) {
+                    g_coef[((size_t)r * 12 + a) * n + k] = P[r][a];
+                    for (int b = 0; b < 3; ++b)
+                        g_coef[((size_t)r * 12 + 3 + 3 * a + b) * n + k] = Q[r][a][b];
+                }
+        }
         /* coefficients: u_r and grad u_r are linear in d^r */
         stencil sc;
-        make_stencil(g, m0, &sc);
-        for (int nn = 0; nn < 4; ++nn)
+        if (!g->basis) make_stencil(g, m0, &sc);
+        for (int nn = 0; nn < 4 && !g->basis; ++nn)
             for (int mm = 0; mm < 4; ++mm)
                 for (int l = 0; l < 4; ++l) {
                     double wt, dw[3];

@@ -616,3 +616,58 @@ def test_temporal_weights_pins(oracle_mod):
     lhs = (gw * oracle_mod.temporal_weights(c, t0, dt, times)).sum()
     rhs = (oracle_mod.temporal_weights_bwd(Ct, t0, dt, times, gw) * c).sum()
     assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+# ------------------------------------------------------------------------------------------------
+# The second ablation's motion model (Sec. 4.3): a spatial basis stored per Gaussian
+def _ffd_as_basis(oracle_mod, grid, coef, mu):
+    """The per-Gaussian basis that reproduces the lattice's FFD at the canonical means."""
+    U, V = oracle_mod.ffd_eval(grid, coef, mu)
+    return np.concatenate([U, V], axis=1)          # [R][12][n]
+
+
+def test_basis_model_reproduces_the_ffd_forward_and_pins_its_gradients(oracle_mod):
+    p = synth.tiny(seed=13, n=60, nviews=3, det=24)
+    geom = dict(p.geom, pitch_u=2.5, pitch_v=2.5)
+    args = (p.mu, p.scale, p.quat, p.rho, p.angles, p.w)
+    basis = _ffd_as_basis(oracle_mod, p.grid, p.coef, p.mu)
+    ref = oracle_mod.project(geom, p.grid, p.coef, *args)
+    got = oracle_mod.project(geom, p.grid, None, *args, basis=basis)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # zero basis: no motion at all
+    static = oracle_mod.project(geom, p.grid, np.zeros_like(p.coef), *args)
+    np.testing.assert_allclose(oracle_mod.project(geom, p.grid, None, *args,
+                                                  basis=np.zeros_like(basis)), static,
+                               rtol=1e-13, atol=1e-15)
+    # gradients against central differences of the basis forward (FP64)
+    rng = np.random.default_rng(14)
+    c = rng.normal(0, 1, ref.shape)
+    g = oracle_mod.project_bwd(geom, p.grid, None, *args, grad_proj=c, basis=basis)
+
+    def loss(**kw):
+        q = dict(mu=p.mu, scale=p.scale, quat=p.quat, rho=p.rho, w=p.w, basis=basis)
+        q.update(kw)
+        img = oracle_mod.project(geom, p.grid, None, q["mu"], q["scale"], q["quat"], q["rho"],
+                                 p.angles, q["w"], basis=q["basis"])
+        return float((img * c).sum())
+
+    # (steps large enough that the FP64 cancellation in c - b^2/a, ~1e-10 of L, stays small)
+    for name, arr, h in (("basis", basis, 1e-3), ("mu", p.mu, 1e-3), ("w", p.w, 1e-3)):
+        flat = np.asarray(arr, dtype=np.float64).ravel()
+        gk = g["g_" + name].ravel()
+        idx = np.argsort(-np.abs(gk))[:12]
+        for e in idx:
+            up, dn = flat.copy(), flat.copy()
+            up[e] += h
+            dn[e] -= h
+            fd = (loss(**{name: up.reshape(np.shape(arr))}) -
+                  loss(**{name: dn.reshape(np.shape(arr))})) / (2 * h)
+            assert abs(fd - gk[e]) <= 1e-6 * np.abs(gk).max(), (name, e, fd, gk[e])
+    # per view, the deformation is linear in (w_r, basis_r): w_r dL/dw_r = <basis_r, dL/dbasis_r>
+    for t in range(3):
+        g1 = oracle_mod.project_bwd(geom, p.grid, None, *args[:4], p.angles[t:t + 1],
+                                    p.w[t:t + 1], grad_proj=c[t:t + 1], basis=basis)
+        for r in range(p.grid["R"]):
+            lhs = p.w[t, r] * g1["g_w"][0, r]
+            rhs = (basis[r] * g1["g_basis"][r]).sum()
+            assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs))
