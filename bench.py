@@ -292,6 +292,53 @@ def recon_leg(iters: int = 3000):
     return out
 
 
+def basis_leg(p, est, ang, wts, meas, steps: int, tuning: dict):
+    """The second ablation's motion model (Sec. 4.3: the spatial basis stored per Gaussian, no
+    lattice) against the lattice model, both as eager fwd+bwd calls on the same batches (the plan
+    path covers the lattice model only), HIP events around `steps` steps each."""
+    import torch
+    from paper_2506_22280_amd import _lib
+    dev = ang[0].device
+    G, Gd, n, B = p.geom, p.grid, p.n, ang[0].shape[0]
+    ws = _lib.Workspace(dev)
+    U, J = _lib.ffd_eval(Gd, est["coef"], est["mu"])          # per-rank u and grad u at the means
+    basis = torch.cat([U, J], dim=1).contiguous()             # [R][12][n]
+    proj = torch.empty((B, G["nv"], G["nu"]), device=dev)
+    gradp = torch.empty_like(proj)
+    g_l = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
+               g_quat=torch.empty((4, n), device=dev), g_rho=torch.empty((n,), device=dev),
+               g_coef=torch.empty_like(est["coef"]), g_w=torch.empty((B, Gd["R"]), device=dev))
+    g_b = dict(g_l, g_basis=torch.empty_like(basis))
+    del g_b["g_coef"]
+    state = {"k": 0}
+
+    def lattice_step():
+        kb = state["k"] % len(ang)
+        state["k"] += 1
+        _lib.project_fwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], ws, tuning=tuning, proj=proj)
+        torch.sub(proj, meas[kb], out=gradp)
+        _lib.project_bwd(G, Gd, est["coef"], est["mu"], est["scale"], est["quat"], est["rho"],
+                         ang[kb], wts[kb], gradp, ws, tuning=tuning, reuse_fwd=True, out=g_l)
+
+    def basis_step():
+        kb = state["k"] % len(ang)
+        state["k"] += 1
+        _lib.project_basis_fwd(G, Gd, basis, est["mu"], est["scale"], est["quat"], est["rho"],
+                               ang[kb], wts[kb], ws, tuning=tuning, proj=proj)
+        torch.sub(proj, meas[kb], out=gradp)
+        _lib.project_basis_bwd(G, Gd, basis, est["mu"], est["scale"], est["quat"], est["rho"],
+                               ang[kb], wts[kb], gradp, ws, tuning=tuning, reuse_fwd=True,
+                               out=g_b)
+
+    lat_ms = _time_ms(lattice_step, steps)
+    bas_ms = _time_ms(basis_step, steps)
+    return {"eager_ms_per_step_lattice": round(lat_ms, 3),
+            "eager_ms_per_step_basis": round(bas_ms, 3),
+            "projections_per_s_basis": round(B / bas_ms * 1e3, 2),
+            "basis_floats_per_gaussian": 12 * Gd["R"]}
+
+
 def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: float):
     """The batched fwd+bwd step under the EWA model of Eq. 4 (same phantom, batches and plan
     machinery, its own autotuned plan), and the model's deviation from the exact line integral:
@@ -496,6 +543,8 @@ def main():
     if not args.no_extra:
         out["ewa_model"] = ewa_leg(p, est, ang, wts, meas, max(5, args.steps // 2), args.warmup,
                                    ref, dt / args.steps * 1e3)
+        out["basis_model"] = basis_leg(p, est, ang, wts, meas, max(5, args.steps // 2),
+                                       eager_tuning)
         out["single_view_50k"] = single_view_leg(dev)
         out["volume_query_500k_256cubed"] = volume_leg(dev)
         lg = large_leg(dev, 5, 2)

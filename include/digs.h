@@ -173,6 +173,27 @@ int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, const float *
                      float *g_w, void *ws, size_t ws_bytes, const digs_tuning *tuning, int flags,
                      void *stream);
 
+/* digs_project_basis_fwd / digs_project_basis_bwd -- the same forward and adjoint with the
+ * motion model of the paper's second ablation (Sec. 4.3): the spatial basis is stored per
+ * Gaussian instead of being interpolated from the control lattice, so for every (t, n)
+ *   mu' = mu + sum_r w_r(t) u_{n,r},  K = I + sum_r w_r(t) V_{n,r},  Sigma' = K Sigma K^T.
+ *   basis [R][12][n]: rows 0..2 u_{n,r} (mm per unit weight), rows 3..11 V_{n,r} row-major.
+ *   grid: R and the lattice geometry, used only to order the Gaussians by cell for memory
+ *   locality (no coefficients are read). Workspace as digs_project_fwd (same size).
+ *   g_basis [R][12][n] = dL/dbasis; g_mu has no lattice terms. Other arguments, layouts and
+ *   errors as digs_project_fwd / digs_project_bwd. */
+int digs_project_basis_fwd(const digs_geom *geom, const digs_grid *grid, const float *basis,
+                           int n, const float *mu, const float *scale, const float *quat,
+                           const float *rho, int T, const float *angles, const float *w,
+                           float *proj, void *ws, size_t ws_bytes, const digs_tuning *tuning,
+                           void *stream);
+int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const float *basis,
+                           int n, const float *mu, const float *scale, const float *quat,
+                           const float *rho, int T, const float *angles, const float *w,
+                           const float *grad_proj, float *g_mu, float *g_scale, float *g_quat,
+                           float *g_rho, float *g_basis, float *g_w, void *ws, size_t ws_bytes,
+                           const digs_tuning *tuning, int flags, void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Plans: the batched path. A plan fixes the shapes (geometry, lattice, N, T) and the device
  * buffers below; it owns its workspace and replays the forward and the backward as HIP graphs

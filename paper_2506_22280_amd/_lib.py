@@ -97,6 +97,15 @@ _SIGS = {
                                         ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
                                         _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                         ctypes.POINTER(Tuning), ctypes.c_int, _VP]),
+    "digs_project_basis_fwd": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _VP,
+                                              ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int,
+                                              _VP, _VP, _VP, _VP, ctypes.c_size_t,
+                                              ctypes.POINTER(Tuning), _VP]),
+    "digs_project_basis_bwd": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _VP,
+                                              ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int,
+                                              _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                              ctypes.c_size_t, ctypes.POINTER(Tuning),
+                                              ctypes.c_int, _VP]),
     "digs_read_diagnostics": (ctypes.c_int, [_VP, ctypes.POINTER(Diag), _VP]),
     "digs_reset_diagnostics": (ctypes.c_int, [_VP, _VP]),
     "digs_count_pairs": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), ctypes.c_int,
@@ -351,6 +360,55 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
         ctypes.byref(G), ctypes.byref(R), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat),
         _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(grad_proj), _ptr(out["g_mu"]),
         _ptr(out["g_scale"]), _ptr(out["g_quat"]), _ptr(out["g_rho"]), _ptr(out["g_coef"]),
+        _ptr(out["g_w"]), _ptr(buf), buf.numel(), _byref(Tu),
+        DIGS_BWD_REUSE_FWD if reuse_fwd else 0, _stream(stream)))
+    if not reuse_fwd:
+        ws.touched()
+    return out
+
+
+def project_basis_fwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angles, w,
+                      ws: Workspace, tuning: dict | None = None, proj=None, stream=None):
+    """The forward with the second ablation's motion model: basis [R][12][n] per Gaussian
+    instead of the lattice (grid gives R and the lattice geometry that orders the Gaussians)."""
+    n, T = mu.shape[1], angles.shape[0]
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
+    if nbytes == 0:
+        raise DigsError("digs_workspace_size", -1)
+    buf = ws.get(nbytes)
+    if proj is None:
+        proj = torch.empty((T, geom["nv"], geom["nu"]), device=mu.device, dtype=torch.float32)
+    _check("digs_project_basis_fwd", load().digs_project_basis_fwd(
+        ctypes.byref(G), ctypes.byref(R), _ptr(basis), n, _ptr(mu), _ptr(scale), _ptr(quat),
+        _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(proj), _ptr(buf), buf.numel(), _byref(Tu),
+        _stream(stream)))
+    ws.touched()
+    return proj
+
+
+def project_basis_bwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angles, w, grad_proj,
+                      ws: Workspace, tuning: dict | None = None, reuse_fwd: bool = False,
+                      out=None, stream=None):
+    """dL/d(mu, scale, quat, rho, basis, w) of the basis model (reuse_fwd: ws holds the state
+    of a project_basis_fwd with the same inputs)."""
+    n, T = mu.shape[1], angles.shape[0]
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
+    if nbytes == 0:
+        raise DigsError("digs_workspace_size", -1)
+    if reuse_fwd and (ws.buf is None or ws.buf.numel() < nbytes):
+        reuse_fwd = False
+    buf = ws.get(nbytes)
+    dev = mu.device
+    if out is None:
+        out = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
+                   g_quat=torch.empty((4, n), device=dev), g_rho=torch.empty((n,), device=dev),
+                   g_basis=torch.empty_like(basis), g_w=torch.empty((T, grid["R"]), device=dev))
+    _check("digs_project_basis_bwd", load().digs_project_basis_bwd(
+        ctypes.byref(G), ctypes.byref(R), _ptr(basis), n, _ptr(mu), _ptr(scale), _ptr(quat),
+        _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(grad_proj), _ptr(out["g_mu"]),
+        _ptr(out["g_scale"]), _ptr(out["g_quat"]), _ptr(out["g_rho"]), _ptr(out["g_basis"]),
         _ptr(out["g_w"]), _ptr(buf), buf.numel(), _byref(Tu),
         DIGS_BWD_REUSE_FWD if reuse_fwd else 0, _stream(stream)))
     if not reuse_fwd:

@@ -212,6 +212,7 @@ static int prepare(const digs_geom *geom, const digs_grid *grid, const float *co
     a->geom = make_dev_geom(geom);
     a->grid = make_dev_grid(grid);
     a->coef = coef;
+    a->basis = nullptr;
     a->mu = mu;
     a->scale = scale;
     a->quat = quat;
@@ -279,6 +280,65 @@ extern "C" int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, co
     if (!(flags & DIGS_BWD_REUSE_FWD)) e = render_forward_setup(a, s);
     if (e == hipSuccess)
         e = render_backward(a, grad_proj, g_mu, g_scale, g_quat, g_rho, g_coef, g_w, s);
+    return check(e);
+}
+
+// The second ablation's motion model (per-Gaussian basis instead of the lattice): the same
+// forward and adjoint with U, V gathered from `basis` and no lattice terms.
+extern "C" int digs_project_basis_fwd(const digs_geom *geom, const digs_grid *grid,
+                                      const float *basis, int n, const float *mu,
+                                      const float *scale, const float *quat, const float *rho,
+                                      int T, const float *angles, const float *w, float *proj,
+                                      void *ws, size_t ws_bytes, const digs_tuning *tuning,
+                                      void *stream)
+{
+    RenderArgs a;
+    int rc = prepare(geom, grid, basis, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
+                     tuning, &a);
+    if (rc) return rc;
+    a.basis = basis;
+    if (T == 0) return DIGS_OK;
+    if (!proj) return DIGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return check(render_zero(proj, (size_t)T * geom->nu * geom->nv, s));
+    hipError_t e = render_forward_setup(a, s);
+    if (e == hipSuccess) e = render_forward_splat(a, proj, s);
+    return check(e);
+}
+
+extern "C" int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid,
+                                      const float *basis, int n, const float *mu,
+                                      const float *scale, const float *quat, const float *rho,
+                                      int T, const float *angles, const float *w,
+                                      const float *grad_proj, float *g_mu, float *g_scale,
+                                      float *g_quat, float *g_rho, float *g_basis, float *g_w,
+                                      void *ws, size_t ws_bytes, const digs_tuning *tuning,
+                                      int flags, void *stream)
+{
+    RenderArgs a;
+    int rc = prepare(geom, grid, basis, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
+                     tuning, &a);
+    if (rc) return rc;
+    a.basis = basis;
+    if ((n > 0 && (!g_mu || !g_scale || !g_quat || !g_rho || !g_basis)) ||
+        (T > 0 && (!g_w || (n > 0 && !grad_proj))))
+        return DIGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (n == 0 || T == 0) {
+        if (T > 0) e = render_zero(g_w, (size_t)T * grid->R, s);
+        if (e == hipSuccess && n > 0) {
+            e = render_zero(g_mu, (size_t)3 * n, s);
+            if (e == hipSuccess) e = render_zero(g_scale, (size_t)3 * n, s);
+            if (e == hipSuccess) e = render_zero(g_quat, (size_t)4 * n, s);
+            if (e == hipSuccess) e = render_zero(g_rho, (size_t)n, s);
+            if (e == hipSuccess) e = render_zero(g_basis, (size_t)12 * grid->R * n, s);
+        }
+        return check(e);
+    }
+    if (!(flags & DIGS_BWD_REUSE_FWD)) e = render_forward_setup(a, s);
+    if (e == hipSuccess)
+        e = render_backward(a, grad_proj, g_mu, g_scale, g_quat, g_rho, g_basis, g_w, s);
     return check(e);
 }
 

@@ -59,6 +59,7 @@ struct RenderArgs {
     DevGeom geom;
     DevGrid grid;
     const float *coef, *mu, *scale, *quat, *rho, *angles, *w;
+    const float *basis;   // per-Gaussian motion basis [R][12][N] instead of the FFD, or null
     int n, T;
     float cull;
     int splat_waves, bwd_waves, persistent;
@@ -67,6 +68,7 @@ struct RenderArgs {
 };
 hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s);   // a1-a4
 hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s);  // a5
+// g_coef: dL/dcoef, or with a.basis dL/dbasis [R][12][N]
 hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
                            float *g_scale, float *g_quat, float *g_rho, float *g_coef,
                            float *g_w, hipStream_t s);                   // a6-a8

@@ -88,8 +88,10 @@ static hipError_t fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s)
 // ------------------------------------------------------------------------------------------
 // a1: FFD at the canonical means, uv = [U (R x 3) ; V (R x 9)] x N, and the Gaussians' parameters
 // gs = [mu (3); scale (3); quat (4); rho] x N, both in cell order (entry i belongs to Gaussian
-// order[i])
+// order[i]). With a per-Gaussian basis (the second ablation of Sec. 4.3: the spatial basis
+// stored per Gaussian instead of interpolated from the lattice), U and V are gathered from it.
 __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *__restrict__ coef,
+                                                       const float *__restrict__ basis,
                                                        int n, const float *__restrict__ mu,
                                                        const float *__restrict__ scale,
                                                        const float *__restrict__ quat,
@@ -110,9 +112,19 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
 #pragma unroll
     for (int a = 0; a < 4; ++a) gs[(size_t)(6 + a) * n + i] = quat[(size_t)a * n + src];
     gs[(size_t)10 * n + i] = rho[src];
+    float *U = uv, *V = uv + (size_t)3 * g.R * n;
+    if (basis) {
+        for (int r = 0; r < g.R; ++r) {
+            const float *b = basis + (size_t)r * 12 * n + src;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) U[((size_t)r * 3 + a) * n + i] = b[(size_t)a * n];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) V[((size_t)r * 9 + k) * n + i] = b[(size_t)(3 + k) * n];
+        }
+        return;
+    }
     Stencil st;
     make_stencil(g, mu[src], mu[n + src], mu[2 * n + src], st, false);
-    float *U = uv, *V = uv + (size_t)3 * g.R * n;
     for (int r = 0; r < g.R; ++r) {
         float u[3], J[9];
         ffd_rank(g, coef, r, st, u, J);
@@ -1399,7 +1411,8 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     DevGrid grid, int n, int nch, const float *__restrict__ coef, const float *__restrict__ gpar,
     const float *__restrict__ uv, const float *__restrict__ tacc,
     const uint32_t *__restrict__ order, float *__restrict__ g_mu, float *__restrict__ g_scale,
-    float *__restrict__ g_quat, float *__restrict__ g_rho, float *__restrict__ gq, int gq_stride)
+    float *__restrict__ g_quat, float *__restrict__ g_rho, float *__restrict__ gq, int gq_stride,
+    float *__restrict__ g_basis)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1430,22 +1443,25 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
             for (int k = 0; k < 9; ++k) Q[r][k] += src[(16 + 12 * r + k) * fs];
         }
     }
-    // dL/dmu = sum_t dL/dmu' + sum_r V_r^T P_r + sum_r Q_r : d(grad u_r)/dmu
+    // dL/dmu = sum_t dL/dmu' + sum_r V_r^T P_r + sum_r Q_r : d(grad u_r)/dmu (with a per-Gaussian
+    // basis, u and V do not depend on mu: the first term only)
     float gmu[3] = {gsum[0], gsum[1], gsum[2]};
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float *V = uv + ((size_t)3 * NR + r * 9) * n + i;
-            gmu[c] += V[c * (size_t)n] * P[r][0] + V[(3 + c) * (size_t)n] * P[r][1] +
-                      V[(6 + c) * (size_t)n] * P[r][2];
-        }
     const size_t src = order[i];   // i is the position in cell order
-    const float mu0[3] = {gpar[i], gpar[(size_t)n + i], gpar[(size_t)2 * n + i]};
     Stencil st;
-    make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
+    if (!g_basis) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(grid, coef, r, st, Q[r], gmu);
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float *V = uv + ((size_t)3 * NR + r * 9) * n + i;
+                gmu[c] += V[c * (size_t)n] * P[r][0] + V[(3 + c) * (size_t)n] * P[r][1] +
+                          V[(6 + c) * (size_t)n] * P[r][2];
+            }
+        const float mu0[3] = {gpar[i], gpar[(size_t)n + i], gpar[(size_t)2 * n + i]};
+        make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(grid, coef, r, st, Q[r], gmu);
+    }
     // R diag(s) -> s, R(q)
     const float s[3] = {gpar[(size_t)3 * n + i], gpar[(size_t)4 * n + i], gpar[(size_t)5 * n + i]};
     float q[4];
@@ -1473,6 +1489,17 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
 #pragma unroll
     for (int a = 0; a < 4; ++a) g_quat[(size_t)a * n + src] = (gqh[a] - dq * qh[a]) * qn;
     g_rho[src] = grho;
+    if (g_basis) {   // dL/du_r = P_r, dL/dV_r = Q_r, at the Gaussian's own index
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            float *b = g_basis + (size_t)r * 12 * n + src;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) b[(size_t)a * n] = P[r][a];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) b[(size_t)(3 + k) * n] = Q[r][k];
+        }
+        return;
+    }
     // sources of dL/dcoef in cell order: clamped cell, fraction, P_r, Q_r
     float *o = gq + (size_t)i * gq_stride;
     o[0] = __int_as_float(max(-2, min(st.fx, grid.nx + 1)));
@@ -1675,7 +1702,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     {
         ProfScope ps(PS_FFD, s);
         hipLaunchKernelGGL(k_ffd_canonical, dim3((a.n + 255) / 256), dim3(256), 0, s, a.grid,
-                           a.coef, a.n, a.mu, a.scale, a.quat, a.rho,
+                           a.coef, a.basis, a.n, a.mu, a.scale, a.quat, a.rho,
                            WS(a, order, const uint32_t *), WS(a, uv, float *), WS(a, gsort, float *));
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1822,7 +1849,7 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
                                a.L.tchunks, a.coef, WS(a, gsort, const float *),
                                WS(a, uv, const float *), WS(a, tacc, const float *),
                                WS(a, order, const uint32_t *), g_mu, g_scale, g_quat, g_rho,
-                               WS(a, gq, float *), a.L.gq_stride);
+                               WS(a, gq, float *), a.L.gq_stride, a.basis ? g_coef : nullptr);
             e = hipGetLastError();
         }
     }
@@ -1834,7 +1861,7 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
                                WS(a, gwpart, const float *), nparts, g_w);
         e = hipGetLastError();
     }
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || a.basis) return e;   // (a per-Gaussian basis has no lattice gather)
     const int npts = a.grid.nx * a.grid.ny * a.grid.nz;
     {
         ProfScope ps(PS_COEF_GRAD, s);
