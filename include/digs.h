@@ -300,12 +300,14 @@ int digs_standardize(int M, int N, float *X, int ldx, const float *mean, const f
  * B-spline grids updated jointly by Adam on the L2 projection loss). Device pointers, float32;
  * asynchronous on `stream`.
  * digs_l2_residual: grad[i] = proj[i] - meas[i] for i < n (dL/dproj of L = 1/2 ||proj - meas||^2)
- *   and, if loss is not NULL, loss[0] = L (one workgroup, fixed summation order).
+ *   and, if loss is not NULL (a buffer of 1 + DIGS_L2_PARTS floats), loss[0] = L; loss[1..] hold
+ *   per-workgroup parts, added in a fixed order, so L is the same on every run.
  * digs_adam_mapped: one bias-corrected Adam step (step >= 1) on n unconstrained parameters raw
  *   given dL/dvalue, where value = map(raw): map 0 identity (value must equal raw), 1 exp (for
  *   scales), 2 softplus (for densities); the chain rule is applied to the gradient, then raw is
  *   updated and value rewritten from it. m, v: the moments (zero before step 1).
  * Errors: DIGS_EINVAL, DIGS_EHIP. */
+#define DIGS_L2_PARTS 256
 int digs_l2_residual(int64_t n, const float *proj, const float *meas, float *grad, float *loss,
                      void *stream);
 int digs_adam_mapped(int n, float *raw, float *value, const float *g_value, float *m, float *v,

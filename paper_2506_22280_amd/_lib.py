@@ -547,8 +547,12 @@ def adam(w, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
 MAPS = {"identity": 0, "exp": 1, "softplus": 2}
 
 
+L2_PARTS = 256   # DIGS_L2_PARTS
+
+
 def l2_residual(proj, meas, grad, loss=None, stream=None):
-    """grad = proj - meas and (if loss, a device [1] tensor) loss[0] = 1/2 ||proj - meas||^2."""
+    """grad = proj - meas and (if loss, a device tensor of 1 + L2_PARTS floats)
+    loss[0] = 1/2 ||proj - meas||^2."""
     _check("digs_l2_residual", load().digs_l2_residual(proj.numel(), _ptr(proj), _ptr(meas),
                                                        _ptr(grad), _ptr(loss), _stream(stream)))
 

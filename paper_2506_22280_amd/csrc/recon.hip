@@ -8,28 +8,38 @@
 
 static int rc(hipError_t e) { return e == hipSuccess ? DIGS_OK : digs_set_hip_error(e); }
 
-// grad = proj - meas; loss[0] = 1/2 sum grad^2. One workgroup: grid-stride per-thread sums, then a
-// fixed tree, so the value is the same on every run.
+// grad = proj - meas, and per workgroup 1/2 the sum of grad^2 over its grid-stride share
+// (per-thread sums, then a fixed tree) into part[blockIdx.x]; k_l2_total adds the parts in order,
+// so the value is the same on every run.
 __global__ __launch_bounds__(RES_THREADS) void k_l2_residual(size_t n,
                                                              const float *__restrict__ proj,
                                                              const float *__restrict__ meas,
                                                              float *__restrict__ grad,
-                                                             float *__restrict__ loss)
+                                                             float *__restrict__ part)
 {
-    __shared__ float part[RES_THREADS];
+    __shared__ float red[RES_THREADS];
     float s = 0.0f;
-    for (size_t i = threadIdx.x; i < n; i += RES_THREADS) {
+    const size_t stride = (size_t)gridDim.x * RES_THREADS;
+    for (size_t i = (size_t)blockIdx.x * RES_THREADS + threadIdx.x; i < n; i += stride) {
         const float d = proj[i] - meas[i];
         grad[i] = d;
         s = fmaf(d, d, s);
     }
-    part[threadIdx.x] = s;
+    if (!part) return;
+    red[threadIdx.x] = s;
     __syncthreads();
     for (int h = RES_THREADS / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && loss) loss[0] = 0.5f * part[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = 0.5f * red[0];
+}
+
+__global__ void k_l2_total(int nparts, float *__restrict__ loss)
+{
+    float s = 0.0f;
+    for (int b = 0; b < nparts; ++b) s += loss[1 + b];
+    loss[0] = s;
 }
 
 // softplus(x) = log(1 + e^x), written so that it neither overflows nor loses small values
@@ -66,9 +76,18 @@ extern "C" int digs_l2_residual(int64_t n, const float *proj, const float *meas,
                                 float *loss, void *stream)
 {
     if (n < 0 || (n > 0 && (!proj || !meas || !grad))) return DIGS_EINVAL;
-    if (n == 0) return DIGS_OK;
-    hipLaunchKernelGGL(k_l2_residual, dim3(1), dim3(RES_THREADS), 0, (hipStream_t)stream,
-                       (size_t)n, proj, meas, grad, loss);
+    if (n == 0) {   // L = 0: the total of no parts
+        if (!loss) return DIGS_OK;
+        hipLaunchKernelGGL(k_l2_total, dim3(1), dim3(1), 0, (hipStream_t)stream, 0, loss);
+        return rc(hipGetLastError());
+    }
+    const int64_t want = (n + RES_THREADS * 8 - 1) / (RES_THREADS * 8);
+    const int blocks = (int)(want < DIGS_L2_PARTS ? want : DIGS_L2_PARTS);
+    hipLaunchKernelGGL(k_l2_residual, dim3(blocks), dim3(RES_THREADS), 0, (hipStream_t)stream,
+                       (size_t)n, proj, meas, grad, loss ? loss + 1 : nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !loss) return rc(e);
+    hipLaunchKernelGGL(k_l2_total, dim3(1), dim3(1), 0, (hipStream_t)stream, blocks, loss);
     return rc(hipGetLastError());
 }
 

@@ -102,7 +102,7 @@ class Reconstruction:
         self.proj = torch.zeros((B, nv, nu), device=dev)
         self.grad = torch.zeros_like(self.proj)
         self.meas_buf = torch.empty_like(self.proj)
-        self.loss = torch.zeros(1, device=dev)
+        self.loss = torch.zeros(1 + _lib.L2_PARTS, device=dev)   # loss[0] and its parts
         self.g = dict(g_mu=torch.empty_like(self.mu), g_scale=torch.empty_like(self.scale),
                       g_quat=torch.empty_like(self.quat), g_rho=torch.empty_like(self.rho),
                       g_coef=torch.empty_like(self.coef), g_w=torch.empty((B, R), device=dev))
@@ -169,7 +169,7 @@ class Reconstruction:
         cnt = 0
         for k in range(iters):
             self.step()
-            acc += self.loss
+            acc += self.loss[:1]
             cnt += 1
             if check_every and (k + 1) % check_every == 0:
                 diag, resized = self.plan.check()
@@ -177,7 +177,7 @@ class Reconstruction:
                 if diag["nonfinite"]:
                     raise FloatingPointError("non-finite Gaussians at iteration %d" % self.step_no)
             if log_every and ((k + 1) % log_every == 0 or k == iters - 1):
-                losses.append((self.step_no, float(acc.item()) / (cnt * self.B)))
+                losses.append((self.step_no, float(acc[0].item()) / (cnt * self.B)))
                 acc.zero_()
                 cnt = 0
                 if log:

@@ -22,15 +22,29 @@ def _print(*a):
 
 
 def test_l2_residual_matches_fp64():
-    _print("case: l2_residual on 3 x 75 x 90 values")
+    _print("case: l2_residual on 3 x 75 x 90 and 64 x 384 x 512 values")
     rng = np.random.default_rng(1)
     a, b = rng.normal(0, 1, (3, 75, 90)), rng.normal(0, 1, (3, 75, 90))
     grad = torch.empty((3, 75, 90), device="cuda")
-    loss = torch.zeros(1, device="cuda")
+    loss = torch.zeros(1 + _lib.L2_PARTS, device="cuda")
     _lib.l2_residual(dev(a), dev(b), grad, loss)
     d = a.astype(np.float32).astype(np.float64) - b.astype(np.float32).astype(np.float64)
     np.testing.assert_allclose(grad.cpu().numpy(), d, rtol=0, atol=1e-6)
-    assert abs(float(loss.item()) - 0.5 * (d * d).sum()) <= 1e-5 * 0.5 * (d * d).sum()
+    assert abs(float(loss[0].item()) - 0.5 * (d * d).sum()) <= 1e-5 * 0.5 * (d * d).sum()
+    # many workgroups: the same value on a second call
+    big_a, big_b = dev(rng.normal(0, 1, (64, 384, 512))), dev(rng.normal(0, 1, (64, 384, 512)))
+    g2 = torch.empty_like(big_a)
+    _lib.l2_residual(big_a, big_b, g2, loss)
+    first = loss[0].clone()
+    _lib.l2_residual(big_a, big_b, g2, loss)
+    ref = 0.5 * ((big_a.double() - big_b.double()) ** 2).sum()
+    assert torch.equal(loss[0], first)
+    assert abs(float(first) - float(ref)) <= 1e-5 * float(ref)
+    # no values: L = 0
+    loss.fill_(7.0)
+    e = torch.empty(0, device="cuda")
+    _lib.l2_residual(e, e, e, loss)
+    assert float(loss[0].item()) == 0.0
 
 
 @pytest.mark.parametrize("mapping", ["identity", "exp", "softplus"])
