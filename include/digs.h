@@ -47,7 +47,7 @@ extern "C" {
 
 #define DIGS_MAX_RANK 8
 #define DIGS_MAX_TILES 4096 /* detector tiles (16x16 pixels) per projection                   */
-#define DIGS_MAX_GAUSSIANS 268435455 /* 2^28 - 1 Gaussians per call                              */
+#define DIGS_MAX_GAUSSIANS 16777215 /* 2^24 - 1 Gaussians per call                               */
 
 /* Cone-beam CT geometry of a circular orbit about z (the paper's acquisition, Sec. 4.1).
  * View angle theta: source at sid*(cos, sin, 0); detector centre at (sid - sdd)*(cos, sin, 0);

@@ -393,8 +393,11 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
 // a4: binning sources. A tile list entry is the Gaussian's index in the low 28 bits and, in the
 // top 4 bits, which of the tile's four 8x8 pixel blocks the cut-off footprint ellipse meets
 // (bit b: block column b & 1, block row b >> 1); the splats evaluate only those blocks.
-#define LIST_INDEX_MASK 0x0FFFFFFFu
-#define LIST_BLOCK_SHIFT 28
+// A list entry: the Gaussian's index in the low 24 bits; above it two bits per 8x8 block b of the
+// tile (blocks in row-major order): bit LIST_BLOCK_SHIFT + 2b is set when the footprint ellipse
+// meets rows 0-3 of the block, the next bit when it meets rows 4-7.
+#define LIST_INDEX_MASK 0x00FFFFFFu
+#define LIST_BLOCK_SHIFT 24
 
 struct TileSrc {
     const int2 *rect;        // [T][N]
@@ -469,23 +472,24 @@ struct TileSrc {
             it.ryl = a01 / sqrtf(a00 * a11) * it.ry;
         }
     }
-    // the entry: the Gaussian's index and the mask of the 8x8 blocks that its ellipse meets (a
-    // footprint that is not an ellipse meets all four)
+    // the entry: the Gaussian's index and, per 8x8 block, which 4-row halves its ellipse meets
+    // (a footprint that is not an ellipse meets them all)
     __device__ void emit(int, int item, const Item &it, int k, uint32_t pos) const
     {
         if (pos >= cap) return;
         int tx, ty;
         it.tile(k, tx, ty);
-        uint32_t m = 0xFu;
+        uint32_t m = 0xFFu;
         if (it.ell) {
             m = 0u;
             const float x0 = (float)(tx * DIGS_TILE), y0 = (float)(ty * DIGS_TILE);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int s4 = 0; s4 < 4; ++s4) {   // 4-row strips; block row s4 >> 1, half s4 & 1
                 float L, R;
-                if (it.strip(y0 + (float)(8 * h), y0 + (float)(8 * h + 7), L, R)) {
-                    if (x0 <= R && x0 + 7.0f >= L) m |= 1u << (2 * h);
-                    if (x0 + 8.0f <= R && x0 + 15.0f >= L) m |= 2u << (2 * h);
+                if (it.strip(y0 + (float)(4 * s4), y0 + (float)(4 * s4 + 3), L, R)) {
+                    const int b = 2 * (s4 >> 1), h = s4 & 1;
+                    if (x0 <= R && x0 + 7.0f >= L) m |= 1u << (2 * b + h);
+                    if (x0 + 8.0f <= R && x0 + 15.0f >= L) m |= 1u << (2 * (b + 1) + h);
                 }
             }
         }
@@ -513,10 +517,11 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 // ------------------------------------------------------------------------------------------
 // a5: forward splat. One workgroup per (view, tile), one wave per 8x8 pixel block (with
 // WAVES == 1 a single wave takes the tile's four blocks in turn). The wave walks the tile's list
-// in chunks of 64 entries and appends the Gaussians whose footprint meets its block (bit of the
-// list entry) to a queue in LDS; it evaluates the queue 8 Gaussians at a time and carries the
-// remainder (fewer than 8) over to the next chunk, so that only the block's last group has idle
-// lanes. lane = (Gaussian slot, column); each lane runs down the 8 rows of its column with forward
+// in chunks of 64 entries and appends the Gaussians whose footprint meets its block (bits of the
+// list entry) to one of three queues in LDS: those that meet both 4-row halves of the block, only
+// the upper, only the lower. It evaluates each queue 8 Gaussians at a time, over the rows its
+// Gaussians meet, and carries the remainder (fewer than 8) over to the next chunk, so that only
+// each queue's last group has idle lanes. lane = (Gaussian slot, column); each lane runs down the 8 rows of its column with forward
 // differences of the two quadratic forms (two adds each per row). The records of the next 8
 // Gaussians are loaded while the current 8 are evaluated. The amplitude enters as log2|amp| added
 // to the exponent when the 8 Gaussians are all positive (one multiply less per pixel), as a
@@ -524,9 +529,10 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 // order, and every pixel is written once.
 #define FWD_QUEUE (DIGS_WAVE + 8)
 
-// Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8, or the block's last group)
-// into the lane's 8 row sums. EWA: q = 1, so a pixel costs one exp2 and the E recurrence.
-template <bool EWA>
+// Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8, or the queue's last group)
+// over rows [R0, R0 + NR) of the block, into the lane's row sums. EWA: q = 1, so a pixel costs
+// one exp2 and the E recurrence.
+template <bool EWA, int R0, int NR>
 __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ qid, int ns,
                                                 int gslot, float fi, float fby, float *acc)
@@ -551,7 +557,7 @@ __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
         }
         // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
         // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
-        const float du = fi - r0.x, dv0 = fby - r0.y;
+        const float du = fi - r0.x, dv0 = (fby + (float)R0) - r0.y;
         const float Aq = fmaf(du, fmaf(r1.w, du, r1.y), 1.0f);
         const float Bq = fmaf(r2.x, du, r1.z), Cq = fabsf(r2.y);
         const float AE = r0.z * du * du, BE = r0.w * du, CE = r1.x;
@@ -567,16 +573,16 @@ __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
             if (__ballot(signbit(r2.y)) == 0ull) {
                 e += la;   // amp 2^E = 2^(E + log2 amp)
 #pragma unroll
-                for (int row = 0; row < 8; ++row) {
-                    acc[row] += __builtin_amdgcn_exp2f(e);
+                for (int row = 0; row < NR; ++row) {
+                    acc[R0 + row] += __builtin_amdgcn_exp2f(e);
                     e += de;
                     de += dde;
                 }
             } else {
                 const float amp = copysignf(exp2f(la), r2.y);
 #pragma unroll
-                for (int row = 0; row < 8; ++row) {
-                    acc[row] = fmaf(amp, __builtin_amdgcn_exp2f(e), acc[row]);
+                for (int row = 0; row < NR; ++row) {
+                    acc[R0 + row] = fmaf(amp, __builtin_amdgcn_exp2f(e), acc[R0 + row]);
                     e += de;
                     de += dde;
                 }
@@ -584,10 +590,10 @@ __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
         } else if (__ballot(signbit(r2.y)) == 0ull) {
             // all eight amplitudes positive: amp rs 2^x = rs 2^(x + log2 amp)
 #pragma unroll
-            for (int row = 0; row < 8; ++row) {
+            for (int row = 0; row < NR; ++row) {
                 const float rs = __builtin_amdgcn_rsqf(q);
                 const float x = fmaf(e, rs * rs, la);
-                acc[row] = fmaf(rs, __builtin_amdgcn_exp2f(x), acc[row]);
+                acc[R0 + row] = fmaf(rs, __builtin_amdgcn_exp2f(x), acc[R0 + row]);
                 q += dq;
                 dq += ddq;
                 e += de;
@@ -596,10 +602,10 @@ __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
         } else {
             const float amp = copysignf(exp2f(la), r2.y);
 #pragma unroll
-            for (int row = 0; row < 8; ++row) {
+            for (int row = 0; row < NR; ++row) {
                 const float rs = __builtin_amdgcn_rsqf(q);
                 const float x = e * (rs * rs);
-                acc[row] = fmaf(amp * rs, __builtin_amdgcn_exp2f(x), acc[row]);
+                acc[R0 + row] = fmaf(amp * rs, __builtin_amdgcn_exp2f(x), acc[R0 + row]);
                 q += dq;
                 dq += ddq;
                 e += de;
@@ -622,7 +628,7 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
                                                const uint32_t *__restrict__ list,
                                                const uint32_t *__restrict__ cnt, int nblk,
                                                unsigned cap, float *__restrict__ proj,
-                                               uint32_t (*ids)[FWD_QUEUE])
+                                               uint32_t (*ids)[3][FWD_QUEUE])
 {
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
@@ -632,7 +638,8 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
     const float4 *rt = rec + (size_t)t * n * 4;
-    uint32_t *qid = ids[wave];
+    // the wave's three queues: Gaussians that meet rows 0-7 of the block, only rows 0-3, only 4-7
+    uint32_t(*qs)[FWD_QUEUE] = ids[wave];
     for (int pass = 0; pass < 4 / WAVES; ++pass) {
         const int blkid = (WAVES == 4) ? wave : pass;
         const int bx = tx * DIGS_TILE + (blkid & 1) * 8, by = ty * DIGS_TILE + (blkid >> 1) * 8;
@@ -640,33 +647,46 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
         float acc[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) acc[r] = 0.0f;
-        int pend = 0;   // queued Gaussians carried over from earlier chunks (fewer than 8)
+        // queued Gaussians carried over from earlier chunks (fewer than 8 per queue)
+        int pend0 = 0, pend1 = 0, pend2 = 0;
         for (uint32_t c0 = begin; c0 < end; c0 += DIGS_WAVE) {
             const uint32_t k = c0 + lane;
-            uint32_t g = 0;
-            bool hit = false;
+            uint32_t g = 0, h = 0;
             if (k < end) {
                 const uint32_t e = list[k];
                 g = e & LIST_INDEX_MASK;
-                hit = g < (uint32_t)n && ((e >> (LIST_BLOCK_SHIFT + blkid)) & 1u);
+                h = g < (uint32_t)n ? (e >> (LIST_BLOCK_SHIFT + 2 * blkid)) & 3u : 0u;
             }
-            const unsigned long long m = __ballot(hit);
-            if (hit) qid[pend + __popcll(m & lanemask_lt())] = g;
-            const int ns = pend + __popcll(m);
-            const int full = ns & ~7;
+            const unsigned long long m0 = __ballot(h == 3u), m1 = __ballot(h == 1u),
+                                     m2 = __ballot(h == 2u), lt = lanemask_lt();
+            if (h == 3u) qs[0][pend0 + __popcll(m0 & lt)] = g;
+            else if (h == 1u) qs[1][pend1 + __popcll(m1 & lt)] = g;
+            else if (h == 2u) qs[2][pend2 + __popcll(m2 & lt)] = g;
+            const int ns0 = pend0 + __popcll(m0), ns1 = pend1 + __popcll(m1),
+                      ns2 = pend2 + __popcll(m2);
+            const int f0 = ns0 & ~7, f1 = ns1 & ~7, f2 = ns2 & ~7;
             wave_sync_lds();
-            if (full > 0) {
-                splat_fwd_group<EWA>(rt, qid, full, gslot, fi, fby, acc);
-                // move the remainder to the front of the queue
-                const int left = ns - full;
-                const uint32_t keep = (lane < left) ? qid[full + lane] : 0u;
+            if (f0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], f0, gslot, fi, fby, acc);
+            if (f1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], f1, gslot, fi, fby, acc);
+            if (f2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], f2, gslot, fi, fby, acc);
+            if ((f0 | f1 | f2) > 0) {
+                // move each queue's remainder to its front: lane 8c + i moves entry i of queue c
+                const int qc = lane >> 3, qi = lane & 7;
+                const int fc = qc == 0 ? f0 : (qc == 1 ? f1 : f2);
+                const int lc = (qc == 0 ? ns0 : (qc == 1 ? ns1 : ns2)) - fc;
+                const bool mv = qc < 3 && qi < lc;
+                const uint32_t keep = mv ? qs[qc][fc + qi] : 0u;
                 wave_sync_lds();
-                if (lane < left) qid[lane] = keep;
+                if (mv) qs[qc][qi] = keep;
                 wave_sync_lds();
             }
-            pend = ns - full;
+            pend0 = ns0 - f0;
+            pend1 = ns1 - f1;
+            pend2 = ns2 - f2;
         }
-        if (pend > 0) splat_fwd_group<EWA>(rt, qid, pend, gslot, fi, fby, acc);
+        if (pend0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], pend0, gslot, fi, fby, acc);
+        if (pend1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], pend1, gslot, fi, fby, acc);
+        if (pend2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], pend2, gslot, fi, fby, acc);
         wave_sync_lds();
         // sum over the 8 Gaussian slots (lane bits 3..5) in a fixed order
 #pragma unroll
@@ -716,7 +736,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int 
                                                           int nblk, unsigned cap,
                                                           float *__restrict__ proj)
 {
-    __shared__ uint32_t ids[WAVES][FWD_QUEUE];
+    __shared__ uint32_t ids[WAVES][3][FWD_QUEUE];
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
     splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
@@ -729,7 +749,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
     const uint32_t *__restrict__ cnt, int nblk, unsigned cap, float *__restrict__ proj,
     uint32_t *__restrict__ queue)
 {
-    __shared__ uint32_t ids[WAVES][FWD_QUEUE];
+    __shared__ uint32_t ids[WAVES][3][FWD_QUEUE];
     __shared__ int s_item;
     const int home = blockIdx.x & 7;
     for (;;) {
@@ -745,7 +765,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
 }
 
 // Measurement only: the pairs inside each footprint and on the detector, and the pairs the forward
-// and backward splats evaluate (64 per 8x8 block that a footprint ellipse meets, in both).
+// and backward splats evaluate (per 8x8 block that a footprint ellipse meets, 64, or 32 when it
+// meets only one 4-row half of the block; the same in both).
 __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, float cull,
                                                      const float *__restrict__ rec,
                                                      const uint32_t *__restrict__ list,
@@ -771,9 +792,10 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
     for (uint32_t k = begin; k < end; ++k) {
         const uint32_t ent = uniform(list[k]);
         const uint32_t g = ent & LIST_INDEX_MASK;
-        if (g >= (uint32_t)n || !((ent >> (LIST_BLOCK_SHIFT + wave)) & 1u)) continue;
+        const uint32_t h = (ent >> (LIST_BLOCK_SHIFT + 2 * wave)) & 3u;
+        if (g >= (uint32_t)n || h == 0u) continue;
         const float *r = rec + ((size_t)t * n + g) * DIGS_REC_FLOATS;
-        eval_f += 64;
+        eval_f += h == 3u ? 64 : 32;
         const float du = (float)px - r[0], dv = (float)py - r[1];
         const float q = fmaf(du, fmaf(r[7], du, fmaf(r[8], dv, r[5])),
                              fmaf(dv, fmaf(fabsf(r[9]), dv, r[6]), 1.0f));
@@ -809,8 +831,9 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // a6: backward splat. One workgroup per (projection, tile); the tile's dL/dI (times |e|) is staged
 // in LDS (row stride 18 keeps the four 8x8 blocks in distinct banks). Each wave takes chunks of
 // 64 list entries and appends the (entry, 8x8 block) pairs whose footprint ellipse meets the block
-// (block-major) to a pair queue in LDS. The queue is evaluated 64 pairs at a time, one pair per
-// lane, and the remainder is carried over to the next chunk, so that lanes idle only when a chunk
+// (block-major) to one of two pair queues in LDS: pairs whose ellipse meets both 4-row halves of
+// the block run over its 8 rows, the others over the one half they meet. Each queue is evaluated
+// 64 pairs at a time, one pair per lane, and its remainder is carried over to the next chunk, so that lanes idle only when a chunk
 // must be finished early (below) and at the end of the tile. A lane runs over its block's 64
 // pixels with forward differences along each row and accumulates twelve moment sums, which are
 // added into the entry's LDS slot in block order (fixed order, no atomics). Entry slots belong to
@@ -827,14 +850,15 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 #define BWD_QUEUE (5 * DIGS_WAVE)   // carried (< 64) + one chunk's pairs (<= 256)
 struct BwdShared {
     float gpx[DIGS_TILE * GPX_STRIDE];
-    uint32_t pairs[4][BWD_QUEUE];          // (entry slot << 2) | block
+    uint32_t pairs[4][2][BWD_QUEUE];       // (entry slot << 3) | (half << 2) | block
     uint32_t gid[4][2 * DIGS_WAVE];        // Gaussian of each entry slot
     float accS[4][2 * DIGS_WAVE][13];      // moment sums of each entry slot
 };
 
-// Evaluates queued pairs [j0, j0 + cnt) of the wave (cnt <= 64), one per lane, and adds their
-// moment sums into the entries' slots. EWA: q = 1 (no dL/dq moments), one exp2 per pixel.
-template <bool EWA>
+// Evaluates queued pairs [j0, j0 + cnt) of the wave (cnt <= 64), one per lane, over NROWS rows of
+// the pair's block (with NROWS == 4 the half that bit 2 of the pair names), and adds their moment
+// sums into the entries' slots. EWA: q = 1 (no dL/dq moments), one exp2 per pixel.
+template <bool EWA, int NROWS>
 __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ pq,
                                                 const uint32_t *__restrict__ gid,
@@ -848,7 +872,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     const int lane = lane_id();
     const bool active = lane < cnt;
     const uint32_t pr = active ? pq[j0 + lane] : 0u;
-    const int slot = (int)(pr >> 2), blk = (int)(pr & 3u);
+    const int slot = (int)(pr >> 3), blk = (int)(pr & 3u);
     float4 r0 = zero4, r1 = zero4, r2 = zero4;
     if (active) {
         const size_t ge = gid[slot];
@@ -858,7 +882,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     }
     // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
     // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
-    const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8;
+    const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8 + (NROWS == 4 ? (int)((pr >> 2) & 1u) * 4 : 0);
     const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
     const float Cq = r1.w, CE = r0.z, Gvv = fabsf(r2.y);
     const float s1 = fmaf(2.0f, du0, 1.0f);
@@ -873,7 +897,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         // per pixel a = g 2^x (dL/dE up to the factor -amp/2); dL/damp = sum a
         float E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
         const float *gp = gpx + lby * GPX_STRIDE + lbx;
-        for (int row = 0; row < 8; ++row) {
+        for (int row = 0; row < NROWS; ++row) {
             const float dv = dv0 + (float)row;
             const float BE = r0.w * dv, AE = r1.x * dv * dv;
             float ee = fmaf(du0, ea + BE, AE);
@@ -910,7 +934,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
         float X0 = 0.f, X1 = 0.f, X2 = 0.f, XV0 = 0.f, XV1 = 0.f, XW0 = 0.f;
         const float *gp = gpx + lby * GPX_STRIDE + lbx;
-        for (int row = 0; row < 8; ++row) {
+        for (int row = 0; row < NROWS; ++row) {
             const float dv = dv0 + (float)row;
             // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
             const float Bq = fmaf(r2.x, dv, r1.y);
@@ -1044,10 +1068,11 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
     end = min(max(end, begin), cap);
     const float4 *rt = rec + (size_t)t * n * 4;
     const int tx0 = tx * DIGS_TILE, ty0 = ty * DIGS_TILE;
-    uint32_t *pq = sh.pairs[wave];
+    uint32_t *pq0 = sh.pairs[wave][0];   // pairs over all 8 rows of the block
+    uint32_t *pq1 = sh.pairs[wave][1];   // pairs over 4 rows (one half of the block)
     uint32_t *gid = sh.gid[wave];
     float(*accS)[13] = sh.accS[wave];
-    int pend = 0;              // queued pairs carried over (all of the previous chunk), < 64
+    int pend0 = 0, pend1 = 0;  // queued pairs carried over (all of the previous chunk), < 64 each
     int it = 0;
     bool prev_valid = false;   // the previous chunk's entry of this lane
     uint32_t prev_g = 0;
@@ -1061,36 +1086,50 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         gid[ring + lane] = g;
 #pragma unroll
         for (int c = 0; c < 12; ++c) accS[ring + lane][c] = 0.0f;
-        int np = pend;
+        int np0 = pend0, np1 = pend1;
+        const unsigned long long lt = lanemask_lt();
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
-            const bool hit = valid && ((ent >> (LIST_BLOCK_SHIFT + blk)) & 1u);
-            const unsigned long long m = __ballot(hit);
-            if (hit) pq[np + __popcll(m & lanemask_lt())] = ((uint32_t)(ring + lane) << 2) | blk;
-            np += __popcll(m);
+            const uint32_t h = valid ? (ent >> (LIST_BLOCK_SHIFT + 2 * blk)) & 3u : 0u;
+            const bool whole = h == 3u, half = h == 1u || h == 2u;
+            const unsigned long long mw = __ballot(whole), mh = __ballot(half);
+            const uint32_t pe = ((uint32_t)(ring + lane) << 3) | (uint32_t)blk;
+            if (whole) pq0[np0 + __popcll(mw & lt)] = pe;
+            if (half) pq1[np1 + __popcll(mh & lt)] = pe | ((h >> 1) << 2);
+            np0 += __popcll(mw);
+            np1 += __popcll(mh);
         }
         wave_sync_lds();
         // full groups; if pairs of the previous chunk are queued and no full group forms, they
         // are evaluated now in a partial group (with everything queued) to finish that chunk
-        int done = np & ~(DIGS_WAVE - 1);
-        if (done == 0 && pend > 0) done = np;
-        for (int j = 0; j < done; j += DIGS_WAVE)
-            splat_bwd_group<EWA>(rt, pq, gid, accS, gpx, j, min(DIGS_WAVE, done - j), tx0, ty0);
+        int done0 = np0 & ~(DIGS_WAVE - 1), done1 = np1 & ~(DIGS_WAVE - 1);
+        if (done0 == 0 && pend0 > 0) done0 = np0;
+        if (done1 == 0 && pend1 > 0) done1 = np1;
+        for (int j = 0; j < done0; j += DIGS_WAVE)
+            splat_bwd_group<EWA, 8>(rt, pq0, gid, accS, gpx, j, min(DIGS_WAVE, done0 - j), tx0,
+                                    ty0);
+        for (int j = 0; j < done1; j += DIGS_WAVE)
+            splat_bwd_group<EWA, 4>(rt, pq1, gid, accS, gpx, j, min(DIGS_WAVE, done1 - j), tx0,
+                                    ty0);
         if (it > 0 && prev_valid)
             splat_bwd_write(n, t, tx, ty, prev_g, accS[(ring ^ DIGS_WAVE) + lane], cap, rect, goff,
                             part);
-        const int left = np - done;
-        if (done > 0 && left > 0) {
-            const uint32_t keep = (lane < left) ? pq[done + lane] : 0u;
+        const int left0 = np0 - done0, left1 = np1 - done1;
+        if ((done0 > 0 && left0 > 0) || (done1 > 0 && left1 > 0)) {
+            const uint32_t keep0 = (lane < left0) ? pq0[done0 + lane] : 0u;
+            const uint32_t keep1 = (lane < left1) ? pq1[done1 + lane] : 0u;
             wave_sync_lds();
-            if (lane < left) pq[lane] = keep;
+            if (lane < left0) pq0[lane] = keep0;
+            if (lane < left1) pq1[lane] = keep1;
         }
         wave_sync_lds();
-        pend = left;
+        pend0 = left0;
+        pend1 = left1;
         prev_valid = valid;
         prev_g = g;
     }
-    if (pend > 0) splat_bwd_group<EWA>(rt, pq, gid, accS, gpx, 0, pend, tx0, ty0);
+    if (pend0 > 0) splat_bwd_group<EWA, 8>(rt, pq0, gid, accS, gpx, 0, pend0, tx0, ty0);
+    if (pend1 > 0) splat_bwd_group<EWA, 4>(rt, pq1, gid, accS, gpx, 0, pend1, tx0, ty0);
     if (it > 0 && prev_valid)
         splat_bwd_write(n, t, tx, ty, prev_g, accS[((it - 1) & 1) * DIGS_WAVE + lane], cap, rect,
                         goff, part);
