@@ -529,32 +529,51 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 // order, and every pixel is written once.
 #define FWD_QUEUE (DIGS_WAVE + 8)
 
+// Adds rows [R0, R0 + NR) of one Gaussian at the lane's column into acc: from the row quadratics
+// q (and its first and second differences) and E, with la = log2|amp| (-inf: adds zero). EWA:
+// q = 1, so a pixel costs one exp2 and the E recurrence.
+template <bool EWA, int R0, int NR>
+__device__ __forceinline__ void splat_fwd_rows(float q, float dq, float ddq, float e, float de,
+                                               float dde, float la, float *acc)
+{
+    if constexpr (EWA) {
+        e += la;   // amp 2^E = 2^(E + log2 amp)
+#pragma unroll
+        for (int row = 0; row < NR; ++row) {
+            acc[R0 + row] += __builtin_amdgcn_exp2f(e);
+            e += de;
+            de += dde;
+        }
+    } else {
+        // amp rs 2^x = rs 2^(x + log2 amp)
+#pragma unroll
+        for (int row = 0; row < NR; ++row) {
+            const float rs = __builtin_amdgcn_rsqf(q);
+            const float x = fmaf(e, rs * rs, la);
+            acc[R0 + row] = fmaf(rs, __builtin_amdgcn_exp2f(x), acc[R0 + row]);
+            q += dq;
+            dq += ddq;
+            e += de;
+            de += dde;
+        }
+    }
+}
+
 // Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8, or the queue's last group)
-// over rows [R0, R0 + NR) of the block, into the lane's row sums. EWA: q = 1, so a pixel costs
-// one exp2 and the E recurrence.
+// over rows [R0, R0 + NR) of the block: positive amplitudes into the lane's row sums acc,
+// negative ones (by magnitude, in a second pass taken only when the group has any) into accn.
 template <bool EWA, int R0, int NR>
 __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ qid, int ns,
-                                                int gslot, float fi, float fby, float *acc)
+                                                int gslot, float fi, float fby, float *acc,
+                                                float *accn)
 {
-    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float4 n0 = zero4, n1 = zero4, n2 = idle_rec2();
-    if (gslot < ns) {
-        const size_t gg = qid[gslot];
-        n0 = rt[gg * 4 + 0];
-        n1 = rt[gg * 4 + 1];
-        n2 = rt[gg * 4 + 2];
-    }
     for (int j = 0; j < ns; j += 8) {
-        const float4 r0 = n0, r1 = n1, r2 = n2;
-        const int sn = j + 8 + gslot;
-        n0 = zero4; n1 = zero4; n2 = idle_rec2();
-        if (sn < ns) {
-            const size_t gg = qid[sn];
-            n0 = rt[gg * 4 + 0];
-            n1 = rt[gg * 4 + 1];
-            n2 = rt[gg * 4 + 2];
-        }
+        // a slot past the queue's end repeats its last Gaussian with amplitude 0
+        const int sn = j + gslot;
+        const bool live = sn < ns;
+        const size_t gg = qid[live ? sn : ns - 1];
+        const float4 r0 = rt[gg * 4 + 0], r1 = rt[gg * 4 + 1], r2 = rt[gg * 4 + 2];
         // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
         // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
         const float du = fi - r0.x, dv0 = (fby + (float)R0) - r0.y;
@@ -562,56 +581,16 @@ __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
         const float Bq = fmaf(r2.x, du, r1.z), Cq = fabsf(r2.y);
         const float AE = r0.z * du * du, BE = r0.w * du, CE = r1.x;
         const float s1 = fmaf(2.0f, dv0, 1.0f);
-        float q = fmaf(dv0, fmaf(Cq, dv0, Bq), Aq);
-        float dq = fmaf(Cq, s1, Bq);
-        const float ddq = 2.0f * Cq;
-        float e = fmaf(dv0, fmaf(CE, dv0, BE), AE);
-        float de = fmaf(CE, s1, BE);
-        const float dde = 2.0f * CE;
-        const float la = r2.z;
-        if constexpr (EWA) {
-            if (__ballot(signbit(r2.y)) == 0ull) {
-                e += la;   // amp 2^E = 2^(E + log2 amp)
-#pragma unroll
-                for (int row = 0; row < NR; ++row) {
-                    acc[R0 + row] += __builtin_amdgcn_exp2f(e);
-                    e += de;
-                    de += dde;
-                }
-            } else {
-                const float amp = copysignf(exp2f(la), r2.y);
-#pragma unroll
-                for (int row = 0; row < NR; ++row) {
-                    acc[R0 + row] = fmaf(amp, __builtin_amdgcn_exp2f(e), acc[R0 + row]);
-                    e += de;
-                    de += dde;
-                }
-            }
-        } else if (__ballot(signbit(r2.y)) == 0ull) {
-            // all eight amplitudes positive: amp rs 2^x = rs 2^(x + log2 amp)
-#pragma unroll
-            for (int row = 0; row < NR; ++row) {
-                const float rs = __builtin_amdgcn_rsqf(q);
-                const float x = fmaf(e, rs * rs, la);
-                acc[R0 + row] = fmaf(rs, __builtin_amdgcn_exp2f(x), acc[R0 + row]);
-                q += dq;
-                dq += ddq;
-                e += de;
-                de += dde;
-            }
-        } else {
-            const float amp = copysignf(exp2f(la), r2.y);
-#pragma unroll
-            for (int row = 0; row < NR; ++row) {
-                const float rs = __builtin_amdgcn_rsqf(q);
-                const float x = e * (rs * rs);
-                acc[R0 + row] = fmaf(amp * rs, __builtin_amdgcn_exp2f(x), acc[R0 + row]);
-                q += dq;
-                dq += ddq;
-                e += de;
-                de += dde;
-            }
-        }
+        const float q = fmaf(dv0, fmaf(Cq, dv0, Bq), Aq);
+        const float dq = fmaf(Cq, s1, Bq);
+        const float e = fmaf(dv0, fmaf(CE, dv0, BE), AE);
+        const float de = fmaf(CE, s1, BE);
+        const bool neg = signbit(r2.y);
+        splat_fwd_rows<EWA, R0, NR>(q, dq, 2.0f * Cq, e, de, 2.0f * CE,
+                                    (live && !neg) ? r2.z : -INFINITY, acc);
+        if (__ballot(live && neg) != 0ull)
+            splat_fwd_rows<EWA, R0, NR>(q, dq, 2.0f * Cq, e, de, 2.0f * CE,
+                                        (live && neg) ? r2.z : -INFINITY, accn);
     }
 }
 
@@ -644,9 +623,9 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
         const int blkid = (WAVES == 4) ? wave : pass;
         const int bx = tx * DIGS_TILE + (blkid & 1) * 8, by = ty * DIGS_TILE + (blkid >> 1) * 8;
         const float fi = (float)(bx + col), fby = (float)by;
-        float acc[8];
+        float acc[8], accn[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) acc[r] = 0.0f;
+        for (int r = 0; r < 8; ++r) acc[r] = accn[r] = 0.0f;
         // queued Gaussians carried over from earlier chunks (fewer than 8 per queue)
         int pend0 = 0, pend1 = 0, pend2 = 0;
         for (uint32_t c0 = begin; c0 < end; c0 += DIGS_WAVE) {
@@ -666,9 +645,9 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
                       ns2 = pend2 + __popcll(m2);
             const int f0 = ns0 & ~7, f1 = ns1 & ~7, f2 = ns2 & ~7;
             wave_sync_lds();
-            if (f0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], f0, gslot, fi, fby, acc);
-            if (f1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], f1, gslot, fi, fby, acc);
-            if (f2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], f2, gslot, fi, fby, acc);
+            if (f0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], f0, gslot, fi, fby, acc, accn);
+            if (f1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], f1, gslot, fi, fby, acc, accn);
+            if (f2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], f2, gslot, fi, fby, acc, accn);
             if ((f0 | f1 | f2) > 0) {
                 // move each queue's remainder to its front: lane 8c + i moves entry i of queue c
                 const int qc = lane >> 3, qi = lane & 7;
@@ -684,13 +663,14 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
             pend1 = ns1 - f1;
             pend2 = ns2 - f2;
         }
-        if (pend0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], pend0, gslot, fi, fby, acc);
-        if (pend1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], pend1, gslot, fi, fby, acc);
-        if (pend2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], pend2, gslot, fi, fby, acc);
+        if (pend0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], pend0, gslot, fi, fby, acc, accn);
+        if (pend1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], pend1, gslot, fi, fby, acc, accn);
+        if (pend2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], pend2, gslot, fi, fby, acc, accn);
         wave_sync_lds();
         // sum over the 8 Gaussian slots (lane bits 3..5) in a fixed order
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
+            acc[r] -= accn[r];
             acc[r] += __shfl_xor(acc[r], 8, 64);
             acc[r] += __shfl_xor(acc[r], 16, 64);
             acc[r] += __shfl_xor(acc[r], 32, 64);
