@@ -865,25 +865,33 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8 + (NROWS == 4 ? (int)((pr >> 2) & 1u) * 4 : 0);
     const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
     const float Cq = r1.w, CE = r0.z, Gvv = fabsf(r2.y);
-    const float s1 = fmaf(2.0f, du0, 1.0f);
-    const float qa = Cq * du0, ea = CE * du0;
-    // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2, applied at the end), a row
-    // accumulates a and a x weighted by 1, c and c^2 (c = 0..7, the column inside the block, a
-    // compile-time constant); rows are folded with dv, dv^2, and the block's column offset du0 is
-    // applied at the end. dL/dq (up to the same factor) is b = a (1 + 2 ln2 x): its moments are
-    // those of a plus 2 ln2 times those of a x.
+    const float s1 = fmaf(2.0f, du0, 1.0f), t1 = fmaf(2.0f, dv0, 1.0f);
+    // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2, applied at the end), the
+    // lane accumulates a and a x weighted by 1, c and c^2 (c = 0..7, the column inside the block,
+    // a compile-time constant) over all its rows. The row moments come from prefix sums: with P_r
+    // the sum through row r, sum_r r c_r = (R-1) P_{R-1} - sum_{r<R-1} P_r and
+    // sum_r r^2 c_r = (R-1)^2 P_{R-1} - sum_{r<R-1} (2r+1) P_r, so a row costs three adds per
+    // accumulated quantity; dv = dv0 + r and the column offset du0 are applied at the end. dL/dq
+    // (up to the same factor) is b = a (1 + 2 ln2 x): its moments are those of a plus 2 ln2 times
+    // those of a x. Each row starts from q and E at its first pixel, carried down the rows by
+    // their differences (q and E are quadratic in du and dv).
+    const float ddq = 2.0f * Cq, dde = 2.0f * CE;
+    float er = fmaf(du0, fmaf(CE, du0, r0.w * dv0), r1.x * (dv0 * dv0));
+    float ve = fmaf(r1.x, t1, r0.w * du0);
+    const float vve = 2.0f * r1.x;
+    float der = fmaf(CE, s1, r0.w * dv0);
+    const float Rm = (float)(NROWS - 1);
     float S[12];
     if constexpr (EWA) {
         // per pixel a = g 2^x (dL/dE up to the factor -amp/2); dL/damp = sum a
-        float E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, Q0 = 0.f, Q1 = 0.f, W0 = 0.f, tw = -1.0f;
         const float *gp = gpx + lby * GPX_STRIDE + lbx;
         for (int row = 0; row < NROWS; ++row) {
-            const float dv = dv0 + (float)row;
-            const float BE = r0.w * dv, AE = r1.x * dv * dv;
-            float ee = fmaf(du0, ea + BE, AE);
-            float de = fmaf(CE, s1, BE);
-            const float dde = 2.0f * CE;
-            float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+            Q0 += e0;
+            Q1 += e1;
+            W0 = fmaf(tw, e0, W0);
+            tw += 2.0f;
+            float ee = er, de = der;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const float a = gp[row * GPX_STRIDE + c] * __builtin_amdgcn_exp2f(ee);
@@ -895,38 +903,41 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
                 ee += de;
                 de += dde;
             }
-            E0 += e0;
-            E1 += e1;
-            E2 += e2;
-            EV0 = fmaf(dv, e0, EV0);
-            EV1 = fmaf(dv, e1, EV1);
-            EW0 = fmaf(dv * dv, e0, EW0);
+            er += ve;
+            ve += vve;
+            der += r0.w;
         }
+        const float R0 = fmaf(Rm, e0, -Q0), R1 = fmaf(Rm, e1, -Q1), RR0 = fmaf(Rm * Rm, e0, -W0);
+        const float EV0 = fmaf(dv0, e0, R0), EV1 = fmaf(dv0, e1, R1);
+        const float EW0 = fmaf(dv0, fmaf(dv0, e0, 2.0f * R0), RR0);
         const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
-        S[0] = E0;
-        S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);
+        S[0] = e0;
+        S[1] = cA * fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);
         S[2] = cA * fmaf(du0, EV0, EV1);
         S[3] = cA * EW0;
         S[4] = S[5] = S[6] = S[7] = S[8] = S[9] = 0.0f;
-        S[10] = cA * fmaf(du0, E0, E1);
+        S[10] = cA * fmaf(du0, e0, e1);
         S[11] = cA * EV0;
     } else {
-        float S0 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f, EV0 = 0.f, EV1 = 0.f, EW0 = 0.f;
-        float X0 = 0.f, X1 = 0.f, X2 = 0.f, XV0 = 0.f, XV1 = 0.f, XW0 = 0.f;
+        const float Bq0 = fmaf(r2.x, dv0, r1.y);
+        float qr = fmaf(du0, fmaf(Cq, du0, Bq0), fmaf(dv0, fmaf(Gvv, dv0, r1.z), 1.0f));
+        float vq = fmaf(Gvv, t1, fmaf(r2.x, du0, r1.z));
+        const float vvq = 2.0f * Gvv;
+        float dqr = fmaf(Cq, s1, Bq0);
+        float S0 = 0.f, e0 = 0.f, e1 = 0.f, e2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        float Qe0 = 0.f, Qe1 = 0.f, We0 = 0.f, Qx0 = 0.f, Qx1 = 0.f, Wx0 = 0.f, tw = -1.0f;
         const float *gp = gpx + lby * GPX_STRIDE + lbx;
+#pragma unroll
         for (int row = 0; row < NROWS; ++row) {
-            const float dv = dv0 + (float)row;
-            // along the row: q(du) = Aq + Bq du + Cq du^2, E(du) = AE + BE du + CE du^2
-            const float Bq = fmaf(r2.x, dv, r1.y);
-            const float Aq = fmaf(dv, fmaf(Gvv, dv, r1.z), 1.0f);
-            const float BE = r0.w * dv, AE = r1.x * dv * dv;
-            float q = fmaf(du0, qa + Bq, Aq);
-            float dq = fmaf(Cq, s1, Bq);
-            const float ddq = 2.0f * Cq;
-            float ee = fmaf(du0, ea + BE, AE);
-            float de = fmaf(CE, s1, BE);
-            const float dde = 2.0f * CE;
-            float e0 = 0.f, e1 = 0.f, e2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
+            Qe0 += e0;
+            Qe1 += e1;
+            We0 = fmaf(tw, e0, We0);
+            Qx0 += x0;
+            Qx1 += x1;
+            Wx0 = fmaf(tw, x0, Wx0);
+            tw += 2.0f;
+            // along the row: q(du) and E(du) by forward differences from the row's first pixel
+            float q = qr, dq = dqr, ee = er, de = der;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const float gval = gp[row * GPX_STRIDE + c];
@@ -950,27 +961,29 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
                 ee += de;
                 de += dde;
             }
-            const float dv2 = dv * dv;
-            E0 += e0;
-            E1 += e1;
-            E2 += e2;
-            EV0 = fmaf(dv, e0, EV0);
-            EV1 = fmaf(dv, e1, EV1);
-            EW0 = fmaf(dv2, e0, EW0);
-            X0 += x0;
-            X1 += x1;
-            X2 += x2;
-            XV0 = fmaf(dv, x0, XV0);
-            XV1 = fmaf(dv, x1, XV1);
-            XW0 = fmaf(dv2, x0, XW0);
+            qr += vq;
+            vq += vvq;
+            dqr += r2.x;
+            er += ve;
+            ve += vve;
+            der += r0.w;
         }
+        // row-index moments, then dv = dv0 + r
+        const float Re0 = fmaf(Rm, e0, -Qe0), Re1 = fmaf(Rm, e1, -Qe1);
+        const float RRe0 = fmaf(Rm * Rm, e0, -We0);
+        const float Rx0 = fmaf(Rm, x0, -Qx0), Rx1 = fmaf(Rm, x1, -Qx1);
+        const float RRx0 = fmaf(Rm * Rm, x0, -Wx0);
+        const float EV0 = fmaf(dv0, e0, Re0), EV1 = fmaf(dv0, e1, Re1);
+        const float EW0 = fmaf(dv0, fmaf(dv0, e0, 2.0f * Re0), RRe0);
+        const float XV0 = fmaf(dv0, x0, Rx0), XV1 = fmaf(dv0, x1, Rx1);
+        const float XW0 = fmaf(dv0, fmaf(dv0, x0, 2.0f * Rx0), RRx0);
         const float k2 = 2.0f * LN2;
-        const float Q0 = fmaf(k2, X0, E0), Q1 = fmaf(k2, X1, E1), Q2 = fmaf(k2, X2, E2);
+        const float Q0 = fmaf(k2, x0, e0), Q1 = fmaf(k2, x1, e1), Q2 = fmaf(k2, x2, e2);
         const float QV0 = fmaf(k2, XV0, EV0), QV1 = fmaf(k2, XV1, EV1), QW0 = fmaf(k2, XW0, EW0);
         // the twelve moment sums (du = du0 + c), with the factor -amp/2
         const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
         S[0] = S0;
-        S[1] = cA * fmaf(du0, fmaf(du0, E0, 2.0f * E1), E2);    // sum dE du^2
+        S[1] = cA * fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);    // sum dE du^2
         S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
         S[3] = cA * EW0;                                        // sum dE dv^2
         S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
@@ -979,7 +992,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
         S[8] = cA * QV0;                                        // sum dq dv
         S[9] = cA * Q0;                                         // sum dq
-        S[10] = cA * fmaf(du0, E0, E1);                         // sum dE du
+        S[10] = cA * fmaf(du0, e0, e1);                         // sum dE du
         S[11] = cA * EV0;                                       // sum dE dv
     }
     // add into the entry's slot, one block at a time (an entry has at most one pair per block)
