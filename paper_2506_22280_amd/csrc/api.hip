@@ -117,7 +117,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->uv = take(sizeof(float) * 12 * grid->R * N);
     L->gsort = take(sizeof(float) * 11 * N);
     L->rec = take(sizeof(float) * DIGS_REC_FLOATS * TN);
-    L->rect = take(sizeof(int) * 2 * TN);
+    L->rect = take(sizeof(int) * 4 * TN);
     L->gcount = take(sizeof(uint32_t) * TN);
     L->cnt = take(sizeof(uint32_t) * cnt_elems);
     L->scratch = take(sizeof(uint32_t) * sc);

@@ -11,8 +11,8 @@ struct WsLayout {
     size_t uv;         // [3R + 9R][N] f32: per-rank u_r(mu), grad u_r(mu) at the canonical means
     size_t gsort;      // [11][N] f32: mu, scale, quat, rho of the Gaussians in cell order
     size_t rec;        // [T][N][16] f32 projected records
-    size_t rect;       // [T][N] int2 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
-    size_t gcount;     // [T][N] u32 tiles per (t,n), scanned in place to instance offsets
+    size_t rect;       // [T][N] int4 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16) and instance mask
+    size_t gcount;     // [T][N] u32 instances per (t,n), scanned in place to instance offsets
     size_t cnt;        // [T][ntiles][nblk] u32 per-block tile counts, scanned in place
     size_t scratch;    // scan block sums
     size_t list;       // [cap] u32 Gaussian index of each instance, grouped by (t, tile)

@@ -281,6 +281,103 @@ __device__ __forceinline__ bool footprint_box(const DevGeom &G, const SetupFwd &
     return true;
 }
 
+// The cut-off ellipse by horizontal chords: at y = cy + dy the chord is
+// x in cx - s dy -+ sqrt((1 - D dy^2) ia), |dy| <= ry; its leftmost point is at dy = ryl and its
+// rightmost at dy = -ryl (1 carries a slack of 1e-5). ell is false for a footprint that is not an
+// ellipse (it meets everything).
+struct FootEll {
+    float cx, cy, s, ia, D, ry, ryl;
+    bool ell;
+    __device__ void init(float a00, float a01, float a11, float ccx, float ccy)
+    {
+        cx = ccx;
+        cy = ccy;
+        s = ia = D = ry = ryl = 0.0f;
+        const float d = a11 - a01 * (a01 / a00);
+        ell = a00 > 0.0f && d > 0.0f && isfinite(d);
+        if (ell) {
+            s = a01 / a00;
+            ia = 1.0f / a00;
+            D = d;
+            ry = sqrtf(1.00001f / d);
+            ryl = a01 / sqrtf(a00 * a11) * ry;
+        }
+    }
+    // x-extent [L, R] of the ellipse within the strip y in [ya, yb]; false if it misses
+    __device__ bool strip(float ya, float yb, float &L, float &R) const
+    {
+        const float lo = fmaxf(ya - cy, -ry), hi = fminf(yb - cy, ry);
+        if (!(lo <= hi)) return false;
+        const float dl = fminf(fmaxf(ryl, lo), hi), dr = fminf(fmaxf(-ryl, lo), hi);
+        L = cx - s * dl - __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dl, dl, 1.00001f)) * ia);
+        R = cx - s * dr + __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dr, dr, 1.00001f)) * ia);
+        return true;
+    }
+};
+
+// The instances of a (view, Gaussian): the tiles of its footprint's bounding rectangle that the
+// footprint ellipse meets. rect = (tx0 | tx1 << 16, ty0 | ty1 << 16, m, 0): for a rectangle of at
+// most 32 tiles bit k of m marks tile k (row-major) as an instance; a larger rectangle has all its
+// tiles as instances. Instance j of the (view, Gaussian) sits at slot goff + j, in row-major order.
+struct TileRect {
+    int tx0, ty0, w, R;
+    uint32_t m;
+    __device__ static TileRect from(int4 r)
+    {
+        TileRect q;
+        q.tx0 = r.x & 0xffff;
+        q.ty0 = r.y & 0xffff;
+        const int tx1 = r.x >> 16, ty1 = r.y >> 16;
+        q.w = tx1 - q.tx0 + 1;
+        q.R = (tx1 >= q.tx0 && ty1 >= q.ty0) ? q.w * (ty1 - q.ty0 + 1) : 0;
+        q.m = q.R >= 32 ? ~0u : ((uint32_t)r.z & ((1u << q.R) - 1u));
+        return q;
+    }
+    __device__ int count() const { return R > 32 ? R : __popc(m); }
+    // rectangle tile (row-major index) of instance j < count()
+    __device__ int tile_of(int j) const
+    {
+        if (R > 32) return j;
+        uint32_t v = m;
+        int p = 0;
+#pragma unroll
+        for (int b = 16; b >= 1; b >>= 1) {
+            const int c = __popc(v & ((1u << b) - 1u));
+            if (j >= c) {
+                j -= c;
+                v >>= b;
+                p += b;
+            }
+        }
+        return p;
+    }
+    // instance index of rectangle tile k (an instance)
+    __device__ int inst_of(int k) const { return R > 32 ? k : __popc(m & ((1u << k) - 1u)); }
+};
+
+// Instance mask of a footprint rectangle of R <= 32 tiles (see TileRect): in each row of tiles,
+// the tiles whose 16 columns meet the ellipse's x-extent over the row's 16 pixel rows. (This
+// keeps every tile in which a list entry could mark an 8x8 block; a kept tile with no such block
+// only costs an empty entry.)
+__device__ uint32_t footprint_tiles(const Footprint &fp, int tx0, int ty0, int w, int h)
+{
+    FootEll fe;
+    fe.init(fp.a00, fp.a01, fp.a11, fp.cx, fp.cy);
+    if (!fe.ell) return ~0u;
+    uint32_t m = 0u;
+    for (int r = 0; r < h; ++r) {
+        const float y0 = (float)((ty0 + r) * DIGS_TILE);
+        float L, R;
+        if (!fe.strip(y0, y0 + (float)(DIGS_TILE - 1), L, R)) continue;
+        // columns c with (tx0 + c) 16 <= R and (tx0 + c) 16 + 15 >= L
+        const float inv = 1.0f / (float)DIGS_TILE;
+        const int c0 = max(0, (int)ceilf(fmaxf((L - (float)(DIGS_TILE - 1)) * inv, -1.0f)) - tx0);
+        const int c1 = min(w - 1, (int)floorf(fminf(R * inv, 65536.0f)) - tx0);
+        if (c0 <= c1) m |= (((1u << (c1 - c0)) << 1) - 1u) << (r * w + c0);
+    }
+    return m;
+}
+
 template <int NR>
 __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
                                                const float *__restrict__ gs,
@@ -288,7 +385,7 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
                                                const float *__restrict__ w,
                                                const float *__restrict__ uv, float cull,
                                                float4 *__restrict__ rec,
-                                               int2 *__restrict__ rect,
+                                               int4 *__restrict__ rect,
                                                uint32_t *__restrict__ gcount,
                                                DiagBlock *__restrict__ diag)
 {
@@ -346,12 +443,19 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
                 atomicAdd(&diag->wide, 1u);
         }
         uint32_t count = 0;
-        int2 rr = make_int2(1, 0);
+        int4 rr = make_int4(1, 0, 0, 0);
         if (valid && ok && x0 <= x1 && y0 <= y1) {
             const int tx0 = x0 / DIGS_TILE, tx1 = x1 / DIGS_TILE;
             const int ty0 = y0 / DIGS_TILE, ty1 = y1 / DIGS_TILE;
-            count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-            rr = make_int2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+            const int w = tx1 - tx0 + 1, h = ty1 - ty0 + 1;
+            count = (uint32_t)(w * h);
+            uint32_t m = ~0u;
+            if (w * h <= 32) {
+                m = footprint_tiles(fp, tx0, ty0, w, h);
+                if (w * h < 32) m &= (1u << (w * h)) - 1u;
+                count = (uint32_t)__popc(m);
+            }
+            rr = make_int4(tx0 | (tx1 << 16), ty0 | (ty1 << 16), (int)m, 0);
         } else {
             x0 = 1; x1 = 0; y0 = 1; y1 = 0;
         }
@@ -400,27 +504,25 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
 #define LIST_BLOCK_SHIFT 24
 
 struct TileSrc {
-    const int2 *rect;        // [T][N]
+    const int4 *rect;        // [T][N] footprint rectangles and instance masks (TileRect)
     const float4 *rec;       // [T][N][4] projected records (footprint conic in rec[2].w, rec[3])
     uint32_t *list;
     size_t cap;
     int items;               // N
     int tiles_x;
     struct Item {
-        int tx0, ty0, w, cnt, tiles_x;
+        TileRect tr;
+        int cnt, tiles_x;
         float inv_w;
-        // the cut-off ellipse by horizontal chords (prepare): at y = cy + dy the chord is
-        // x in cx - s dy -+ sqrt((1 - D dy^2) ia), |dy| <= ry; its leftmost point is at dy = ryl
-        // and its rightmost at dy = -ryl (1 carries a slack of 1e-5)
-        float cx, cy, s, ia, D, ry, ryl;
-        bool ell;
+        FootEll fe;          // the cut-off ellipse (prepare)
         __device__ int nkeys() const { return cnt; }
-        // k-th tile of the rectangle in row-major order (k / w in float: exact for k < 2^21)
+        // tile of instance k (row-major in the rectangle; k / w in float: exact for k < 2^21)
         __device__ void tile(int k, int &tx, int &ty) const
         {
-            const int q = (int)(((float)k + 0.5f) * inv_w);
-            tx = tx0 + (k - __mul24(q, w));
-            ty = ty0 + q;
+            const int p = tr.tile_of(k);
+            const int q = (int)(((float)p + 0.5f) * inv_w);
+            tx = tr.tx0 + (p - __mul24(q, tr.w));
+            ty = tr.ty0 + q;
         }
         __device__ int key(int k) const
         {
@@ -428,49 +530,23 @@ struct TileSrc {
             tile(k, tx, ty);
             return __mul24(ty, tiles_x) + tx;
         }
-        // x-extent [L, R] of the ellipse within the strip y in [ya, yb]; false if it misses
-        __device__ bool strip(float ya, float yb, float &L, float &R) const
-        {
-            const float lo = fmaxf(ya - cy, -ry), hi = fminf(yb - cy, ry);
-            if (!(lo <= hi)) return false;
-            const float dl = fminf(fmaxf(ryl, lo), hi), dr = fminf(fmaxf(-ryl, lo), hi);
-            L = cx - s * dl - __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dl, dl, 1.00001f)) * ia);
-            R = cx - s * dr + __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dr, dr, 1.00001f)) * ia);
-            return true;
-        }
     };
     __device__ Item load(int t, int item) const
     {
-        const int2 r = rect[(size_t)t * items + item];
         Item it;
-        it.tx0 = r.x & 0xffff;
-        const int tx1 = r.x >> 16;
-        it.ty0 = r.y & 0xffff;
-        const int ty1 = r.y >> 16;
-        it.w = tx1 - it.tx0 + 1;
-        it.cnt = (tx1 >= it.tx0 && ty1 >= it.ty0) ? it.w * (ty1 - it.ty0 + 1) : 0;
-        it.inv_w = it.cnt > 0 ? 1.0f / (float)it.w : 0.0f;
+        it.tr = TileRect::from(rect[(size_t)t * items + item]);
+        it.cnt = it.tr.count();
+        it.inv_w = it.cnt > 0 ? 1.0f / (float)it.tr.w : 0.0f;
         it.tiles_x = tiles_x;
-        it.cx = it.cy = it.s = it.ia = it.D = it.ry = it.ryl = 0.0f;
-        it.ell = false;
+        it.fe.cx = it.fe.cy = it.fe.s = it.fe.ia = it.fe.D = it.fe.ry = it.fe.ryl = 0.0f;
+        it.fe.ell = false;
         return it;
     }
     __device__ void prepare(int t, int item, Item &it) const
     {
         const float4 *r = rec + ((size_t)t * items + item) * 4;
         const float4 c = r[2], d = r[3];
-        const float a00 = c.w, a01 = d.x, a11 = d.y;
-        it.cx = d.z;
-        it.cy = d.w;
-        const float D = a11 - a01 * (a01 / a00);
-        it.ell = a00 > 0.0f && D > 0.0f && isfinite(D);
-        if (it.ell) {
-            it.s = a01 / a00;
-            it.ia = 1.0f / a00;
-            it.D = D;
-            it.ry = sqrtf(1.00001f / D);
-            it.ryl = a01 / sqrtf(a00 * a11) * it.ry;
-        }
+        it.fe.init(c.w, d.x, d.y, d.z, d.w);
     }
     // the entry: the Gaussian's index and, per 8x8 block, which 4-row halves its ellipse meets
     // (a footprint that is not an ellipse meets them all)
@@ -480,13 +556,13 @@ struct TileSrc {
         int tx, ty;
         it.tile(k, tx, ty);
         uint32_t m = 0xFFu;
-        if (it.ell) {
+        if (it.fe.ell) {
             m = 0u;
             const float x0 = (float)(tx * DIGS_TILE), y0 = (float)(ty * DIGS_TILE);
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {   // 4-row strips; block row s4 >> 1, half s4 & 1
                 float L, R;
-                if (it.strip(y0 + (float)(4 * s4), y0 + (float)(4 * s4 + 3), L, R)) {
+                if (it.fe.strip(y0 + (float)(4 * s4), y0 + (float)(4 * s4 + 3), L, R)) {
                     const int b = 2 * (s4 >> 1), h = s4 & 1;
                     if (x0 <= R && x0 + 7.0f >= L) m |= 1u << (2 * b + h);
                     if (x0 + 8.0f <= R && x0 + 15.0f >= L) m |= 1u << (2 * (b + 1) + h);
@@ -1010,16 +1086,15 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
 // Writes the partial of the entry in slot `slot` (Gaussian g of view t, this tile).
 __device__ __forceinline__ void splat_bwd_write(int n, int t, int tx, int ty, uint32_t g,
                                                 const float *acc, unsigned cap,
-                                                const int2 *__restrict__ rect,
+                                                const int4 *__restrict__ rect,
                                                 const uint32_t *__restrict__ goff,
                                                 float4 *__restrict__ part)
 {
     // instance slot of (t, g, this tile): the Gaussian's instances are contiguous, in row-major
     // order over its tile rectangle
     const size_t o = (size_t)t * n + g;
-    const int2 rr = rect[o];
-    const int rtx0 = rr.x & 0xffff, rtx1 = rr.x >> 16, rty0 = rr.y & 0xffff;
-    const size_t slot = (size_t)goff[o] + (size_t)((ty - rty0) * (rtx1 - rtx0 + 1) + (tx - rtx0));
+    const TileRect tr = TileRect::from(rect[o]);
+    const size_t slot = (size_t)goff[o] + (size_t)tr.inst_of((ty - tr.ty0) * tr.w + (tx - tr.tx0));
     if (slot < cap) {
         part[slot * 3 + 0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
         part[slot * 3 + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
@@ -1032,7 +1107,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ list,
                                                const uint32_t *__restrict__ cnt, int nblk,
-                                               unsigned cap, const int2 *__restrict__ rect,
+                                               unsigned cap, const int4 *__restrict__ rect,
                                                const uint32_t *__restrict__ goff,
                                                const float *__restrict__ grad_proj,
                                                float4 *__restrict__ part, BwdShared &sh)
@@ -1134,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                                                    const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ list,
                                                    const uint32_t *__restrict__ cnt, int nblk,
-                                                   unsigned cap, const int2 *__restrict__ rect,
+                                                   unsigned cap, const int4 *__restrict__ rect,
                                                    const uint32_t *__restrict__ goff,
                                                    const float *__restrict__ grad_proj,
                                                    float4 *__restrict__ part)
@@ -1149,7 +1224,7 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
 template <bool EWA>
 __global__ __launch_bounds__(256) void k_splat_bwd_persist(
     DevGeom G, int n, int T, const float4 *__restrict__ rec, const uint32_t *__restrict__ list,
-    const uint32_t *__restrict__ cnt, int nblk, unsigned cap, const int2 *__restrict__ rect,
+    const uint32_t *__restrict__ cnt, int nblk, unsigned cap, const int4 *__restrict__ rect,
     const uint32_t *__restrict__ goff, const float *__restrict__ grad_proj,
     float4 *__restrict__ part, uint32_t *__restrict__ queue)
 {
@@ -1192,7 +1267,7 @@ template <int NR>
 __global__ __launch_bounds__(256) void k_tn_bwd(
     DevGeom G, int n, int T, int tpc, const float *__restrict__ gs,
     const float *__restrict__ angles, const float *__restrict__ w, const float *__restrict__ uv,
-    const int2 *__restrict__ rect,
+    const int4 *__restrict__ rect,
     const uint32_t *__restrict__ goff,
     const float4 *__restrict__ part, unsigned cap,
     float *__restrict__ tacc, float *__restrict__ gwpart, int nparts)
@@ -1236,10 +1311,7 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
     }
     for (int t = t0; t < t1; ++t) {
         const size_t o = (size_t)t * n + ii;
-        const int2 rr = rect[o];
-        const int tx0 = rr.x & 0xffff, tx1 = rr.x >> 16, ty0 = rr.y & 0xffff, ty1 = rr.y >> 16;
-        const int cntk =
-            (valid && tx1 >= tx0 && ty1 >= ty0) ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
+        const int cntk = valid ? TileRect::from(rect[o]).count() : 0;
         float gwc[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) gwc[r] = 0.0f;
@@ -1681,7 +1753,7 @@ static hipError_t setup_dispatch(const RenderArgs &a, hipStream_t s)
     dim3 grid((n + 255) / 256, (T + SETUP_TCHUNK - 1) / SETUP_TCHUNK);
     hipLaunchKernelGGL(k_setup<NR>, grid, dim3(256), 0, s, a.geom, n, T,
                        WS(a, gsort, const float *), a.angles, a.w, WS(a, uv, const float *), a.cull,
-                       WS(a, rec, float4 *), WS(a, rect, int2 *), WS(a, gcount, uint32_t *),
+                       WS(a, rec, float4 *), WS(a, rect, int4 *), WS(a, gcount, uint32_t *),
                        WS(a, diag, DiagBlock *));
     return hipGetLastError();
 }
@@ -1760,7 +1832,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     }
     if (e != hipSuccess) return e;
     TileSrc src;
-    src.rect = WS(a, rect, const int2 *);
+    src.rect = WS(a, rect, const int4 *);
     src.rec = WS(a, rec, const float4 *);
     src.list = WS(a, list, uint32_t *);
     src.cap = a.L.cap;
@@ -1870,7 +1942,7 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
         ProfScope ps(PS_GAUSS_BWD, s);
         hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, a.L.tchunks), dim3(256), 0, s, a.geom, n, T,
                            a.L.tpc, WS(a, gsort, const float *), a.angles, a.w,
-                           WS(a, uv, const float *), WS(a, rect, const int2 *),
+                           WS(a, uv, const float *), WS(a, rect, const int4 *),
                            WS(a, gcount, const uint32_t *),
                            WS(a, part, const float4 *),
                            (unsigned)a.L.cap, WS(a, tacc, float *), WS(a, gwpart, float *),
@@ -1914,14 +1986,14 @@ static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32
                            dim3(persistent_grid(k_splat_bwd_persist<EWA>, 256, items)), dim3(256),
                            0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
                            WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
-                           (unsigned)a.L.cap, WS(a, rect, const int2 *),
+                           (unsigned)a.L.cap, WS(a, rect, const int4 *),
                            WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
                            queue);
     else
         hipLaunchKernelGGL(k_splat_bwd<EWA>, dim3((unsigned)items), dim3(256), 0, s, a.geom, a.n,
                            a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
-                           WS(a, rect, const int2 *), WS(a, gcount, const uint32_t *), grad_proj,
+                           WS(a, rect, const int4 *), WS(a, gcount, const uint32_t *), grad_proj,
                            WS(a, part, float4 *));
 }
 
