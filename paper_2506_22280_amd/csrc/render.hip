@@ -597,12 +597,12 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
 // list entry) to one of three queues in LDS: those that meet both 4-row halves of the block, only
 // the upper, only the lower. It evaluates each queue 8 Gaussians at a time, over the rows its
 // Gaussians meet, and carries the remainder (fewer than 8) over to the next chunk, so that only
-// each queue's last group has idle lanes. lane = (Gaussian slot, column); each lane runs down the 8 rows of its column with forward
-// differences of the two quadratic forms (two adds each per row). The records of the next 8
-// Gaussians are loaded while the current 8 are evaluated. The amplitude enters as log2|amp| added
-// to the exponent when the 8 Gaussians are all positive (one multiply less per pixel), as a
-// factor otherwise. The per-lane row sums are reduced over the 8 slots at the end in a fixed
-// order, and every pixel is written once.
+// each queue's last group has idle lanes. lane = (Gaussian slot, column); each lane runs down the
+// rows of its column with forward differences of the two quadratic forms (two adds each per row).
+// The amplitude enters as log2|amp| added to the exponent (one multiply less per pixel); positive
+// and negative amplitudes go to separate row sums, the negative ones in a second pass that only
+// groups holding one take. The per-lane row sums are reduced over the 8 slots at the end in a
+// fixed order, and every pixel is written once.
 #define FWD_QUEUE (DIGS_WAVE + 8)
 
 // Adds rows [R0, R0 + NR) of one Gaussian at the lane's column into acc: from the row quadratics

@@ -55,6 +55,9 @@ def test_host_side_validation_and_sizes():
     assert lib.digs_workspace_size(ctypes.byref(ewa), ctypes.byref(R), 4096, 16, None) == s1
     ewa.model = 7                                                 # no such model
     assert lib.digs_workspace_size(ctypes.byref(ewa), ctypes.byref(R), 10, 1, None) == 0
+    # a list entry holds the Gaussian's index in 24 bits
+    assert lib.digs_workspace_size(ctypes.byref(G), ctypes.byref(R), (1 << 24) - 1, 1, None) > 0
+    assert lib.digs_workspace_size(ctypes.byref(G), ctypes.byref(R), 1 << 24, 1, None) == 0
     # null pointers are rejected before any device work
     rc = lib.digs_project_fwd(ctypes.byref(G), ctypes.byref(R), None, 10, None, None, None, None,
                               1, None, None, None, None, 0, None, None)
