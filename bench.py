@@ -520,6 +520,7 @@ def main():
         out["eager_profiled_ms_per_step"] = round(dt_eager / args.steps * 1e3, 3)
         stages = {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items() if v[0]}
         totals = {k: v[1] for k, v in prof.items() if v[0]}
+        out["stage_ms_per_step"] = {k: round(v / args.steps, 4) for k, v in totals.items()}
         out["stage_avg_ms_per_launch"] = stages
         out["stage_share"] = {k: round(v / sum(totals.values()), 4) for k, v in totals.items()}
         dom = max(("splat_fwd", "splat_bwd"), key=lambda k: totals.get(k, 0.0))

@@ -47,6 +47,19 @@ def test_ewa_fwd_tiny_all_pixels():
         assert err <= 1e-4, (k, err)
 
 
+def test_ewa_fwd_signed_densities():
+    _print("case: EWA project_fwd with densities of both signs (tiny, 2000 Gaussians, 8 views)")
+    p = _ewa(synth.tiny(seed=24, n=2000, nviews=8, det=48))
+    flip = np.random.default_rng(25).random(p.n) < 0.3
+    p.rho = np.where(flip, -p.rho, p.rho).astype(np.float32)
+    t = problem_tensors(p)
+    proj, _ = _fwd(p, t)
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(ref.shape[0]):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+
+
 def test_ewa_fwd_ragged_detector_with_offsets():
     _print("case: EWA project_fwd small phantom, 90x75 detector, offsets (7.5, -3) mm, 4 views")
     p = _ewa(synth.small_phantom(n=2048, nviews=4), off_u=7.5, off_v=-3.0)

@@ -187,6 +187,30 @@ def test_project_bwd_matches_oracle():
         assert torch.equal(out[k], out2[k]), k
 
 
+def test_signed_densities_match_oracle():
+    _print("case: densities of both signs (tiny, 2000 Gaussians, 8 views 48x48): fwd and bwd "
+           "against the oracle")
+    p = synth.tiny(seed=21, n=2000, nviews=8, det=48)
+    flip = np.random.default_rng(22).random(p.n) < 0.3
+    p.rho = np.where(flip, -p.rho, p.rho).astype(np.float32)
+    t = problem_tensors(p)
+    proj, ws = _fwd(p, t)
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(ref.shape[0]):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+    G = np.random.default_rng(23).normal(0, 1, ref.shape).astype(np.float32)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True)
+    torch.cuda.synchronize()
+    gref = oracle.project_bwd(p.geom, p.grid, *oracle_inputs(p), grad_proj=G)
+    errs = {k: norm_rel(out[k].cpu().numpy(), gref[k]) for k in gref}
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+
+
 def test_project_bwd_identities():
     _print("case: gradient identities on the GPU (rho-linearity, quaternion, homogeneity)")
     p, G = _bwd_problem()
