@@ -56,9 +56,9 @@ ALGO_BYTES_PER_PROJ = (2 * 200_000 * 44 + 3 * 29 ** 3 * 9 * 4 + 64 * 512 * 384 *
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while the sources are unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2154893.1 * 2.0 * 1024,
-           "write_bytes": 7414265.5 * 1.0 * 1024,
-           "sources_sha256": "256693d2d5cafdcd85db4d1c411f6913f488a722687f5cd7273225974f9ebee2"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2355533.1 * 2.000 * 1024,
+           "write_bytes": 6585444.5 * 1.000 * 1024,
+           "sources_sha256": "f44563cefc73e0d581847f9a24f31a7f11fab785539ea9668cf723c00b899b85"}
 
 
 def sources_digest() -> str:
