@@ -1,7 +1,8 @@
 // bin.h -- deterministic, atomics-free-in-global-memory binning of items into keyed lists.
 //
 // Each item (a Gaussian of one projection, or one key of a radix pass) contributes nkeys()
-// keys; before its keys are placed, prepare() may load what emit() needs beyond the keys. k_bin_count builds per-wave key histograms in LDS (integer LDS atomics: exact counts)
+// keys: key(k) is its k-th, and count(h) adds one to h[key] for each of them (in any order);
+// before its keys are placed, prepare() may load what emit() needs beyond the keys. k_bin_count builds per-wave key histograms in LDS (integer LDS atomics: exact counts)
 // and writes one count per (slice, key, item block). After an exclusive scan of those counts
 // in (slice, key, block) order, k_bin_fill recomputes the per-wave histograms, turns them into
 // per-wave running offsets, and places every (item, key) pair: the rank among equal keys in
@@ -43,11 +44,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_count(Src src, uint32_t *__
     const int base = blk * DIGS_BIN_ITEMS + wave * BIN_PER_WAVE;
     for (int step = 0; step < BIN_PER_WAVE / DIGS_WAVE; ++step) {
         const int item = base + step * DIGS_WAVE + lane;
-        if (item < src.items) {
-            typename Src::Item it = src.load(slice, item);
-            const int nk = it.nkeys();
-            for (int k = 0; k < nk; ++k) atomicAdd(&h[it.key(k)], 1u);
-        }
+        if (item < src.items) src.load(slice, item).count(h);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbins; b += BIN_THREADS) {
@@ -72,11 +69,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
     const int base = blk * DIGS_BIN_ITEMS + wave * BIN_PER_WAVE;
     for (int step = 0; step < BIN_PER_WAVE / DIGS_WAVE; ++step) {
         const int item = base + step * DIGS_WAVE + lane;
-        if (item < src.items) {
-            typename Src::Item it = src.load(slice, item);
-            const int nk = it.nkeys();
-            for (int k = 0; k < nk; ++k) atomicAdd(&h[it.key(k)], 1u);
-        }
+        if (item < src.items) src.load(slice, item).count(h);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbins; b += BIN_THREADS) {
@@ -128,7 +121,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
             const int rank = __popcll(peers & lanemask_lt());
             if (active) pos = h[key] + (uint32_t)rank;
             if (active && rank == 0) h[key] = pos + (uint32_t)__popcll(peers);
-            if (active) src.emit(slice, item0 + j, o, k, pos);
+            if (active) src.emit(slice, item0 + j, o, k, key, pos);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -145,6 +138,7 @@ struct RadixSrc {
         uint32_t k;
         __device__ int nkeys() const { return 1; }
         __device__ int key(int) const { return (int)k; }
+        __device__ void count(uint32_t *h) const { atomicAdd(&h[k], 1u); }
     };
     __device__ Item load(int, int item) const
     {
@@ -153,7 +147,7 @@ struct RadixSrc {
         return it;
     }
     __device__ void prepare(int, int, Item &) const {}
-    __device__ void emit(int, int item, const Item &, int, uint32_t pos) const
+    __device__ void emit(int, int item, const Item &, int, unsigned, uint32_t pos) const
     {
         if (pos < (uint32_t)items) {
             keys_out[pos] = keys_in[item];

@@ -320,7 +320,7 @@ struct FootEll {
 // most 32 tiles bit k of m marks tile k (row-major) as an instance; a larger rectangle has all its
 // tiles as instances. Instance j of the (view, Gaussian) sits at slot goff + j, in row-major order.
 struct TileRect {
-    int tx0, ty0, w, R;
+    int tx0, ty0, w, h, R;
     uint32_t m;
     __device__ static TileRect from(int4 r)
     {
@@ -329,7 +329,8 @@ struct TileRect {
         q.ty0 = r.y & 0xffff;
         const int tx1 = r.x >> 16, ty1 = r.y >> 16;
         q.w = tx1 - q.tx0 + 1;
-        q.R = (tx1 >= q.tx0 && ty1 >= q.ty0) ? q.w * (ty1 - q.ty0 + 1) : 0;
+        q.h = ty1 - q.ty0 + 1;
+        q.R = (tx1 >= q.tx0 && ty1 >= q.ty0) ? q.w * q.h : 0;
         q.m = q.R >= 32 ? ~0u : ((uint32_t)r.z & ((1u << q.R) - 1u));
         return q;
     }
@@ -510,6 +511,7 @@ struct TileSrc {
     size_t cap;
     int items;               // N
     int tiles_x;
+    float inv_tiles_x;       // 1 / tiles_x
     struct Item {
         TileRect tr;
         int cnt, tiles_x;
@@ -529,6 +531,21 @@ struct TileSrc {
             int tx, ty;
             tile(k, tx, ty);
             return __mul24(ty, tiles_x) + tx;
+        }
+        // one count per instance tile, by rows of the rectangle (no instance search)
+        __device__ void count(uint32_t *h) const
+        {
+            if (cnt == 0) return;
+            const uint32_t rowmask = tr.w >= 32 ? ~0u : ((1u << tr.w) - 1u);
+            for (int r = 0; r < tr.h; ++r) {
+                const int row = __mul24(tr.ty0 + r, tiles_x) + tr.tx0;
+                if (tr.R > 32) {
+                    for (int c = 0; c < tr.w; ++c) atomicAdd(&h[row + c], 1u);
+                } else {
+                    for (uint32_t v = (tr.m >> (r * tr.w)) & rowmask; v; v &= v - 1u)
+                        atomicAdd(&h[row + __builtin_ctz(v)], 1u);
+                }
+            }
         }
     };
     __device__ Item load(int t, int item) const
@@ -550,11 +567,12 @@ struct TileSrc {
     }
     // the entry: the Gaussian's index and, per 8x8 block, which 4-row halves its ellipse meets
     // (a footprint that is not an ellipse meets them all)
-    __device__ void emit(int, int item, const Item &it, int k, uint32_t pos) const
+    __device__ void emit(int, int item, const Item &it, int, unsigned key, uint32_t pos) const
     {
         if (pos >= cap) return;
-        int tx, ty;
-        it.tile(k, tx, ty);
+        // the tile from its key (key / tiles_x in float: exact for keys below 2^21)
+        const int ty = (int)(((float)key + 0.5f) * inv_tiles_x);
+        const int tx = (int)key - __mul24(ty, tiles_x);
         uint32_t m = 0xFFu;
         if (it.fe.ell) {
             m = 0u;
@@ -1838,6 +1856,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     src.cap = a.L.cap;
     src.items = a.n;
     src.tiles_x = a.geom.tiles_x;
+    src.inv_tiles_x = 1.0f / (float)a.geom.tiles_x;
     e = launch_binning(src, a.T, a.geom.ntiles, a.L.nblk, bits_for(a.geom.ntiles), cnt,
                        cnt_elems + 1, scratch, s);
     if (e != hipSuccess) return e;
