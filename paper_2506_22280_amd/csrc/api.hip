@@ -86,10 +86,11 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->ncells = (grid->nx + 4) * (grid->ny + 4) * (grid->nz + 4);
     L->gq_stride = 6 + 12 * grid->R;
     // the per-Gaussian adjoint runs one thread per (Gaussian, chunk of views): enough chunks for
-    // about 64k threads, a function of n and T alone so that the sums' order is fixed
+    // about 256k threads (at this kernel's register use one round of the chip holds ~130k, so the
+    // last round's tail stays short), a function of n and T alone so that the sums' order is fixed
     {
         const int Tp = T > 0 ? T : 1;
-        const int want = (int)std::min<int64_t>(Tp, std::max<int64_t>(1, (65536 + (int64_t)n - 1) /
+        const int want = (int)std::min<int64_t>(Tp, std::max<int64_t>(1, (262144 + (int64_t)n - 1) /
                                                                            std::max(n, 1)));
         L->tpc = (Tp + want - 1) / want;
         L->tchunks = (Tp + L->tpc - 1) / L->tpc;
