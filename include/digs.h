@@ -314,7 +314,9 @@ int digs_adam_mapped(int n, float *raw, float *value, const float *g_value, floa
                      float lr, float b1, float b2, float eps, int step, int map, void *stream);
 
 /* Diagnostics of a workspace: digs_read_diagnostics synchronises `stream` and copies the block
- * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). */
+ * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). The block (at the start
+ * of the workspace) holds whatever the memory held until it is first cleared: clear a newly
+ * allocated workspace once before its first call (digs_plan_create does so for its own). */
 int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);
 int digs_reset_diagnostics(void *ws, void *stream);
 

@@ -295,10 +295,14 @@ class Workspace:
         self.buf = None
         self._gen = 0
 
-    def get(self, nbytes: int):
+    def get(self, nbytes: int, stream=None):
+        """The buffer, of at least nbytes; a new buffer's diagnostics block is cleared (on
+        `stream`, before the call that uses it)."""
         if self.buf is None or self.buf.numel() < nbytes:
             self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
             self._gen += 1
+            _check("digs_reset_diagnostics",
+                   load().digs_reset_diagnostics(_ptr(self.buf), _stream(stream)))
         return self.buf
 
     def stamp(self):
@@ -328,7 +332,7 @@ def project_fwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, w
     nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
     if nbytes == 0:
         raise DigsError("digs_workspace_size", -1)
-    buf = ws.get(nbytes)
+    buf = ws.get(nbytes, stream)
     if proj is None:
         proj = torch.empty((T, geom["nv"], geom["nu"]), device=mu.device, dtype=torch.float32)
     _check("digs_project_fwd", load().digs_project_fwd(
@@ -350,7 +354,7 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
         raise DigsError("digs_workspace_size", -1)
     if reuse_fwd and (ws.buf is None or ws.buf.numel() < nbytes):
         reuse_fwd = False
-    buf = ws.get(nbytes)
+    buf = ws.get(nbytes, stream)
     if out is None:
         dev = mu.device
         out = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
@@ -376,7 +380,7 @@ def project_basis_fwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angle
     nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
     if nbytes == 0:
         raise DigsError("digs_workspace_size", -1)
-    buf = ws.get(nbytes)
+    buf = ws.get(nbytes, stream)
     if proj is None:
         proj = torch.empty((T, geom["nv"], geom["nu"]), device=mu.device, dtype=torch.float32)
     _check("digs_project_basis_fwd", load().digs_project_basis_fwd(
@@ -399,7 +403,7 @@ def project_basis_bwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angle
         raise DigsError("digs_workspace_size", -1)
     if reuse_fwd and (ws.buf is None or ws.buf.numel() < nbytes):
         reuse_fwd = False
-    buf = ws.get(nbytes)
+    buf = ws.get(nbytes, stream)
     dev = mu.device
     if out is None:
         out = dict(g_mu=torch.empty((3, n), device=dev), g_scale=torch.empty((3, n), device=dev),
@@ -612,7 +616,7 @@ def phi_grid(grid: dict, coef, mu, scale, quat, rho, w, vgrid: dict, ws: "Worksp
         nbytes = int(load().digs_phi_workspace_size(ctypes.byref(V), n, int(capacity)))
         if nbytes == 0:
             raise DigsError("digs_phi_workspace_size", -1)
-        buf = ws.get(nbytes)
+        buf = ws.get(nbytes, stream)
         _check("digs_phi_grid", load().digs_phi_grid(
             ctypes.byref(G), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat), _ptr(rho), _ptr(w),
             ctypes.byref(V), float(cull), int(capacity), _ptr(out), _ptr(buf), buf.numel(),

@@ -211,6 +211,38 @@ def test_signed_densities_match_oracle():
     assert errs["g_w"] <= 1e-3
 
 
+def test_large_footprints_match_oracle():
+    _print("case: 48 large Gaussians (scales 8-16 mm) on a 128x128 detector, 4 views: footprint "
+           "rectangles of more than 32 tiles (every tile an instance); fwd and bwd against the oracle")
+    p = synth.tiny(seed=31, n=48, nviews=4, det=128)
+    rng = np.random.default_rng(32)
+    p.scale = np.exp(rng.uniform(np.log(8.0), np.log(16.0), (3, p.n))).astype(np.float32)
+    t = problem_tensors(p)
+    T = len(p.angles)
+    # capacity for every tile of the 8x8-tile detector (the default, 16 per (view, Gaussian),
+    # would overflow, which the diagnostics report)
+    proj, ws = _fwd(p, t, tuning=dict(capacity=64 * p.n * T))
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0
+    # on average more than 32 instances per (view, Gaussian): rectangles above 32 tiles
+    assert d["instances"] > 32 * p.n * T
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(ref.shape[0]):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+    G = rng.normal(0, 1, ref.shape).astype(np.float32)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True,
+                           tuning=dict(capacity=64 * p.n * T))
+    torch.cuda.synchronize()
+    gref = oracle.project_bwd(p.geom, p.grid, *oracle_inputs(p), grad_proj=G)
+    errs = {k: norm_rel(out[k].cpu().numpy(), gref[k]) for k in gref}
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+
+
 def test_project_bwd_identities():
     _print("case: gradient identities on the GPU (rho-linearity, quaternion, homogeneity)")
     p, G = _bwd_problem()
