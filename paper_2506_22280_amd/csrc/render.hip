@@ -495,12 +495,10 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
 }
 
 // ------------------------------------------------------------------------------------------
-// a4: binning sources. A tile list entry is the Gaussian's index in the low 28 bits and, in the
-// top 4 bits, which of the tile's four 8x8 pixel blocks the cut-off footprint ellipse meets
-// (bit b: block column b & 1, block row b >> 1); the splats evaluate only those blocks.
-// A list entry: the Gaussian's index in the low 24 bits; above it two bits per 8x8 block b of the
-// tile (blocks in row-major order): bit LIST_BLOCK_SHIFT + 2b is set when the footprint ellipse
-// meets rows 0-3 of the block, the next bit when it meets rows 4-7.
+// a4: binning sources. A tile list entry is the Gaussian's index in the low 24 bits; above it two
+// bits per 8x8 pixel block b of the tile (blocks in row-major order: block column b & 1, block row
+// b >> 1): bit LIST_BLOCK_SHIFT + 2b is set when the cut-off footprint ellipse meets rows 0-3 of
+// the block, the next bit when it meets rows 4-7. The splats evaluate only those rows.
 #define LIST_INDEX_MASK 0x00FFFFFFu
 #define LIST_BLOCK_SHIFT 24
 
