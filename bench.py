@@ -56,9 +56,9 @@ ALGO_BYTES_PER_PROJ = (2 * 200_000 * 44 + 3 * 29 ** 3 * 9 * 4 + 64 * 512 * 384 *
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while the sources are unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2350682.7 * 2.000 * 1024,
-           "write_bytes": 6584638.5 * 1.000 * 1024,
-           "sources_sha256": "2e061e92e9db6c7a4378ce8c3b5dbe1acddd7bea9a26f90efd0c4b2866b46371"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2354470.2 * 2.000 * 1024,
+           "write_bytes": 6585126.1 * 1.000 * 1024,
+           "sources_sha256": "f365ac33844523c897c05eda79c4825de973ad4fb3b837dbbf1425598a3dbcad"}
 
 
 def sources_digest() -> str:
