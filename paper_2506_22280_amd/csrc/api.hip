@@ -81,7 +81,12 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->n = n;
     L->T = T;
     L->R = grid->R;
-    L->nblk = (n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS;
+    // tile binning: smaller workgroups when the launch would have fewer than ~1024 of them
+    {
+        const int64_t full = (int64_t)(T > 0 ? T : 1) * ((n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS);
+        L->bin_items = full < 1024 ? DIGS_BIN_ITEMS_SMALL : DIGS_BIN_ITEMS;
+    }
+    L->nblk = (n + L->bin_items - 1) / L->bin_items;
     L->ntiles = G.ntiles;
     L->ncells = (grid->nx + 4) * (grid->ny + 4) * (grid->nz + 4);
     L->gq_stride = 6 + 12 * grid->R;

@@ -17,7 +17,8 @@
 
 #define BIN_THREADS 256
 #define BIN_WAVES (BIN_THREADS / DIGS_WAVE)
-#define BIN_PER_WAVE (DIGS_BIN_ITEMS / BIN_WAVES)   // 256 items per wave, 4 steps of 64
+// ITEMS: items per workgroup (DIGS_BIN_ITEMS, or DIGS_BIN_ITEMS_SMALL for launches with few
+// workgroups); each wave takes ITEMS / BIN_WAVES of them, 64 per step
 
 // lanes whose key equals this lane's key (among active lanes)
 __device__ __forceinline__ unsigned long long wave_match(unsigned key, bool active, int nbits)
@@ -31,7 +32,7 @@ __device__ __forceinline__ unsigned long long wave_match(unsigned key, bool acti
     return m;
 }
 
-template <class Src>
+template <class Src, int ITEMS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_count(Src src, uint32_t *__restrict__ cnt,
                                                            int nbins, int nblk)
 {
@@ -41,8 +42,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_count(Src src, uint32_t *__
     for (int k = threadIdx.x; k < BIN_WAVES * nbins; k += BIN_THREADS) hist[k] = 0;
     __syncthreads();
     uint32_t *h = hist + wave * nbins;
-    const int base = blk * DIGS_BIN_ITEMS + wave * BIN_PER_WAVE;
-    for (int step = 0; step < BIN_PER_WAVE / DIGS_WAVE; ++step) {
+    constexpr int PER_WAVE = ITEMS / BIN_WAVES;
+    const int base = blk * ITEMS + wave * PER_WAVE;
+    for (int step = 0; step < PER_WAVE / DIGS_WAVE; ++step) {
         const int item = base + step * DIGS_WAVE + lane;
         if (item < src.items) src.load(slice, item).count(h);
     }
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_count(Src src, uint32_t *__
     }
 }
 
-template <class Src>
+template <class Src, int ITEMS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
                                                           const uint32_t *__restrict__ cnt_scan,
                                                           int nbins, int nblk, int nbits)
@@ -66,8 +68,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
     for (int k = threadIdx.x; k < BIN_WAVES * nbins; k += BIN_THREADS) hist[k] = 0;
     __syncthreads();
     uint32_t *h = hist + wave * nbins;
-    const int base = blk * DIGS_BIN_ITEMS + wave * BIN_PER_WAVE;
-    for (int step = 0; step < BIN_PER_WAVE / DIGS_WAVE; ++step) {
+    constexpr int PER_WAVE = ITEMS / BIN_WAVES;
+    const int base = blk * ITEMS + wave * PER_WAVE;
+    for (int step = 0; step < PER_WAVE / DIGS_WAVE; ++step) {
         const int item = base + step * DIGS_WAVE + lane;
         if (item < src.items) src.load(slice, item).count(h);
     }
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
     // so items with many keys do not leave the rest of the wave idle.
     __shared__ int starts[BIN_WAVES][DIGS_WAVE];
     __shared__ typename Src::Item items[BIN_WAVES][DIGS_WAVE];
-    for (int step = 0; step < BIN_PER_WAVE / DIGS_WAVE; ++step) {
+    for (int step = 0; step < PER_WAVE / DIGS_WAVE; ++step) {
         const int item0 = base + step * DIGS_WAVE;
         const int item = item0 + lane;
         const bool valid = item < src.items;
@@ -157,16 +160,23 @@ struct RadixSrc {
 };
 
 // Count, scan and place (see above); the scan runs over (slice, key, block) counts.
+// items: items per workgroup, DIGS_BIN_ITEMS or DIGS_BIN_ITEMS_SMALL (nblk = ceil(items of a
+// slice / items))
 template <class Src>
 static inline hipError_t launch_binning(const Src &src, int slices, int nbins, int nblk, int nbits,
-                                 uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
-                                 hipStream_t s)
+                                        uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
+                                        hipStream_t s, int items = DIGS_BIN_ITEMS)
 {
     const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
+    const bool small = items == DIGS_BIN_ITEMS_SMALL;
     {
         ProfScope ps(PS_BIN_COUNT, s);
-        hipLaunchKernelGGL(k_bin_count<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
-                           cnt, nbins, nblk);
+        if (small)
+            hipLaunchKernelGGL((k_bin_count<Src, DIGS_BIN_ITEMS_SMALL>), dim3(nblk, slices),
+                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk);
+        else
+            hipLaunchKernelGGL((k_bin_count<Src, DIGS_BIN_ITEMS>), dim3(nblk, slices),
+                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -177,8 +187,12 @@ static inline hipError_t launch_binning(const Src &src, int slices, int nbins, i
     if (e != hipSuccess) return e;
     {
         ProfScope ps(PS_BIN_FILL, s);
-        hipLaunchKernelGGL(k_bin_fill<Src>, dim3(nblk, slices), dim3(BIN_THREADS), lds, s, src,
-                           cnt, nbins, nblk, nbits);
+        if (small)
+            hipLaunchKernelGGL((k_bin_fill<Src, DIGS_BIN_ITEMS_SMALL>), dim3(nblk, slices),
+                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk, nbits);
+        else
+            hipLaunchKernelGGL((k_bin_fill<Src, DIGS_BIN_ITEMS>), dim3(nblk, slices),
+                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk, nbits);
     }
     return hipGetLastError();
 }

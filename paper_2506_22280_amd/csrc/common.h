@@ -10,6 +10,7 @@
 #define DIGS_TILE 16                 // detector tile edge (pixels)
 #define DIGS_TILE_PX (DIGS_TILE * DIGS_TILE)
 #define DIGS_BIN_ITEMS 1024          // items (Gaussians) per binning workgroup: 4 waves x 256
+#define DIGS_BIN_ITEMS_SMALL 256     // the same when a launch would have few workgroups
 #define DIGS_REC_FLOATS 16           // per-(t,n) projected record, 64 bytes
 #define DIGS_PART_FLOATS 12          // per-instance backward partial sums, 48 bytes
 

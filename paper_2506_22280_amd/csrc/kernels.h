@@ -28,6 +28,7 @@ struct WsLayout {
     size_t total;
     // derived sizes
     int n, T, R, nblk, ntiles, ncells, gq_stride;
+    int bin_items;     // Gaussians per tile-binning workgroup (nblk = ceil(n / bin_items))
     int tpc, tchunks;  // views per chunk of the per-Gaussian adjoint, and the number of chunks
     size_t cap;
     size_t scratch_elems;

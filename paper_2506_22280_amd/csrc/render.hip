@@ -1856,7 +1856,7 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     src.tiles_x = a.geom.tiles_x;
     src.inv_tiles_x = 1.0f / (float)a.geom.tiles_x;
     e = launch_binning(src, a.T, a.geom.ntiles, a.L.nblk, bits_for(a.geom.ntiles), cnt,
-                       cnt_elems + 1, scratch, s);
+                       cnt_elems + 1, scratch, s, a.L.bin_items);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_check, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *));
     return hipGetLastError();
