@@ -905,10 +905,11 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // 64 list entries and appends the (entry, 8x8 block) pairs whose footprint ellipse meets the block
 // (block-major) to one of two pair queues in LDS: pairs whose ellipse meets both 4-row halves of
 // the block run over its 8 rows, the others over the one half they meet. Each queue is evaluated
-// 64 pairs at a time, one pair per lane, and its remainder is carried over to the next chunk, so that lanes idle only when a chunk
-// must be finished early (below) and at the end of the tile. A lane runs over its block's 64
-// pixels with forward differences along each row and accumulates twelve moment sums, which are
-// added into the entry's LDS slot in block order (fixed order, no atomics). Entry slots belong to
+// 64 pairs at a time, one pair per lane, and its remainder is carried over to the next chunk, so
+// that lanes idle only when a chunk must be finished early (below) and at the end of the tile. A
+// lane runs over its pair's 64 (or 32) pixels with forward differences along each row and
+// accumulates twelve moment sums, which are added into the entry's LDS slot in block order (fixed
+// order, no atomics). Entry slots belong to
 // two chunks in turn; once the pairs of a chunk are all evaluated (by the end of the next chunk's
 // step, with a partial group if no full one forms), its entries are written as the instances'
 // partials, at each instance's slot in Gaussian-major order (so that the per-Gaussian reduction
