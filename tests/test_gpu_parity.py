@@ -295,6 +295,55 @@ def test_project_bwd_identities():
         assert abs(lhs - rhs) <= 2e-4 * max(abs(lhs), 1e-12), (r, lhs, rhs)
 
 
+def test_project_bwd_full_size_sampled():
+    """The benchmark's launch: 200k Gaussians, 512x384, a batch of 64 uneven-time views, through
+    an autotuned plan. dL/dI is nonzero on 2 x 96 sampled pixels (views 0 and 63), so that the
+    oracle's adjoint over those pixels alone is the whole gradient; then with a dense dL/dI the
+    rho-linearity identity sum_n rho_n dL/drho_n = L at full size."""
+    _print("case: project_bwd 200k Gaussians 512x384, batch of 64 views (plan), sampled pixels")
+    p = synth.batched(seed=0)
+    batch = synth.batch_schedule(len(p.angles), 64, seed=0)[0]
+    angles, w = p.views(batch)
+    T, n, nv, nu = len(batch), p.n, p.geom["nv"], p.geom["nu"]
+    rng = np.random.default_rng(11)
+    sel, m = np.array([0, 63]), 96
+    pt = np.repeat(sel, m)
+    pj = rng.integers(0, nv, pt.size)
+    pi = rng.integers(0, nu, pt.size)
+    pg = rng.normal(0, 1, pt.size).astype(np.float32)
+    G = np.zeros((T, nv, nu), np.float32)
+    np.add.at(G, (pt, pj, pi), pg)
+    b = dict(problem_tensors(p, batch), proj=torch.empty((T, nv, nu), device="cuda"),
+             grad_proj=dev(G), g_mu=torch.empty((3, n), device="cuda"),
+             g_scale=torch.empty((3, n), device="cuda"), g_quat=torch.empty((4, n), device="cuda"),
+             g_rho=torch.empty((n,), device="cuda"), g_coef=torch.empty_like(dev(p.coef)),
+             g_w=torch.empty((T, p.grid["R"]), device="cuda"))
+    with _lib.Plan(p.geom, p.grid, n, T, b) as plan:
+        _print("tuning", plan.tuning()[0])
+        plan.fwd()
+        plan.bwd()
+        diag, resized = plan.check()
+        assert not resized and diag["overflow"] == 0 and diag["nonfinite"] == 0
+        got = {k: b[k].double().cpu().numpy() for k in
+               ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef", "g_w")}
+        # a dense dL/dI through the same plan: rho-linearity of the whole projection
+        Gd = rng.normal(0, 1, (T, nv, nu)).astype(np.float32)
+        b["grad_proj"].copy_(dev(Gd))
+        plan.bwd()
+        torch.cuda.synchronize()
+        L = float((b["proj"].double().cpu().numpy() * Gd).sum())
+        lhs = float((b["g_rho"].double().cpu().numpy() * p.rho).sum())
+        _print("rho-linearity", lhs, L)
+        assert abs(lhs - L) <= 1e-5 * abs(L)
+    ref = oracle.project_bwd(p.geom, p.grid, p.coef, p.mu, p.scale, p.quat, p.rho, angles, w,
+                             pixels=(pt, pj, pi, pg))
+    errs = {k: norm_rel(got[k], ref[k]) for k in ref}
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+
+
 def test_temporal_weights_matches_oracle():
     _print("case: temporal weights, 40 control values x rank 3, 1320 time points (some outside)")
     rng = np.random.default_rng(61)
