@@ -227,6 +227,43 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _shape(name, t, shape):
+    """Raise unless tensor t (or None, if allowed by the caller) has exactly this shape: the
+    library indexes every buffer by the sizes passed beside it, so a smaller tensor would be read
+    or written past its end."""
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+def _lattice(grid: dict):
+    return (grid["R"], grid["nz"], grid["ny"], grid["nx"], 3)
+
+
+def _gaussians(n, mu, scale, quat, rho):
+    _shape("mu", mu, (3, n))
+    _shape("scale", scale, (3, n))
+    _shape("quat", quat, (4, n))
+    _shape("rho", rho, (n,))
+
+
+def _views(T, R, angles, w):
+    _shape("angles", angles, (T,))
+    _shape("w", w, (T, R))
+
+
+def _same_numel(name, t, numel):
+    if t is not None and t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+
+
+def _grad_shapes(out: dict, motion: str, motion_shape, n, T, R):
+    for k, shp in (("g_mu", (3, n)), ("g_scale", (3, n)), ("g_quat", (4, n)), ("g_rho", (n,)),
+                   (motion, motion_shape), ("g_w", (T, R))):
+        _shape(k, out.get(k), shp)
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -242,6 +279,10 @@ def ffd_eval(grid: dict, coef, x, w=None, jac=True, stream=None):
     n = x.shape[1]
     R = grid["R"]
     lead = R if w is None else w.shape[0]
+    _shape("coef", coef, _lattice(grid))
+    _shape("x", x, (3, n))
+    if w is not None:
+        _shape("w", w, (lead, R))
     disp = torch.empty((lead, 3, n), device=x.device, dtype=torch.float32)
     J = torch.empty((lead, 9, n), device=x.device, dtype=torch.float32) if jac else None
     G = make_grid(grid)
@@ -254,6 +295,11 @@ def ffd_eval(grid: dict, coef, x, w=None, jac=True, stream=None):
 def deform_gaussians(grid: dict, coef, mu, scale, quat, w, stream=None):
     """mu_t [T][3][n], cov_t [T][6][n] of the deformation-informed warp (Eq. 7-8)."""
     n, T = mu.shape[1], w.shape[0]
+    _shape("coef", coef, _lattice(grid))
+    _shape("mu", mu, (3, n))
+    _shape("scale", scale, (3, n))
+    _shape("quat", quat, (4, n))
+    _shape("w", w, (T, grid["R"]))
     mu_t = torch.empty((T, 3, n), device=mu.device, dtype=torch.float32)
     cov_t = torch.empty((T, 6, n), device=mu.device, dtype=torch.float32)
     G = make_grid(grid)
@@ -276,6 +322,7 @@ def temporal_weights(ctrl, t0: float, dt: float, times, stream=None):
 def temporal_weights_bwd(Ct: int, t0: float, dt: float, times, g_w, stream=None):
     """dL/dctrl [Ct][R] given dL/dw [T][R]."""
     T, R = g_w.shape
+    _shape("times", times, (T,))
     g = torch.empty((Ct, R), device=g_w.device, dtype=torch.float32)
     _check("digs_temporal_weights_bwd", load().digs_temporal_weights_bwd(
         Ct, R, float(t0), float(dt), T, _ptr(times), _ptr(g_w), _ptr(g), _stream(stream)))
@@ -328,6 +375,11 @@ def project_fwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, w
                 tuning: dict | None = None, proj=None, stream=None):
     """proj [T][nv][nu] of the deformed Gaussians (Eq. 1, 3, 4, 6)."""
     n, T = mu.shape[1], angles.shape[0]
+    _shape("coef", coef, _lattice(grid))
+    _gaussians(n, mu, scale, quat, rho)
+    _views(T, grid["R"], angles, w)
+    if proj is not None:
+        _shape("proj", proj, (T, geom["nv"], geom["nu"]))
     G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
     nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
     if nbytes == 0:
@@ -348,6 +400,12 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
                 stream=None):
     """dL/d(mu, scale, quat, rho, coef, w) given dL/dproj (hand-written adjoint)."""
     n, T = mu.shape[1], angles.shape[0]
+    _shape("coef", coef, _lattice(grid))
+    _gaussians(n, mu, scale, quat, rho)
+    _views(T, grid["R"], angles, w)
+    _shape("grad_proj", grad_proj, (T, geom["nv"], geom["nu"]))
+    if out is not None:
+        _grad_shapes(out, "g_coef", _lattice(grid), n, T, grid["R"])
     G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
     nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
     if nbytes == 0:
@@ -376,6 +434,11 @@ def project_basis_fwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angle
     """The forward with the second ablation's motion model: basis [R][12][n] per Gaussian
     instead of the lattice (grid gives R and the lattice geometry that orders the Gaussians)."""
     n, T = mu.shape[1], angles.shape[0]
+    _shape("basis", basis, (grid["R"], 12, n))
+    _gaussians(n, mu, scale, quat, rho)
+    _views(T, grid["R"], angles, w)
+    if proj is not None:
+        _shape("proj", proj, (T, geom["nv"], geom["nu"]))
     G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
     nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
     if nbytes == 0:
@@ -397,6 +460,12 @@ def project_basis_bwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angle
     """dL/d(mu, scale, quat, rho, basis, w) of the basis model (reuse_fwd: ws holds the state
     of a project_basis_fwd with the same inputs)."""
     n, T = mu.shape[1], angles.shape[0]
+    _shape("basis", basis, (grid["R"], 12, n))
+    _gaussians(n, mu, scale, quat, rho)
+    _views(T, grid["R"], angles, w)
+    _shape("grad_proj", grad_proj, (T, geom["nv"], geom["nu"]))
+    if out is not None:
+        _grad_shapes(out, "g_basis", (grid["R"], 12, n), n, T, grid["R"])
     G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
     nbytes = int(load().digs_workspace_size(ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu)))
     if nbytes == 0:
@@ -460,6 +529,14 @@ class Plan:
     def __init__(self, geom: dict, grid: dict, n: int, T: int, buffers: dict,
                  tuning: dict | None = None):
         self.buffers = dict(buffers)
+        R, nv, nu = grid["R"], geom["nv"], geom["nu"]
+        expect = dict(coef=_lattice(grid), mu=(3, n), scale=(3, n), quat=(4, n), rho=(n,),
+                      angles=(T,), w=(T, R), proj=(T, nv, nu), grad_proj=(T, nv, nu),
+                      g_mu=(3, n), g_scale=(3, n), g_quat=(4, n), g_rho=(n,),
+                      g_coef=_lattice(grid), g_w=(T, R))
+        for k, shp in expect.items():
+            if self.buffers.get(k) is not None:
+                _shape(k, self.buffers[k], shp)
         B = PlanBuffers()
         for k, _ in PlanBuffers._fields_:
             t = self.buffers.get(k)
@@ -543,6 +620,8 @@ def mse(pred, target, mean, std, dpred, loss=None, stream=None):
 
 
 def adam(w, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    for k, t in (("g", g), ("m", m), ("v", v)):
+        _same_numel(k, t, w.numel())
     _check("digs_adam", load().digs_adam(w.numel(), _ptr(w), _ptr(g), _ptr(m), _ptr(v),
                                          float(lr), float(b1), float(b2), float(eps), int(step),
                                          _stream(stream)))
@@ -557,6 +636,9 @@ L2_PARTS = 256   # DIGS_L2_PARTS
 def l2_residual(proj, meas, grad, loss=None, stream=None):
     """grad = proj - meas and (if loss, a device tensor of 1 + L2_PARTS floats)
     loss[0] = 1/2 ||proj - meas||^2."""
+    _same_numel("meas", meas, proj.numel())
+    _same_numel("grad", grad, proj.numel())
+    _same_numel("loss", loss, 1 + L2_PARTS)
     _check("digs_l2_residual", load().digs_l2_residual(proj.numel(), _ptr(proj), _ptr(meas),
                                                        _ptr(grad), _ptr(loss), _stream(stream)))
 
@@ -564,6 +646,8 @@ def l2_residual(proj, meas, grad, loss=None, stream=None):
 def adam_mapped(raw, value, g_value, m, v, lr, step, mapping="identity", b1=0.9, b2=0.999,
                 eps=1e-8, stream=None):
     """One Adam step on raw given dL/dvalue, value = mapping(raw) (rewritten)."""
+    for k, t in (("value", value), ("g_value", g_value), ("m", m), ("v", v)):
+        _same_numel(k, t, raw.numel())
     _check("digs_adam_mapped", load().digs_adam_mapped(
         raw.numel(), _ptr(raw), _ptr(value), _ptr(g_value), _ptr(m), _ptr(v), float(lr),
         float(b1), float(b2), float(eps), int(step), MAPS[mapping], _stream(stream)))
@@ -596,6 +680,8 @@ def standardize(X, mean, istd, ncols: int | None = None, stream=None):
 def dvf_grid(grid: dict, coef, w, vgrid: dict, stream=None):
     """dvf [3][nz][ny][nx] = sum_r w_r u_r(x) at the voxel centres (w: device [R])."""
     V = make_vgrid(vgrid)
+    _shape("coef", coef, _lattice(grid))
+    _shape("w", w, (grid["R"],))
     out = torch.empty((3, V.nz, V.ny, V.nx), device=coef.device)
     G = make_grid(grid)
     _check("digs_dvf_grid", load().digs_dvf_grid(ctypes.byref(G), _ptr(coef), _ptr(w),
@@ -610,8 +696,13 @@ def phi_grid(grid: dict, coef, mu, scale, quat, rho, w, vgrid: dict, ws: "Worksp
     the call repeat with the capacity the diagnostics say is needed (this synchronises)."""
     V, G = make_vgrid(vgrid), make_grid(grid)
     n = mu.shape[1]
+    _shape("coef", coef, _lattice(grid))
+    _gaussians(n, mu, scale, quat, rho)
+    _shape("w", w, (grid["R"],))
     if out is None:
         out = torch.empty((V.nz, V.ny, V.nx), device=mu.device)
+    else:
+        _shape("out", out, (V.nz, V.ny, V.nx))
     while True:
         nbytes = int(load().digs_phi_workspace_size(ctypes.byref(V), n, int(capacity)))
         if nbytes == 0:

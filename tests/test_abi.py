@@ -72,3 +72,38 @@ def test_host_side_validation_and_sizes():
                               ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
                               16, ctypes.byref(t), None)
     assert rc == -2
+
+
+def test_binding_rejects_mismatched_shapes():
+    """The library indexes each buffer by the sizes passed beside it; the binding checks every
+    tensor's shape against them first (host side, before any device call)."""
+    import torch
+    from paper_2506_22280_amd import _lib, synth
+    p = synth.tiny(n=16, nviews=2, det=16)
+    n, T, R = p.n, 2, p.grid["R"]
+    good = dict(coef=torch.zeros(p.coef.shape), mu=torch.zeros(3, n), scale=torch.ones(3, n),
+                quat=torch.zeros(4, n), rho=torch.zeros(n), angles=torch.zeros(T),
+                w=torch.zeros(T, R))
+    ws = _lib.Workspace(device="cpu")
+    cases = [("scale", torch.ones(3, n - 1)), ("quat", torch.zeros(3, n)),
+             ("rho", torch.zeros(n + 1)), ("w", torch.zeros(T, R + 1)),
+             ("angles", torch.zeros(T, 1)), ("coef", torch.zeros(R, 8, 8, 7, 3))]
+    for name, bad in cases:
+        a = dict(good, **{name: bad})
+        with pytest.raises(ValueError, match=name):
+            _lib.project_fwd(p.geom, p.grid, a["coef"], a["mu"], a["scale"], a["quat"], a["rho"],
+                             a["angles"], a["w"], ws)
+    with pytest.raises(ValueError, match="grad_proj"):
+        _lib.project_bwd(p.geom, p.grid, *good.values(), torch.zeros(T, 16, 15), ws)
+    with pytest.raises(ValueError, match="proj"):
+        _lib.project_fwd(p.geom, p.grid, *good.values(), ws, proj=torch.zeros(T + 1, 16, 16))
+    with pytest.raises(ValueError, match="g_rho"):
+        out = dict(g_mu=torch.zeros(3, n), g_scale=torch.zeros(3, n), g_quat=torch.zeros(4, n),
+                   g_rho=torch.zeros(n - 1), g_coef=torch.zeros(p.coef.shape),
+                   g_w=torch.zeros(T, R))
+        _lib.project_bwd(p.geom, p.grid, *good.values(), torch.zeros(T, 16, 16), ws, out=out)
+    with pytest.raises(ValueError, match="g_w"):
+        bufs = dict(good, proj=torch.zeros(T, 16, 16), g_w=torch.zeros(T + 1, R))
+        _lib.Plan(p.geom, p.grid, n, T, bufs)
+    with pytest.raises(ValueError, match="v"):
+        _lib.adam(torch.zeros(10), torch.zeros(10), torch.zeros(10), torch.zeros(9), 1e-3, 1)
