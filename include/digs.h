@@ -163,6 +163,8 @@ int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *
  * [T][nv][nu], writes dL/d(each input):
  *   g_mu [3][n], g_scale [3][n], g_quat [4][n], g_rho [n], g_coef [R][nz][ny][nx][3], g_w [T][R]
  * The mean gradient includes the term through K(mu) (second derivatives of the B-spline).
+ * A Gaussian whose inputs the forward rejects (non-finite mean, quaternion or density, a scale
+ * that is not positive; counted in nonfinite) gets zero gradients and adds nothing to g_coef.
  * Without DIGS_BWD_REUSE_FWD in `flags` the forward set-up and binning are recomputed.
  * Reductions are fixed-order: results are bitwise reproducible run to run.
  * Errors: DIGS_EINVAL, DIGS_ENOWS, DIGS_EHIP. */

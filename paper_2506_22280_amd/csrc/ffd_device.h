@@ -19,7 +19,11 @@ __device__ __forceinline__ void make_stencil(const DevGrid &g, float x, float y,
                                              Stencil &s, bool second)
 {
     const float qx = (x - g.ox) / g.hx, qy = (y - g.oy) / g.hy, qz = (z - g.oz) / g.hz;
-    const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+    // the cell is taken from the coordinate clamped to +-1e6 cells, so that a non-finite point
+    // still converts to a valid integer; its fraction (and hence its weights) stays non-finite
+    const float fx = floorf(fminf(fmaxf(qx, -1.0e6f), 1.0e6f));
+    const float fy = floorf(fminf(fmaxf(qy, -1.0e6f), 1.0e6f));
+    const float fz = floorf(fminf(fmaxf(qz, -1.0e6f), 1.0e6f));
     s.fx = (int)fx;
     s.fy = (int)fy;
     s.fz = (int)fz;

@@ -1589,6 +1589,28 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
 #pragma unroll
     for (int a = 0; a < 4; ++a) q[a] = gpar[(size_t)(6 + a) * n + i];
     const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    // a Gaussian whose inputs the set-up rejects (non-finite mean, quaternion or density, a scale
+    // that is not positive) was skipped in every view: all its gradients are zero, and it adds
+    // nothing to dL/dcoef (its B-spline weights may be NaN, and NaN * 0 is NaN)
+    const float mu0[3] = {gpar[i], gpar[(size_t)n + i], gpar[(size_t)2 * n + i]};
+    const bool inputs_ok = isfinite(mu0[0]) && isfinite(mu0[1]) && isfinite(mu0[2]) &&
+                           s[0] > 0.0f && s[1] > 0.0f && s[2] > 0.0f &&
+                           isfinite(1.0f / s[0] * (1.0f / s[1]) * (1.0f / s[2])) && isfinite(qn) &&
+                           isfinite(gpar[(size_t)10 * n + i]);
+    if (!inputs_ok) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gmu[a] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gRS[k] = 0.0f;
+        grho = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) P[r][a] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Q[r][k] = 0.0f;
+        }
+    }
     const float qh[4] = {q[0] * qn, q[1] * qn, q[2] * qn, q[3] * qn};
     float Rm[9];
     quat_to_rot(qh[0], qh[1], qh[2], qh[3], Rm);
@@ -1608,7 +1630,12 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
         g_scale[(size_t)a * n + src] = gs[a];
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) g_quat[(size_t)a * n + src] = (gqh[a] - dq * qh[a]) * qn;
+    for (int a = 0; a < 4; ++a)
+        g_quat[(size_t)a * n + src] = inputs_ok ? (gqh[a] - dq * qh[a]) * qn : 0.0f;
+    if (!inputs_ok) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g_scale[(size_t)a * n + src] = 0.0f;
+    }
     g_rho[src] = grho;
     if (g_basis) {   // dL/du_r = P_r, dL/dV_r = Q_r, at the Gaussian's own index
 #pragma unroll
@@ -1626,9 +1653,9 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     o[0] = __int_as_float(max(-2, min(st.fx, grid.nx + 1)));
     o[1] = __int_as_float(max(-2, min(st.fy, grid.ny + 1)));
     o[2] = __int_as_float(max(-2, min(st.fz, grid.nz + 1)));
-    o[3] = st.px;
-    o[4] = st.py;
-    o[5] = st.pz;
+    o[3] = inputs_ok ? st.px : 0.0f;
+    o[4] = inputs_ok ? st.py : 0.0f;
+    o[5] = inputs_ok ? st.pz : 0.0f;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
 #pragma unroll

@@ -156,6 +156,44 @@ def test_edge_cases():
     assert d["overflow"] == 1 and d["instances"] > 8
 
 
+def test_invalid_gaussians_are_skipped():
+    _print("case: Gaussians with a NaN or infinite mean, a zero scale, a zero quaternion or a NaN "
+           "density among 300 valid ones (3 views 40x40): skipped, counted, zero gradients")
+    p = synth.tiny(seed=51, n=305, nviews=3, det=40)
+    T = len(p.angles)
+    bad = p.n - 5 + np.arange(5)
+    p.mu[:, bad[0]] = np.nan
+    p.mu[1, bad[1]] = np.inf
+    p.scale[0, bad[2]] = 0.0
+    p.quat[:, bad[3]] = 0.0
+    p.rho[bad[4]] = np.nan
+    good = np.arange(p.n - 5)
+    t = problem_tensors(p)
+    proj, ws = _fwd(p, t)
+    d = ws.diagnostics()
+    assert d["nonfinite"] == 5 * T and d["overflow"] == 0, d
+    keep = (p.coef, p.mu[:, good], p.scale[:, good], p.quat[:, good], p.rho[good], p.angles, p.w)
+    ref = oracle.project(p.geom, p.grid, *keep)
+    for k in range(T):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+    G = np.random.default_rng(52).normal(0, 1, ref.shape).astype(np.float32)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho"):
+        assert np.all(got[k][..., bad] == 0.0), k
+    gref = oracle.project_bwd(p.geom, p.grid, *keep, grad_proj=G)
+    errs = {k: norm_rel(got[k][..., good], gref[k]) for k in ("g_mu", "g_scale", "g_quat", "g_rho")}
+    errs["g_coef"] = norm_rel(got["g_coef"], gref["g_coef"])
+    errs["g_w"] = norm_rel(got["g_w"], gref["g_w"])
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+
+
 # ------------------------------------------------------------------------------------------------
 # Backward
 def _bwd_problem():
