@@ -72,6 +72,13 @@ def test_host_side_validation_and_sizes():
                               ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
                               16, ctypes.byref(t), None)
     assert rc == -2
+    # so is a workspace that is not 256-byte aligned, however large
+    rc = lib.digs_project_fwd(ctypes.byref(G), ctypes.byref(R), ctypes.c_void_p(256), 10,
+                              ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                              ctypes.c_void_p(256), 1, ctypes.c_void_p(256),
+                              ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(128),
+                              1 << 40, ctypes.byref(t), None)
+    assert rc == -2
 
 
 def test_binding_rejects_mismatched_shapes():

@@ -194,6 +194,37 @@ def test_invalid_gaussians_are_skipped():
     assert errs["g_w"] <= 1e-3
 
 
+def test_folded_deformation_matches_oracle():
+    _print("case: a deformation with det K < 0 (u_x = -2.5 x on the lattice, the means inside its "
+           "exact region), 400 Gaussians, 3 views 40x40: rendered, counted, fwd and bwd parity")
+    p = synth.tiny(seed=61, n=400, nviews=3, det=40)
+    g = p.grid
+    x_cp = g["origin"][0] + g["spacing"][0] * np.arange(g["nx"])
+    coef = np.zeros_like(p.coef)
+    coef[0, :, :, :, 0] = -2.5 * x_cp[None, None, :]    # cubic B-splines reproduce it exactly
+    p.coef = coef.astype(np.float32)
+    p.w = np.tile(np.array([[1.0, 0.0, 0.0]], np.float32), (len(p.angles), 1))
+    T = len(p.angles)
+    t = problem_tensors(p)
+    proj, ws = _fwd(p, t)
+    d = ws.diagnostics()
+    assert d["folded"] == p.n * T and d["nonfinite"] == 0, d
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(T):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+    G = np.random.default_rng(62).normal(0, 1, ref.shape).astype(np.float32)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True)
+    torch.cuda.synchronize()
+    gref = oracle.project_bwd(p.geom, p.grid, *oracle_inputs(p), grad_proj=G)
+    errs = {k: norm_rel(out[k].cpu().numpy(), gref[k]) for k in gref}
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+
+
 # ------------------------------------------------------------------------------------------------
 # Backward
 def _bwd_problem():
