@@ -1723,8 +1723,8 @@ __global__ void k_cell_start(int n, int ncells, const uint32_t *__restrict__ key
 }
 
 // One wave per control point: for each (cz, cy) row of its candidate cells the Gaussians of
-// the cells cx = lx..hx are contiguous in cell order; lanes stride over them, and the per-lane
-// sums are reduced over the wave in a fixed order.
+// the cells cx = lx..hx are contiguous in cell order; the lanes take the rows' Gaussians 64 at a
+// time over all rows together, and the per-lane sums are reduced over the wave in a fixed order.
 template <int NR>
 __global__ __launch_bounds__(256) void k_coef_grad(DevGrid g, const float *__restrict__ gq,
                                                    int gq_stride,
@@ -1743,42 +1743,67 @@ __global__ __launch_bounds__(256) void k_coef_grad(DevGrid g, const float *__res
     const int ly = (j == 0) ? -2 : j - 2, hy = (j == g.ny - 1) ? g.ny + 1 : j + 1;
     const int lz = (k == 0) ? -2 : k - 2, hz = (k == g.nz - 1) ? g.nz + 1 : k + 1;
     const float ihx = 1.0f / g.hx, ihy = 1.0f / g.hy, ihz = 1.0f / g.hz;
-    for (int cz = lz; cz <= hz; ++cz)
-        for (int cy = ly; cy <= hy; ++cy) {
-            const uint32_t row = ((uint32_t)(cz + 2) * (g.ny + 4) + (cy + 2)) * (g.nx + 4);
-            const uint32_t b = cell_start[row + (lx + 2)], e = cell_start[row + (hx + 2) + 1];
-            for (uint32_t p = b + lane; p < e; p += DIGS_WAVE) {
-                const float *o = gq + (size_t)p * gq_stride;
-                const int cx = __float_as_int(o[0]);
-                float B[4], dB[4];
-                float wx = 0.f, dwx = 0.f, wy = 0.f, dwy = 0.f, wz = 0.f, dwz = 0.f;
-                bspline4(o[3], B);
-                bspline4_d(o[3], dB);
+    // The support's cell rows (cz, cy), at most 5 x 5, each a contiguous range of Gaussians in
+    // cell order: lane r < nrows holds row r's range, and the rows' Gaussians are taken 64 at a
+    // time over all rows together (a row holds only a few Gaussians).
+    const int nry = hy - ly + 1, nrows = (hz - lz + 1) * nry;
+    uint32_t rb = 0, rlen = 0;
+    if (lane < nrows) {
+        const int cz = lz + lane / nry, cy = ly + lane % nry;
+        const uint32_t row = ((uint32_t)(cz + 2) * (g.ny + 4) + (cy + 2)) * (g.nx + 4);
+        rb = cell_start[row + (lx + 2)];
+        rlen = cell_start[row + (hx + 2) + 1] - rb;
+    }
+    // inclusive prefix sum of the row lengths over lanes 0..31 (nrows <= 25)
+    uint32_t incl = rlen;
 #pragma unroll
-                for (int l = 0; l < 4; ++l)
-                    if (clampi(cx - 1 + l, g.nx) == i) { wx += B[l]; dwx += dB[l]; }
-                bspline4(o[4], B);
-                bspline4_d(o[4], dB);
+    for (int off = 1; off < 32; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, DIGS_WAVE);
+        if (lane >= off) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 31, DIGS_WAVE);
+    for (uint32_t q0 = 0; q0 < total; q0 += DIGS_WAVE) {
+        // the row of flattened index q: the first lane whose inclusive sum exceeds q (the
+        // shuffles run with every lane active; lanes past the end then skip the work)
+        const uint32_t q = q0 + (uint32_t)lane;
+        int row = 0;
 #pragma unroll
-                for (int l = 0; l < 4; ++l)
-                    if (clampi(cy - 1 + l, g.ny) == j) { wy += B[l]; dwy += dB[l]; }
-                bspline4(o[5], B);
-                bspline4_d(o[5], dB);
+        for (int step = 16; step >= 1; step >>= 1)
+            if (__shfl(incl, row + step - 1, DIGS_WAVE) <= q) row += step;
+        row = min(row, 31);
+        const uint32_t p = __shfl(rb, row, DIGS_WAVE) + q -
+                           (__shfl(incl, row, DIGS_WAVE) - __shfl(rlen, row, DIGS_WAVE));
+        if (q >= total) continue;
+        const float *o = gq + (size_t)p * gq_stride;
+        // the Gaussian's (clamped) cell
+        const int cx = __float_as_int(o[0]), cy = __float_as_int(o[1]), cz = __float_as_int(o[2]);
+        float B[4], dB[4];
+        float wx = 0.f, dwx = 0.f, wy = 0.f, dwy = 0.f, wz = 0.f, dwz = 0.f;
+        bspline4(o[3], B);
+        bspline4_d(o[3], dB);
 #pragma unroll
-                for (int l = 0; l < 4; ++l)
-                    if (clampi(cz - 1 + l, g.nz) == k) { wz += B[l]; dwz += dB[l]; }
-                const float w0 = wx * wy * wz, w1 = dwx * ihx * wy * wz,
-                            w2 = wx * dwy * ihy * wz, w3 = wx * wy * dwz * ihz;
+        for (int l = 0; l < 4; ++l)
+            if (clampi(cx - 1 + l, g.nx) == i) { wx += B[l]; dwx += dB[l]; }
+        bspline4(o[4], B);
+        bspline4_d(o[4], dB);
 #pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    const float *Pr = o + 6 + 12 * r, *Qr = Pr + 3;
+        for (int l = 0; l < 4; ++l)
+            if (clampi(cy - 1 + l, g.ny) == j) { wy += B[l]; dwy += dB[l]; }
+        bspline4(o[5], B);
+        bspline4_d(o[5], dB);
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        acc[r][a] += w0 * Pr[a] + w1 * Qr[3 * a] + w2 * Qr[3 * a + 1] +
-                                     w3 * Qr[3 * a + 2];
-                }
-            }
+        for (int l = 0; l < 4; ++l)
+            if (clampi(cz - 1 + l, g.nz) == k) { wz += B[l]; dwz += dB[l]; }
+        const float w0 = wx * wy * wz, w1 = dwx * ihx * wy * wz, w2 = wx * dwy * ihy * wz,
+                    w3 = wx * wy * dwz * ihz;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const float *Pr = o + 6 + 12 * r, *Qr = Pr + 3;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                acc[r][a] += w0 * Pr[a] + w1 * Qr[3 * a] + w2 * Qr[3 * a + 1] + w3 * Qr[3 * a + 2];
         }
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
