@@ -379,7 +379,7 @@ def main():
                          "MiB three times (the reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the renderer has no multi-GPU path in this build "
+        print("bench.py runs on one GPU only: the renderer has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

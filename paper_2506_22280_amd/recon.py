@@ -30,7 +30,7 @@ import torch
 from . import _lib
 
 # Initial and final learning rates. The two B-spline grids follow Sec. 4.2; the Gaussians' rates
-# are this build's reading (the paper defers them to R2-Gaussian): means in mm, log-scales,
+# are a reading of the paper (which defers them to R2-Gaussian): means in mm, log-scales,
 # quaternions and softplus-densities in their own units.
 LR = {"mu": (0.05, 0.0005), "log_scale": (5e-3, 5e-4), "quat": (1e-3, 1e-4),
       "rho_raw": (1e-2, 1e-3), "coef": (1e-4, 1e-5), "ctrl": (1e-2, 1e-3)}
