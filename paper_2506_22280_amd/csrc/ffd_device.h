@@ -59,9 +59,18 @@ __device__ __forceinline__ void make_stencil(const DevGrid &g, float x, float y,
     }
 }
 
+// element n of a 4-array without dynamic register indexing (selects, no scratch)
+template <class T>
+__device__ __forceinline__ T pick4(const T (&v)[4], int n)
+{
+    return n == 0 ? v[0] : (n == 1 ? v[1] : (n == 2 ? v[2] : v[3]));
+}
+
 // u_r and grad u_r (row-major, J[3a+b] = du_a/dx_b) of one rank at the stencil's point.
+// With NZ < 4, only the stencil's z index nz0 (its partial sum; the caller adds the four).
+template <int NZ = 4>
 __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restrict__ coef, int r,
-                                         const Stencil &s, float u[3], float J[9])
+                                         const Stencil &s, float u[3], float J[9], int nz0 = 0)
 {
     const float *base = coef + (size_t)r * g.nz * g.ny * g.nx * 3;
 #pragma unroll
@@ -69,10 +78,15 @@ __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restri
 #pragma unroll
     for (int k = 0; k < 9; ++k) J[k] = 0.f;
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int nn = 0; nn < NZ; ++nn) {
+        // z index n (selected without dynamic register indexing when it is a run-time value)
+        const int n = NZ == 4 ? nn : nz0;
+        const int kk = NZ == 4 ? s.kk[nn] : pick4(s.kk, n);
+        const float Bz = NZ == 4 ? s.Bz[nn] : pick4(s.Bz, n);
+        const float dBz = NZ == 4 ? s.dBz[nn] : pick4(s.dBz, n);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const float *row = base + ((size_t)(s.kk[n] * g.ny + s.jj[m]) * g.nx) * 3;
+            const float *row = base + ((size_t)(kk * g.ny + s.jj[m]) * g.nx) * 3;
             float sx[3] = {0.f, 0.f, 0.f}, sdx[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
@@ -84,8 +98,7 @@ __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restri
                     sdx[a] = fmaf(s.dBx[l], v, sdx[a]);
                 }
             }
-            const float wyz = s.By[m] * s.Bz[n], wdy = s.dBy[m] * s.Bz[n],
-                        wdz = s.By[m] * s.dBz[n];
+            const float wyz = s.By[m] * Bz, wdy = s.dBy[m] * Bz, wdz = s.By[m] * dBz;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 u[a] = fmaf(wyz, sx[a], u[a]);
@@ -97,24 +110,17 @@ __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restri
     }
 }
 
-// element n of a 4-array without dynamic register indexing (selects, no scratch)
-template <class T>
-__device__ __forceinline__ T pick4(const T (&v)[4], int n)
-{
-    return n == 0 ? v[0] : (n == 1 ? v[1] : (n == 2 ? v[2] : v[3]));
-}
-
 // sum_{a,b} Q[3a+b] * d^2 u_a / dx_b dx_c for one rank (the term of dL/dmu through K(mu)),
-// accumulated into h[c]. The z and y loops stay rolled (registers); their per-index values are
+// accumulated into h[c] (over the stencil's z indices n0..n1-1). The z and y loops stay rolled (registers); their per-index values are
 // selected.
 __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
                                                           const float *__restrict__ coef, int r,
                                                           const Stencil &s, const float Q[9],
-                                                          float h[3])
+                                                          float h[3], int n0 = 0, int n1 = 4)
 {
     const float *base = coef + (size_t)r * g.nz * g.ny * g.nx * 3;
 #pragma unroll 1
-    for (int n = 0; n < 4; ++n) {
+    for (int n = n0; n < n1; ++n) {
         const int kk = pick4(s.kk, n);
         const float Bz = pick4(s.Bz, n), dBz = pick4(s.dBz, n), d2Bz = pick4(s.d2Bz, n);
 #pragma unroll 1

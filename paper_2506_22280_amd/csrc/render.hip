@@ -100,20 +100,27 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
                                                        float *__restrict__ uv,
                                                        float *__restrict__ gs)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // four lanes per Gaussian: lane `part` takes the stencil's z index part, and the four partial
+    // sums are added in a fixed order
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gt >> 2, part = gt & 3;
     if (i >= n) return;
     const size_t src = order[i];
-    // the Gaussian's parameters, gathered once into cell order: mu (3), scale (3), quat (4), rho
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        gs[(size_t)a * n + i] = mu[(size_t)a * n + src];
-        gs[(size_t)(3 + a) * n + i] = scale[(size_t)a * n + src];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) gs[(size_t)(6 + a) * n + i] = quat[(size_t)a * n + src];
-    gs[(size_t)10 * n + i] = rho[src];
     float *U = uv, *V = uv + (size_t)3 * g.R * n;
+    if (part == 0) {
+        // the Gaussian's parameters, gathered once into cell order: mu (3), scale (3), quat (4),
+        // rho
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gs[(size_t)a * n + i] = mu[(size_t)a * n + src];
+            gs[(size_t)(3 + a) * n + i] = scale[(size_t)a * n + src];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) gs[(size_t)(6 + a) * n + i] = quat[(size_t)a * n + src];
+        gs[(size_t)10 * n + i] = rho[src];
+    }
     if (basis) {
+        if (part != 0) return;
         for (int r = 0; r < g.R; ++r) {
             const float *b = basis + (size_t)r * 12 * n + src;
 #pragma unroll
@@ -127,11 +134,23 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
     make_stencil(g, mu[src], mu[n + src], mu[2 * n + src], st, false);
     for (int r = 0; r < g.R; ++r) {
         float u[3], J[9];
-        ffd_rank(g, coef, r, st, u, J);
+        ffd_rank<1>(g, coef, r, st, u, J, part);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) U[((size_t)r * 3 + a) * n + i] = u[a];
+        for (int a = 0; a < 3; ++a) {
+            u[a] += __shfl_xor(u[a], 1, DIGS_WAVE);
+            u[a] += __shfl_xor(u[a], 2, DIGS_WAVE);
+        }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) V[((size_t)r * 9 + k) * n + i] = J[k];
+        for (int k = 0; k < 9; ++k) {
+            J[k] += __shfl_xor(J[k], 1, DIGS_WAVE);
+            J[k] += __shfl_xor(J[k], 2, DIGS_WAVE);
+        }
+        if (part == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) U[((size_t)r * 3 + a) * n + i] = u[a];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) V[((size_t)r * 9 + k) * n + i] = J[k];
+        }
     }
 }
 
@@ -1535,7 +1554,10 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     float *__restrict__ g_quat, float *__restrict__ g_rho, float *__restrict__ gq, int gq_stride,
     float *__restrict__ g_basis)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // four lanes per Gaussian: lane `part` takes the stencil's z index part in the second-
+    // derivative term (partial sums added in a fixed order); lane 0 writes the results
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gt >> 2, part = gt & 3;
     if (i >= n) return;
     float gsum[3] = {0.f, 0.f, 0.f}, gRS[9], P[NR][3], Q[NR][9], grho = 0.0f;
 #pragma unroll
@@ -1580,8 +1602,16 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
             }
         const float mu0[3] = {gpar[i], gpar[(size_t)n + i], gpar[(size_t)2 * n + i]};
         make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
+        float hs[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(grid, coef, r, st, Q[r], gmu);
+        for (int r = 0; r < NR; ++r)
+            ffd_rank_hessian_contract(grid, coef, r, st, Q[r], hs, part, part + 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            hs[a] += __shfl_xor(hs[a], 1, DIGS_WAVE);
+            hs[a] += __shfl_xor(hs[a], 2, DIGS_WAVE);
+            gmu[a] += hs[a];
+        }
     }
     // R diag(s) -> s, R(q)
     const float s[3] = {gpar[(size_t)3 * n + i], gpar[(size_t)4 * n + i], gpar[(size_t)5 * n + i]};
@@ -1624,6 +1654,7 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     float gqh[4];
     quat_rot_adjoint(qh[0], qh[1], qh[2], qh[3], gR, gqh);
     const float dq = gqh[0] * qh[0] + gqh[1] * qh[1] + gqh[2] * qh[2] + gqh[3] * qh[3];
+    if (part != 0) return;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         g_mu[(size_t)a * n + src] = gmu[a];
@@ -1874,7 +1905,8 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     if ((e = cell_sort(a, s)) != hipSuccess) return e;
     {
         ProfScope ps(PS_FFD, s);
-        hipLaunchKernelGGL(k_ffd_canonical, dim3((a.n + 255) / 256), dim3(256), 0, s, a.grid,
+        hipLaunchKernelGGL(k_ffd_canonical, dim3((unsigned)(((size_t)4 * a.n + 255) / 256)),
+                           dim3(256), 0, s, a.grid,
                            a.coef, a.basis, a.n, a.mu, a.scale, a.quat, a.rho,
                            WS(a, order, const uint32_t *), WS(a, uv, float *), WS(a, gsort, float *));
     }
@@ -2019,7 +2051,8 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
                            nparts);
         e = hipGetLastError();
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_gauss_reduce<NR>, dim3(nb), dim3(256), 0, s, a.grid, n,
+            hipLaunchKernelGGL(k_gauss_reduce<NR>, dim3((unsigned)(((size_t)4 * n + 255) / 256)),
+                               dim3(256), 0, s, a.grid, n,
                                a.L.tchunks, a.coef, WS(a, gsort, const float *),
                                WS(a, uv, const float *), WS(a, tacc, const float *),
                                WS(a, order, const uint32_t *), g_mu, g_scale, g_quat, g_rho,
