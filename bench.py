@@ -56,9 +56,9 @@ ALGO_BYTES_PER_PROJ = (2 * 200_000 * 44 + 3 * 29 ** 3 * 9 * 4 + 64 * 512 * 384 *
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while the sources are unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2350687.3 * 2.000 * 1024,
-           "write_bytes": 6588247.9 * 1.000 * 1024,
-           "sources_sha256": "3cf1debacd9d215ded0e6dcd68d2b5ed5a2e9b5a48939060510a21202fafc9f2"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2350735.0 * 2.000 * 1024,
+           "write_bytes": 6585630.4 * 1.000 * 1024,
+           "sources_sha256": "fcebd8d6ff6e25535ee307b4edcac13432bc32d14acc93cd43b212bfb880498e"}
 
 
 def sources_digest() -> str:
