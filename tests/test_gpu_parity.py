@@ -441,6 +441,50 @@ def test_every_rank_matches_oracle(R):
     assert errs["g_w"] <= 1e-3
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_configurations_match_oracle(seed):
+    """Seeded random combinations of what the other cases vary one at a time: detector size
+    (ragged tiles), unequal pitches, offsets, source and detector distances, motion rank, number
+    of views and Gaussians, Gaussian sizes and density signs; fwd and bwd against the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    R = int(rng.integers(1, 6))
+    nviews = int(rng.integers(1, 5))
+    n = int(rng.integers(50, 900))
+    nu, nv = int(rng.integers(17, 80)), int(rng.integers(17, 80))
+    _print("case: random configuration seed %d: R=%d, %d views, %d Gaussians, %dx%d detector"
+           % (seed, R, nviews, n, nu, nv))
+    p = synth.tiny(seed=2000 + seed, n=n, nviews=nviews, det=32)
+    p.geom = dict(p.geom, nu=nu, nv=nv, pitch_u=float(rng.uniform(0.6, 1.6)),
+                  pitch_v=float(rng.uniform(0.6, 1.6)), off_u=float(rng.uniform(-6, 6)),
+                  off_v=float(rng.uniform(-6, 6)), sid=float(rng.uniform(600, 1100)))
+    p.geom["sdd"] = p.geom["sid"] * float(rng.uniform(1.2, 1.8))
+    p.scale = np.exp(rng.uniform(np.log(0.6), np.log(6.0), (3, n))).astype(np.float32)
+    p.rho = np.where(rng.random(n) < 0.2, -p.rho, p.rho).astype(np.float32)
+    p.grid = dict(p.grid, R=R)
+    p.coef = rng.normal(0.0, 1.5, (R, 8, 8, 8, 3)).astype(np.float32)
+    p.angles = rng.uniform(0, 2 * np.pi, nviews).astype(np.float32)
+    p.w = rng.uniform(-0.5, 0.5, (nviews, R)).astype(np.float32)
+    t = problem_tensors(p)
+    proj, ws = _fwd(p, t, tuning=dict(capacity=64 * n * nviews))
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0, d
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(nviews):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+    G = rng.normal(0, 1, ref.shape).astype(np.float32)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True,
+                           tuning=dict(capacity=64 * n * nviews))
+    torch.cuda.synchronize()
+    gref = oracle.project_bwd(p.geom, p.grid, *oracle_inputs(p), grad_proj=G)
+    errs = {k: norm_rel(out[k].cpu().numpy(), gref[k]) for k in gref}
+    _print(errs)
+    for k in ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert errs["g_w"] <= 1e-3
+
+
 def test_temporal_weights_matches_oracle():
     _print("case: temporal weights, 40 control values x rank 3, 1320 time points (some outside)")
     rng = np.random.default_rng(61)
