@@ -71,6 +71,39 @@ def test_ewa_fwd_ragged_detector_with_offsets():
         assert err <= 1e-4, (k, err)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_ewa_random_configurations_match_oracle(seed):
+    """Seeded random geometry (detector size, pitches, offsets, distances), rank, views and
+    Gaussian sizes and signs: the EWA forward at every pixel against the oracle's EWA model."""
+    rng = np.random.default_rng(3000 + seed)
+    R, nviews, n = int(rng.integers(1, 6)), int(rng.integers(1, 5)), int(rng.integers(50, 900))
+    nu, nv = int(rng.integers(17, 80)), int(rng.integers(17, 80))
+    _print("case: EWA random configuration seed %d: R=%d, %d views, %d Gaussians, %dx%d"
+           % (seed, R, nviews, n, nu, nv))
+    p = synth.tiny(seed=4000 + seed, n=n, nviews=nviews, det=32)
+    sid = float(rng.uniform(600, 1100))
+    p = _ewa(p, nu=nu, nv=nv, pitch_u=float(rng.uniform(0.6, 1.6)),
+             pitch_v=float(rng.uniform(0.6, 1.6)), off_u=float(rng.uniform(-6, 6)),
+             off_v=float(rng.uniform(-6, 6)), sid=sid, sdd=sid * float(rng.uniform(1.2, 1.8)))
+    p.scale = np.exp(rng.uniform(np.log(0.6), np.log(6.0), (3, n))).astype(np.float32)
+    p.rho = np.where(rng.random(n) < 0.2, -p.rho, p.rho).astype(np.float32)
+    p.grid = dict(p.grid, R=R)
+    p.coef = rng.normal(0.0, 1.5, (R, 8, 8, 8, 3)).astype(np.float32)
+    p.angles = rng.uniform(0, 2 * np.pi, nviews).astype(np.float32)
+    p.w = rng.uniform(-0.5, 0.5, (nviews, R)).astype(np.float32)
+    t = problem_tensors(p)
+    ws = _lib.Workspace()
+    proj = _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                            t["angles"], t["w"], ws, tuning=dict(capacity=64 * n * nviews))
+    torch.cuda.synchronize()
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0, d
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(nviews):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+
+
 def test_ewa_minus_exact_matches_oracle():
     _print("case: EWA - exact on the GPU against the oracle's difference (tiny, 4 views)")
     p = synth.tiny(seed=3, nviews=4)
