@@ -459,6 +459,95 @@ def test_projection_superposition_and_linearity(oracle_mod):
     np.testing.assert_allclose(twice, 2 * full, rtol=1e-13)
 
 
+def _ragged_offset_problem(seed, model):
+    """A moving problem on a ragged, offset detector with unequal pitches, three views."""
+    p = synth.tiny(seed=seed, n=60, nviews=3, det=16)
+    p.geom = dict(p.geom, nu=37, nv=29, pitch_u=0.9, pitch_v=1.3, off_u=5.5, off_v=-2.5,
+                  model=model)
+    return p
+
+
+@pytest.mark.parametrize("model", ["exact", "ewa"])
+def test_project_pixels_equals_project(oracle_mod, model):
+    """The sampled-pixel entry point returns the full projection's value at (t, j, i) for every
+    sampled triple: a transposed (j, i), a wrong view index or a dropped Gaussian fails."""
+    p = _ragged_offset_problem(11, model)
+    mu, s, q, rho = p.gaussians()
+    full = oracle_mod.project(p.geom, p.grid, p.coef, mu, s, q, rho, p.angles, p.w)
+    T, nv, nu = full.shape
+    assert (T, nv, nu) == (3, 29, 37)
+    rng = np.random.default_rng(12)
+    pt = np.concatenate([rng.integers(0, T, 400), [0, T - 1, 1, 2]])
+    pj = np.concatenate([rng.integers(0, nv, 400), [0, nv - 1, nv - 1, 0]])
+    pi = np.concatenate([rng.integers(0, nu, 400), [0, nu - 1, 0, nu - 1]])
+    got = oracle_mod.project_pixels(p.geom, p.grid, p.coef, mu, s, q, rho, p.angles, p.w,
+                                    pt, pj, pi)
+    ref = full[pt, pj, pi]
+    assert np.abs(ref).max() > 0.0
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-14 * np.abs(full).max())
+    # each view's own image differs from the others' (the index test above is not vacuous)
+    assert not np.allclose(full[0], full[1]) and not np.allclose(full[1], full[2])
+
+
+def test_project_pixels_isotropic_closed_form(oracle_mod):
+    """Sampled pixels of isotropic Gaussians without motion against the textbook line integral
+    rho sigma sqrt(2 pi) exp(-d^2 / (2 sigma^2)), d the distance from the mean to the ray from the
+    source to the pixel centre, with the ray built here from the geometry convention (source at
+    SID (cos, sin, 0), detector axes e_u = (-sin, cos, 0), e_v = z, offsets along them)."""
+    geom = dict(synth.geometry(41, 27, 0.8), off_u=6.0, off_v=-3.2)
+    g, coef = _nomotion()
+    rng = np.random.default_rng(13)
+    n = 5
+    mu = rng.uniform(-8.0, 8.0, (3, n))
+    sig = rng.uniform(1.0, 3.0, n)
+    s = np.stack([sig, sig, sig])
+    q = np.tile(np.array([[1.0], [0.0], [0.0], [0.0]]), (1, n))
+    rho = rng.uniform(0.2, 1.0, n)
+    ang = np.array([0.3, 2.1])
+    pt = rng.integers(0, 2, 300)
+    pj = rng.integers(0, geom["nv"], 300)
+    pi = rng.integers(0, geom["nu"], 300)
+    got = oracle_mod.project_pixels(geom, g, coef, mu, s, q, rho, ang, np.zeros((2, 1)),
+                                    pt, pj, pi)
+    ref = np.zeros(pt.size)
+    for k in range(pt.size):
+        th = ang[pt[k]]
+        src = geom["sid"] * np.array([math.cos(th), math.sin(th), 0.0])
+        cen = (geom["sid"] - geom["sdd"]) * np.array([math.cos(th), math.sin(th), 0.0])
+        eu, ev = np.array([-math.sin(th), math.cos(th), 0.0]), np.array([0.0, 0.0, 1.0])
+        x = (pi[k] - (geom["nu"] - 1) / 2.0) * geom["pitch_u"] + geom["off_u"]
+        y = (pj[k] - (geom["nv"] - 1) / 2.0) * geom["pitch_v"] + geom["off_v"]
+        d = cen + x * eu + y * ev - src
+        d /= np.linalg.norm(d)
+        for m in range(n):
+            v = mu[:, m] - src
+            dp = np.linalg.norm(v - (v @ d) * d)
+            ref[k] += rho[m] * sig[m] * math.sqrt(2 * math.pi) * math.exp(-dp ** 2 /
+                                                                          (2 * sig[m] ** 2))
+    assert ref.max() > 1e-3
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-12 * ref.max())
+
+
+def test_project_pixels_ewa_isocentre_closed_form(oracle_mod):
+    """EWA model at sampled pixels: a Gaussian at the isocentre projects to the 2D Gaussian of
+    covariance M^2 sigma^2 I (M = SDD/SID) centred on the detector centre, with peak the line
+    integral along the central axis (an index or offset mistake moves or shears it)."""
+    geom = dict(synth.geometry(33, 45, 0.75), off_u=-2.0, off_v=4.5, model="ewa")
+    g, coef = _nomotion()
+    M = geom["sdd"] / geom["sid"]
+    mu, s, q, rho = _single([0.0, 0.0, 0.0], [1.4, 1.4, 1.4], rho=0.6)
+    rng = np.random.default_rng(14)
+    pj = rng.integers(0, geom["nv"], 200)
+    pi = rng.integers(0, geom["nu"], 200)
+    pt = rng.integers(0, 3, 200)
+    got = oracle_mod.project_pixels(geom, g, coef, mu, s, q, rho, [0.2, 1.9, 4.0],
+                                    np.zeros((3, 1)), pt, pj, pi)
+    u = (pi - 16.0) * 0.75 - 2.0
+    v = (pj - 22.0) * 0.75 + 4.5
+    ref = 0.6 * 1.4 * math.sqrt(2 * math.pi) * np.exp(-(u ** 2 + v ** 2) / (2 * 1.4 ** 2 * M ** 2))
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+
+
 def test_projection_matches_quadrature_with_motion(oracle_mod):
     """A few pixels of a moving problem against brute-force ray quadrature of phi(x, t) built
     from the oracle's own deformed Gaussians (pins the ray geometry and the sum)."""
