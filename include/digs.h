@@ -100,7 +100,9 @@ typedef struct digs_diag {
     uint32_t folded;         /* (t,n) with det K <= 0 (rendered, counted)                     */
     uint32_t behind_source;  /* (t,n) whose mean is not in front of the source, skipped       */
     uint32_t wide;           /* (t,n) whose footprint conic is not an ellipse: whole detector  */
-    uint32_t reserved[7];
+    uint32_t reserved0;
+    uint64_t max_instances;  /* the largest `instances` of any call since the last reset        */
+    uint32_t reserved[4];
 } digs_diag;
 
 /* ---------------------------------------------------------------------------------------------
@@ -210,7 +212,9 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
  * forward + backward. Synchronises its own stream; allocates the workspace (hipMalloc).
  * digs_plan_fwd / digs_plan_bwd: replay on `stream` (bwd reuses the last fwd's binning).
  * digs_plan_check: synchronises `stream`, returns the diagnostics; if an instance overflow
- * happened it grows the workspace, sets *resized = 1 and the caller must repeat the call.
+ * happened in any call since the last check it grows the workspace to hold the largest need of
+ * those calls (max_instances; the capacity never shrinks), sets *resized = 1, and the caller must
+ * repeat the calls made since the last check.
  * digs_plan_get_tuning: the tuning in use and, if tune_ms != NULL, the autotuner's timings
  * tune_ms[c][0] (forward) and tune_ms[c][1] (backward) in ms per candidate c.
  * Errors: DIGS_EINVAL, DIGS_ENOMEM, DIGS_EHIP. */
@@ -316,9 +320,10 @@ int digs_adam_mapped(int n, float *raw, float *value, const float *g_value, floa
                      float lr, float b1, float b2, float eps, int step, int map, void *stream);
 
 /* Diagnostics of a workspace: digs_read_diagnostics synchronises `stream` and copies the block
- * to *out; digs_reset_diagnostics clears it (asynchronously, on `stream`). The block (at the start
- * of the workspace) holds whatever the memory held until it is first cleared: clear a newly
- * allocated workspace once before its first call (digs_plan_create does so for its own). */
+ * to *out (all zero if no call has run on the workspace yet); digs_reset_diagnostics clears it
+ * (asynchronously, on `stream`). The block sits at the start of the workspace and carries a stamp:
+ * the first call on a new workspace clears it whatever the memory held, so no reset is needed
+ * before first use. Counters accumulate over calls until a reset. */
 int digs_read_diagnostics(const void *ws, digs_diag *out, void *stream);
 int digs_reset_diagnostics(void *ws, void *stream);
 

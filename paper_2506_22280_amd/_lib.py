@@ -51,10 +51,12 @@ class Diag(ctypes.Structure):
     _fields_ = [("instances", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
                 ("overflow", ctypes.c_uint32), ("nonfinite", ctypes.c_uint32),
                 ("folded", ctypes.c_uint32), ("behind_source", ctypes.c_uint32),
-                ("wide", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+                ("wide", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("max_instances", ctypes.c_uint64), ("reserved", ctypes.c_uint32 * 4)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_
+                if not k.startswith("reserved")}
 
 
 class VGrid(ctypes.Structure):

@@ -8,6 +8,10 @@ w [T][R] (all float32 on the GPU). angles [T] and the geometry are constants. Th
 dL/dproj arrives in backward; the adjoint turns it into the six input gradients (Sec. 3.1-3.3:
 through the splat, the projected record, the covariance warp K Sigma K^T, the quaternion
 normalisation and the B-spline FFD including its second derivatives).
+
+An instance-capacity overflow is never silent here: the forward reads the workspace's diagnostics
+after its call (a synchronisation) and, if the capacity was exceeded, repeats the call with room
+for what it needed; the backward uses the capacity the forward ended with.
 """
 from __future__ import annotations
 
@@ -16,13 +20,30 @@ import torch
 from . import _lib
 
 
+def project_checked(geom, grid, coef, mu, scale, quat, rho, angles, w, ws, tuning=None):
+    """project_fwd whose result is complete: after the call the diagnostics are read, and an
+    instance-capacity overflow repeats the call with the capacity it needed (1.25 x + 4096).
+    Returns the projections and the tuning the complete call used."""
+    if ws.buf is not None:
+        ws.reset()   # counts from earlier calls on this workspace do not concern this one
+    while True:
+        proj = _lib.project_fwd(geom, grid, coef, mu, scale, quat, rho, angles, w, ws,
+                                tuning=tuning)
+        d = ws.diagnostics()
+        if not d["overflow"]:
+            return proj, tuning
+        need = max(d["instances"], d["max_instances"])
+        tuning = dict(tuning or {}, capacity=int(need * 1.25) + 4096)
+        ws.reset()
+
+
 class DigsProject(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mu, scale, quat, rho, coef, w, angles, geom, grid, ws, tuning):
         mu, scale, quat, rho, coef, w, angles = (
             x.detach().contiguous() for x in (mu, scale, quat, rho, coef, w, angles))
-        proj = _lib.project_fwd(geom, grid, coef, mu, scale, quat, rho, angles, w, ws,
-                                tuning=tuning)
+        proj, tuning = project_checked(geom, grid, coef, mu, scale, quat, rho, angles, w, ws,
+                                       tuning)
         ctx.save_for_backward(mu, scale, quat, rho, coef, w, angles)
         ctx.geom, ctx.grid, ctx.ws, ctx.tuning = geom, grid, ws, tuning
         ctx.stamp = ws.stamp()

@@ -380,6 +380,7 @@ extern "C" int digs_read_diagnostics(const void *ws, digs_diag *out, void *strea
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return digs_set_hip_error(e);
     memset(out, 0, sizeof(*out));
+    if (d.stamp != DIAG_STAMP) return DIGS_OK;   // no call has run on this workspace yet
     out->instances = d.instances;
     out->capacity = d.capacity;
     out->overflow = d.overflow;
@@ -387,18 +388,11 @@ extern "C" int digs_read_diagnostics(const void *ws, digs_diag *out, void *strea
     out->folded = d.folded;
     out->behind_source = d.behind_source;
     out->wide = d.wide;
+    out->max_instances = d.max_instances;
     return DIGS_OK;
 }
 
-__global__ void k_diag_reset(DiagBlock *d)
-{
-    d->instances = 0;
-    d->overflow = 0;
-    d->nonfinite = 0;
-    d->folded = 0;
-    d->behind_source = 0;
-    d->wide = 0;
-}
+__global__ void k_diag_reset(DiagBlock *d) { diag_clear(d); }
 
 extern "C" int digs_reset_diagnostics(void *ws, void *stream)
 {

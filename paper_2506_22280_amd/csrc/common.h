@@ -50,7 +50,28 @@ struct DiagBlock {           // device copy of digs_diag plus internal totals
     unsigned int behind_source;
     unsigned int wide;
     unsigned int reserved[1];
+    unsigned long long max_instances;   // largest `instances` of any call since the last reset
+    unsigned long long stamp;           // DIAG_STAMP once the block has been cleared
 };
+
+// A workspace's diagnostics block counts as cleared only while it holds this stamp; the first call
+// on a new workspace (whatever its memory held) clears it.
+#define DIAG_STAMP 0x6469677364696167ull
+
+__device__ __forceinline__ void diag_clear(DiagBlock *d)
+{
+    d->instances = 0;
+    d->capacity = 0;
+    d->stat[0] = d->stat[1] = d->stat[2] = 0;
+    d->overflow = 0;
+    d->nonfinite = 0;
+    d->folded = 0;
+    d->behind_source = 0;
+    d->wide = 0;
+    d->reserved[0] = 0;
+    d->max_instances = 0;
+    d->stamp = DIAG_STAMP;
+}
 
 __device__ __forceinline__ int lane_id()
 {

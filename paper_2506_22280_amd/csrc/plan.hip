@@ -271,8 +271,11 @@ extern "C" int digs_plan_check(digs_plan *p, digs_diag *out, int *resized, void 
     int rc = hip_rc(hipStreamSynchronize((hipStream_t)stream));
     if (rc == DIGS_OK) rc = read_diag(p, out);
     if (rc != DIGS_OK || !out->overflow) return rc;
-    // grow the capacity past what the overflowing call needed; the graphs are re-captured
-    p->tuning.capacity = capacity_for(out->instances);
+    // grow the capacity past the largest need of the calls since the last check (an earlier call
+    // may have needed more than the last one), never below the current capacity; the graphs are
+    // re-captured on the next call
+    const uint64_t need = out->max_instances > out->instances ? out->max_instances : out->instances;
+    p->tuning.capacity = std::max<int64_t>(p->tuning.capacity, capacity_for(need));
     if (p->ws) (void)hipFree(p->ws);
     p->ws = nullptr;
     p->ws_bytes = 0;

@@ -45,6 +45,7 @@
 // Diagnostics and small fills
 __global__ void k_diag_begin(DiagBlock *d, unsigned long long cap, uint32_t *cnt_last)
 {
+    if (d->stamp != DIAG_STAMP) diag_clear(d);
     d->instances = 0;
     d->capacity = cap;
     *cnt_last = 0;
@@ -53,6 +54,7 @@ __global__ void k_diag_begin(DiagBlock *d, unsigned long long cap, uint32_t *cnt
 __global__ void k_diag_check(DiagBlock *d)
 {
     if (d->instances > d->capacity) d->overflow = 1u;
+    if (d->instances > d->max_instances) d->max_instances = d->instances;
 }
 
 __global__ void k_fill_f32(float *p, size_t count, float v)

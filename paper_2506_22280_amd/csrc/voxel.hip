@@ -351,6 +351,7 @@ __global__ __launch_bounds__(256) void k_phi_emit(int n, const int2 *__restrict_
         diag->instances = off[n];
         diag->capacity = cap;
         if ((size_t)off[n] > cap) diag->overflow = 1u;
+        if ((unsigned long long)off[n] > diag->max_instances) diag->max_instances = off[n];
     }
     if (i >= n) return;
     const int2 br = brange[i];
@@ -446,6 +447,7 @@ static void phi_setup_launch(const DevGrid &g, const float *coef, int n, const f
 
 __global__ void k_phi_diag_begin(DiagBlock *d)
 {
+    if (d->stamp != DIAG_STAMP) diag_clear(d);
     d->instances = 0;
     d->overflow = 0;
     d->nonfinite = 0;

@@ -158,30 +158,69 @@ class Reconstruction:
             _lib.adam_mapped(raw, value, grads[name], self.m[name], self.v[name], rates[name],
                              self.step_no, mapping)
 
+    def _snapshot(self):
+        """The loop's state at a clean check: every parameter group's raw values, mapped values
+        and Adam moments (device copies), the iteration count and the view order."""
+        return dict(t={k: (raw.clone(), None if value is raw else value.clone(),
+                           self.m[k].clone(), self.v[k].clone())
+                       for k, raw, value, _ in self.groups},
+                    step_no=self.step_no, rng=self.rng.bit_generator.state,
+                    order=self.order, pos=self.pos)
+
+    def _restore(self, snap):
+        for k, raw, value, _ in self.groups:
+            r, val, m, v = snap["t"][k]
+            raw.copy_(r)
+            if val is not None:
+                value.copy_(val)
+            self.m[k].copy_(m)
+            self.v[k].copy_(v)
+        self.step_no = snap["step_no"]
+        self.rng.bit_generator.state = snap["rng"]
+        self.order, self.pos = snap["order"], snap["pos"]
+
     def run(self, iters: int, log_every: int = 0, log=None, check_every: int = 100):
         """iters iterations; returns (iteration, mean loss per view over the last log_every
-        iterations) every log_every iterations. Every
-        check_every iterations the plan's diagnostics are read (a synchronisation): if the
-        Gaussians have moved so that a view needed more (Gaussian, tile) instances than the plan
-        holds, the plan grows before the next iteration (counted in self.resized)."""
+        iterations) every log_every iterations.
+
+        The iterations run in windows of check_every; after each window the plan's diagnostics
+        are read (a synchronisation). If any view of the window needed more (Gaussian, tile)
+        instances than the plan holds, its renders were incomplete: the plan grows (counted in
+        self.resized), the parameters, Adam moments and view order go back to their state at the
+        previous check, and the window is run again, so no update from an incomplete render
+        survives. check_every = 0 runs without checks."""
         losses = []
         acc = torch.zeros(1, device=self.loss.device)
         cnt = 0
-        for k in range(iters):
-            self.step()
-            acc += self.loss[:1]
-            cnt += 1
-            if check_every and (k + 1) % check_every == 0:
+        window = check_every if check_every else iters
+        k = 0
+        snap = self._snapshot() if check_every else None
+        while k < iters:
+            end = min(k + window, iters)
+            w_losses, w_acc, w_cnt = [], acc.clone(), cnt
+            for kk in range(k, end):
+                self.step()
+                w_acc += self.loss[:1]
+                w_cnt += 1
+                if log_every and ((kk + 1) % log_every == 0 or kk == iters - 1):
+                    w_losses.append((self.step_no, w_acc, w_cnt))
+                    w_acc = torch.zeros(1, device=self.loss.device)
+                    w_cnt = 0
+            if check_every:
                 diag, resized = self.plan.check()
-                self.resized += int(bool(resized))
+                if resized:
+                    self.resized += 1
+                    self._restore(snap)
+                    continue
                 if diag["nonfinite"]:
                     raise FloatingPointError("non-finite Gaussians at iteration %d" % self.step_no)
-            if log_every and ((k + 1) % log_every == 0 or k == iters - 1):
-                losses.append((self.step_no, float(acc[0].item()) / (cnt * self.B)))
-                acc.zero_()
-                cnt = 0
+                snap = self._snapshot()
+            for step_no, a, c in w_losses:
+                losses.append((step_no, float(a[0].item()) / (c * self.B)))
                 if log:
                     log("iteration %d: mean loss per view %.4e" % losses[-1])
+            acc, cnt = w_acc, w_cnt
+            k = end
         return losses
 
     def fit_ctrl(self, w_views):

@@ -104,3 +104,28 @@ def test_central_differences_on_subset():
     _print(errs)
     for k, e in errs.items():
         assert e <= 1e-3, (k, e)
+
+
+def test_autograd_forward_recovers_from_overflow():
+    _print("case: autograd.Function with an instance capacity far too small: the forward repeats "
+           "with the capacity it needed; values and gradients equal the direct calls")
+    p = _problem()
+    P = _params(p)
+    for v in P.values():
+        v.requires_grad_(True)
+    ang = dev(p.angles)
+    c = torch.randn((len(p.angles), p.geom["nv"], p.geom["nu"]), device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(4))
+    proj = autograd.project(p.geom, p.grid, P["mu"], P["scale"], P["quat"], P["rho"],
+                            P["coef"], P["w"], ang, _lib.Workspace(), tuning=dict(capacity=64))
+    (proj * c).sum().backward()
+    det = {k: v.detach() for k, v in P.items()}
+    ref = _lib.project_fwd(p.geom, p.grid, det["coef"], det["mu"], det["scale"], det["quat"],
+                           det["rho"], ang, det["w"], _lib.Workspace())
+    direct = _lib.project_bwd(p.geom, p.grid, det["coef"], det["mu"], det["scale"], det["quat"],
+                              det["rho"], ang, det["w"], c, _lib.Workspace())
+    torch.cuda.synchronize()
+    assert torch.equal(proj.detach(), ref)
+    for k, name in (("mu", "g_mu"), ("scale", "g_scale"), ("quat", "g_quat"), ("rho", "g_rho"),
+                    ("coef", "g_coef"), ("w", "g_w")):
+        assert torch.equal(P[k].grad, direct[name]), k

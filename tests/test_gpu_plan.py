@@ -113,3 +113,52 @@ def test_plan_overflow_is_detected_and_recovered():
         assert torch.equal(b["proj"], ref_proj)
         for k in _GRADS:
             assert torch.equal(b[k], ref_g[k]), k
+
+
+def test_plan_check_grows_to_the_largest_need_since_the_last_check():
+    _print("case: a call that overflows, then one that fits, then check: the plan grows to the "
+           "first call's need")
+    p = synth.small_phantom(n=2048, nviews=8, seed=8)
+    b = _buffers(p, np.arange(8))
+    big, small = dev(p.scale * 2.0), dev(p.scale)
+    need = {}
+    for name, sc in (("big", big), ("small", small)):
+        ws = _lib.Workspace()
+        _lib.project_fwd(p.geom, p.grid, b["coef"], b["mu"], sc, b["quat"], b["rho"],
+                         b["angles"], b["w"], ws)
+        need[name] = ws.diagnostics()["instances"]
+    _print("instances", need)
+    assert need["big"] > 1.5 * need["small"]
+    cap = int(need["small"] * 1.1)
+    with _lib.Plan(p.geom, p.grid, p.n, 8, b, tuning=dict(capacity=cap)) as plan:
+        b["scale"].copy_(big)
+        plan.fwd()            # overflows
+        b["scale"].copy_(small)
+        plan.fwd()            # fits
+        diag, resized = plan.check()
+        assert resized and diag["overflow"] == 1
+        assert diag["instances"] == need["small"] and diag["max_instances"] == need["big"]
+        assert plan.tuning()[0]["capacity"] >= need["big"]
+        b["scale"].copy_(big)
+        plan.fwd()
+        plan.bwd()
+        diag, resized = plan.check()
+        assert diag["overflow"] == 0 and not resized
+        ref_proj, ref_g = _eager(p, b)
+        assert torch.equal(b["proj"], ref_proj)
+        for k in _GRADS:
+            assert torch.equal(b[k], ref_g[k]), k
+
+
+def test_new_workspace_diagnostics_start_clear():
+    _print("case: a workspace filled with garbage reports clean diagnostics after its first call")
+    p = synth.small_phantom(n=2048, nviews=4, seed=9)
+    b = _buffers(p, np.arange(4))
+    ws = _lib.Workspace()
+    nbytes = _lib.workspace_size(p.geom, p.grid, p.n, 4)
+    ws.buf = torch.full((nbytes,), 0xA5, dtype=torch.uint8, device="cuda")
+    _lib.project_fwd(p.geom, p.grid, b["coef"], b["mu"], b["scale"], b["quat"], b["rho"],
+                     b["angles"], b["w"], ws)
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0 and d["folded"] == 0, d
+    assert d["behind_source"] == 0 and d["wide"] == 0 and d["max_instances"] == d["instances"]

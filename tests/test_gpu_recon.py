@@ -106,3 +106,27 @@ def test_loop_is_deterministic():
         rec.close()
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def test_loop_repeats_a_window_whose_renders_overflowed():
+    _print("case: a loop whose plan starts with a far too small instance capacity: the first "
+           "window is rolled back and repeated; the result equals a run that never overflowed")
+    p = _problem()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    ws = _lib.Workspace()
+    meas = _lib.project_fwd(p.geom, p.grid, d(p.coef), d(p.mu), d(p.scale), d(p.quat),
+                            d(p.rho), d(p.angles), d(p.w), ws).clone()
+    outs, resized = [], []
+    for tuning in (dict(capacity=64), None):
+        rec = recon.Reconstruction(p, meas, recon.perturbed_init(p, np.random.default_rng(5)),
+                                   iters=60, seed=7, tuning=tuning)
+        losses = rec.run(60, log_every=20, check_every=20)
+        torch.cuda.synchronize()
+        outs.append([t.clone() for t in (rec.mu, rec.scale, rec.quat, rec.rho, rec.coef,
+                                         rec.ctrl)] + [losses])
+        resized.append(rec.resized)
+        rec.close()
+    assert resized == [1, 0]
+    for a, b in zip(outs[0][:-1], outs[1][:-1]):
+        assert torch.equal(a, b)
+    assert outs[0][-1] == outs[1][-1]
