@@ -32,3 +32,33 @@ def norm_rel(got, ref):
     got = np.asarray(got, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def elem_rel(got, ref):
+    """max |got - ref| / max |ref| over the elements of one parameter group."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)) if ref.size else 0.0
+
+
+GRAD_NORM_BAR = 1e-4   # ||got - ref|| / ||ref|| per parameter group
+GRAD_ELEM_BAR = 1e-3   # max |got - ref| / max |ref| per parameter group
+
+
+def _host(x):
+    return x.double().cpu().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, np.float64)
+
+
+def check_grads(got: dict, ref: dict, norm_bar=GRAD_NORM_BAR, elem_bar=GRAD_ELEM_BAR):
+    """Gradients against a reference, every group (dL/dw included) both norm-wise and
+    element-wise; prints the measured figures and returns them."""
+    errs = {}
+    for k in ref:
+        g, r = _host(got[k]), _host(ref[k])
+        assert g.shape == r.shape, (k, g.shape, r.shape)
+        errs[k] = (norm_rel(g, r), elem_rel(g, r))
+    print({k: "norm %.2e elem %.2e" % e for k, e in errs.items()}, flush=True)
+    for k, (nr, er) in errs.items():
+        assert nr <= norm_bar, (k, "norm-wise", nr)
+        assert er <= elem_bar, (k, "element-wise", er)
+    return errs
