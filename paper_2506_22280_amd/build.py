@@ -46,26 +46,9 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
-    _build_probes()
     if verbose:
         print("built", LIB)
     return LIB
-
-
-PROBES = os.path.join(HERE, "probes")
-
-
-def _build_probes():
-    """Measurement probes (stand-alone executables, not part of the library)."""
-    for src in sorted(os.listdir(PROBES)) if os.path.isdir(PROBES) else []:
-        if not src.endswith(".hip"):
-            continue
-        exe = os.path.join(PROBES, os.path.splitext(src)[0])
-        cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
-               "-packed-fp32-ops", os.path.join(PROBES, src), "-o", exe]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError("probe build failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
 
 
 if __name__ == "__main__":
