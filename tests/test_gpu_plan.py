@@ -122,10 +122,11 @@ def test_plan_check_grows_to_the_largest_need_since_the_last_check():
     b = _buffers(p, np.arange(8))
     big, small = dev(p.scale * 2.0), dev(p.scale)
     need = {}
+    roomy = dict(capacity=64 * p.n * 8)
     for name, sc in (("big", big), ("small", small)):
         ws = _lib.Workspace()
         _lib.project_fwd(p.geom, p.grid, b["coef"], b["mu"], sc, b["quat"], b["rho"],
-                         b["angles"], b["w"], ws)
+                         b["angles"], b["w"], ws, tuning=roomy)
         need[name] = ws.diagnostics()["instances"]
     _print("instances", need)
     assert need["big"] > 1.5 * need["small"]
@@ -144,7 +145,7 @@ def test_plan_check_grows_to_the_largest_need_since_the_last_check():
         plan.bwd()
         diag, resized = plan.check()
         assert diag["overflow"] == 0 and not resized
-        ref_proj, ref_g = _eager(p, b)
+        ref_proj, ref_g = _eager(p, b, tuning=roomy)
         assert torch.equal(b["proj"], ref_proj)
         for k in _GRADS:
             assert torch.equal(b[k], ref_g[k]), k
