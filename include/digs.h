@@ -44,6 +44,7 @@ extern "C" {
 #define DIGS_EHIP (-3)     /* a HIP launch or runtime call failed (see digs_last_hip_error)    */
 #define DIGS_ECAPACITY (-4) /* instance capacity exceeded (reported by diagnostics checks)     */
 #define DIGS_ENOMEM (-5)   /* digs_plan_create could not allocate                             */
+#define DIGS_ESCRATCH (-6) /* digs_project_fwd_noalloc: the problem does not fit the fixed array */
 
 #define DIGS_MAX_RANK 8
 #define DIGS_MAX_TILES 4096 /* detector tiles (16x16 pixels) per projection                   */
@@ -160,6 +161,26 @@ int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *
                      size_t ws_bytes, const digs_tuning *tuning, void *stream);
 
 #define DIGS_BWD_REUSE_FWD 1  /* ws holds the state of a digs_project_fwd with identical inputs */
+
+/* digs_project_fwd_noalloc -- digs_project_fwd for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the forward's intermediate buffers in a device array the library owns
+ * (DIGS_NOALLOC_SCRATCH_BYTES on every GPU it runs on, held until the process ends) instead of a
+ * caller workspace. The call allocates nothing and takes no workspace.
+ *   Arguments as digs_project_fwd; diag_out is a DEVICE pointer to one digs_diag (or NULL) that
+ *   receives this call's diagnostics when its work has run (max_instances = instances; overflow
+ *   means proj is incomplete and the call must be repeated with a larger tuning->capacity).
+ * Limit: the forward's working set (about 84 bytes per (view, Gaussian), 4 bytes per instance of
+ * capacity, 12R + 24 floats per Gaussian) must fit DIGS_NOALLOC_SCRATCH_BYTES, else DIGS_ESCRATCH
+ * is returned before any device work. Every call on one GPU uses that GPU's one array: calls that
+ * overlap on a GPU (unordered streams or threads) race; order them on one stream.
+ * Errors: DIGS_EINVAL, DIGS_ESCRATCH, DIGS_EHIP. */
+#define DIGS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int digs_project_fwd_noalloc(const digs_geom *geom, const digs_grid *grid, const float *coef,
+                             int n, const float *mu, const float *scale, const float *quat,
+                             const float *rho, int T, const float *angles, const float *w,
+                             float *proj, digs_diag *diag_out, const digs_tuning *tuning,
+                             void *stream);
 
 /* digs_project_bwd -- the hand-written adjoint of digs_project_fwd. Given grad_proj = dL/dproj
  * [T][nv][nu], writes dL/d(each input):

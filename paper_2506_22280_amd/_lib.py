@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libdigs.so")
 
 DIGS_BWD_REUSE_FWD = 1
 _ERRORS = {-1: "DIGS_EINVAL", -2: "DIGS_ENOWS", -3: "DIGS_EHIP", -4: "DIGS_ECAPACITY",
-           -5: "DIGS_ENOMEM"}
+           -5: "DIGS_ENOMEM", -6: "DIGS_ESCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 << 20   # DIGS_NOALLOC_SCRATCH_BYTES
 
 
 class DigsError(RuntimeError):
@@ -99,6 +100,9 @@ _SIGS = {
                                         ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
                                         _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                         ctypes.POINTER(Tuning), ctypes.c_int, _VP]),
+    "digs_project_fwd_noalloc": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _VP,
+                                                ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int,
+                                                _VP, _VP, _VP, _VP, ctypes.POINTER(Tuning), _VP]),
     "digs_project_basis_fwd": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Grid), _VP,
                                               ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int,
                                               _VP, _VP, _VP, _VP, ctypes.c_size_t,
@@ -429,6 +433,37 @@ def project_bwd(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w, g
     if not reuse_fwd:
         ws.touched()
     return out
+
+
+def project_fwd_noalloc(geom: dict, grid: dict, coef, mu, scale, quat, rho, angles, w,
+                        tuning: dict | None = None, proj=None, diag=None, stream=None):
+    """project_fwd without a workspace (digs_project_fwd_noalloc: the library's fixed device
+    array holds the intermediate buffers; nothing is allocated by the library). diag: a device
+    uint8 tensor of at least ctypes.sizeof(Diag) bytes that receives the call's diagnostics
+    (read it with diag_from_device), or None."""
+    n, T = mu.shape[1], angles.shape[0]
+    _shape("coef", coef, _lattice(grid))
+    _gaussians(n, mu, scale, quat, rho)
+    _views(T, grid["R"], angles, w)
+    if proj is None:
+        proj = torch.empty((T, geom["nv"], geom["nu"]), device=mu.device, dtype=torch.float32)
+    _shape("proj", proj, (T, geom["nv"], geom["nu"]))
+    if diag is not None and (diag.dtype != torch.uint8 or diag.numel() < ctypes.sizeof(Diag)):
+        raise ValueError("diag must be a device uint8 tensor of at least %d bytes"
+                         % ctypes.sizeof(Diag))
+    G, R, Tu = make_geom(geom), make_grid(grid), make_tuning(tuning)
+    _check("digs_project_fwd_noalloc", load().digs_project_fwd_noalloc(
+        ctypes.byref(G), ctypes.byref(R), _ptr(coef), n, _ptr(mu), _ptr(scale), _ptr(quat),
+        _ptr(rho), T, _ptr(angles), _ptr(w), _ptr(proj), _ptr(diag), _byref(Tu),
+        _stream(stream)))
+    return proj
+
+
+def diag_from_device(diag) -> dict:
+    """The digs_diag a no-allocation call wrote into the device buffer `diag` (synchronises
+    with the copy)."""
+    raw = bytes(diag[:ctypes.sizeof(Diag)].cpu().numpy().tobytes())
+    return Diag.from_buffer_copy(raw).as_dict()
 
 
 def project_basis_fwd(geom: dict, grid: dict, basis, mu, scale, quat, rho, angles, w,

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdigs.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "ffd.hip", "render.hip", "scan.hip", "prof.hip", "plan.hip", "voxel.hip",
-           "warmstart.hip", "recon.hip"]
+           "warmstart.hip", "recon.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

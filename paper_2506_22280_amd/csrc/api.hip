@@ -73,7 +73,7 @@ DevGrid make_dev_grid(const digs_grid *g)
 static int64_t default_capacity(int n, int T) { return (int64_t)16 * n * T + 4096; }
 
 bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
-               const digs_tuning *tuning, WsLayout *L)
+               const digs_tuning *tuning, WsLayout *L, bool fwd_only)
 {
     if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0 || n > DIGS_MAX_GAUSSIANS) return false;
     memset(L, 0, sizeof(*L));
@@ -128,17 +128,18 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->cnt = take(sizeof(uint32_t) * cnt_elems);
     L->scratch = take(sizeof(uint32_t) * sc);
     L->list = take(sizeof(uint32_t) * L->cap);
-    L->part = take(sizeof(float) * DIGS_PART_FLOATS * L->cap);
-    L->gwpart = take(sizeof(float) * (size_t)(T > 0 ? T : 1) * grid->R * nparts);
+    const size_t bwd = fwd_only ? 0 : 1;   // the backward's arrays
+    L->part = take(bwd * sizeof(float) * DIGS_PART_FLOATS * L->cap);
+    L->gwpart = take(bwd * sizeof(float) * (size_t)(T > 0 ? T : 1) * grid->R * nparts);
     L->keys_a = take(sizeof(uint32_t) * N);
     L->vals_a = take(sizeof(uint32_t) * N);
     L->keys_b = take(sizeof(uint32_t) * N);
     L->vals_b = take(sizeof(uint32_t) * N);
     L->rhist = take(sizeof(uint32_t) * 256 * (size_t)nblk_r);
     L->cell_start = take(sizeof(uint32_t) * ((size_t)L->ncells + 1));
-    L->tacc = take(sizeof(float) * (13 + 12 * (size_t)grid->R) * L->tchunks * N);
+    L->tacc = take(bwd * sizeof(float) * (13 + 12 * (size_t)grid->R) * L->tchunks * N);
     L->order = take(sizeof(uint32_t) * N);
-    L->gq = take(sizeof(float) * L->gq_stride * N);
+    L->gq = take(bwd * sizeof(float) * L->gq_stride * N);
     L->total = off;
     return true;
 }
@@ -198,10 +199,10 @@ extern "C" int digs_temporal_weights_bwd(int Ct, int R, float t0, float dt, int 
     return check(launch_temporal_bwd(Ct, R, t0, dt, T, times, g_w, g_ctrl, (hipStream_t)stream));
 }
 
-static int prepare(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+int render_prepare(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
                    const float *mu, const float *scale, const float *quat, const float *rho,
                    int T, const float *angles, const float *w, void *ws, size_t ws_bytes,
-                   const digs_tuning *tuning, RenderArgs *a)
+                   const digs_tuning *tuning, bool fwd_only, RenderArgs *a)
 {
     if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0 || n > DIGS_MAX_GAUSSIANS)
         return DIGS_EINVAL;
@@ -213,7 +214,7 @@ static int prepare(const digs_geom *geom, const digs_grid *grid, const float *co
         return DIGS_EINVAL;
     if (T > 0 && n > 0 && (!coef || !mu || !scale || !quat || !rho || !angles || !w))
         return DIGS_EINVAL;
-    if (!ws_layout(geom, grid, n, T, tuning, &a->L)) return DIGS_EINVAL;
+    if (!ws_layout(geom, grid, n, T, tuning, &a->L, fwd_only)) return DIGS_EINVAL;
     if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < a->L.total) return DIGS_ENOWS;
     a->geom = make_dev_geom(geom);
     a->grid = make_dev_grid(grid);
@@ -242,8 +243,8 @@ extern "C" int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, co
                                 const digs_tuning *tuning, void *stream)
 {
     RenderArgs a;
-    int rc = prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
-                     tuning, &a);
+    int rc = render_prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws,
+                            ws_bytes, tuning, false, &a);
     if (rc) return rc;
     if (T == 0) return DIGS_OK;
     if (!proj) return DIGS_EINVAL;
@@ -263,8 +264,8 @@ extern "C" int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, co
                                 void *stream)
 {
     RenderArgs a;
-    int rc = prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
-                     tuning, &a);
+    int rc = render_prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws,
+                            ws_bytes, tuning, false, &a);
     if (rc) return rc;
     if (!g_coef || (n > 0 && (!g_mu || !g_scale || !g_quat || !g_rho)) ||
         (T > 0 && (!g_w || (n > 0 && !grad_proj))))
@@ -299,8 +300,8 @@ extern "C" int digs_project_basis_fwd(const digs_geom *geom, const digs_grid *gr
                                       void *stream)
 {
     RenderArgs a;
-    int rc = prepare(geom, grid, basis, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
-                     tuning, &a);
+    int rc = render_prepare(geom, grid, basis, n, mu, scale, quat, rho, T, angles, w, ws,
+                            ws_bytes, tuning, false, &a);
     if (rc) return rc;
     a.basis = basis;
     if (T == 0) return DIGS_OK;
@@ -322,8 +323,8 @@ extern "C" int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *gr
                                       int flags, void *stream)
 {
     RenderArgs a;
-    int rc = prepare(geom, grid, basis, n, mu, scale, quat, rho, T, angles, w, ws, ws_bytes,
-                     tuning, &a);
+    int rc = render_prepare(geom, grid, basis, n, mu, scale, quat, rho, T, angles, w, ws,
+                            ws_bytes, tuning, false, &a);
     if (rc) return rc;
     a.basis = basis;
     if ((n > 0 && (!g_mu || !g_scale || !g_quat || !g_rho || !g_basis)) ||
@@ -355,8 +356,8 @@ extern "C" int digs_count_pairs(const digs_geom *geom, const digs_grid *grid, in
     RenderArgs a;
     if (!out) return DIGS_EINVAL;
     const float dummy = 0.0f;
-    int rc = prepare(geom, grid, &dummy, n, &dummy, &dummy, &dummy, &dummy, T, &dummy, &dummy,
-                     ws, ws_bytes, tuning, &a);
+    int rc = render_prepare(geom, grid, &dummy, n, &dummy, &dummy, &dummy, &dummy, T, &dummy,
+                            &dummy, ws, ws_bytes, tuning, false, &a);
     if (rc) return rc;
     out[0] = out[1] = out[2] = 0;
     if (n == 0 || T == 0) return DIGS_OK;
@@ -410,6 +411,7 @@ extern "C" const char *digs_strerror(int code)
     case DIGS_EHIP: return "HIP runtime error";
     case DIGS_ECAPACITY: return "instance capacity exceeded";
     case DIGS_ENOMEM: return "out of device memory";
+    case DIGS_ESCRATCH: return "problem too large for the fixed device array of the no-allocation call";
     default: return "unknown error";
     }
 }

@@ -34,8 +34,10 @@ struct WsLayout {
     size_t scratch_elems;
 };
 
+// fwd_only: the forward's arrays alone (the backward's partials, adjoint sums and coefficient-
+// gradient sources get no space)
 bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
-               const digs_tuning *tuning, WsLayout *L);
+               const digs_tuning *tuning, WsLayout *L, bool fwd_only = false);
 
 DevGeom make_dev_geom(const digs_geom *g);
 DevGrid make_dev_grid(const digs_grid *g);
@@ -74,5 +76,10 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
                            float *g_scale, float *g_quat, float *g_rho, float *g_coef,
                            float *g_w, hipStream_t s);                   // a6-a8
 hipError_t render_zero(float *p, size_t count, hipStream_t s);
+// Checks the arguments of a render call and fills *a (api.hip); DIGS_OK or a DIGS_E* code.
+int render_prepare(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+                   const float *mu, const float *scale, const float *quat, const float *rho, int T,
+                   const float *angles, const float *w, void *ws, size_t ws_bytes,
+                   const digs_tuning *tuning, bool fwd_only, RenderArgs *a);
 hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s);   // measurement only
 void render_prepare_launch_shapes();

@@ -22,6 +22,13 @@ bool prof_on();
 void prof_begin(int stage, hipStream_t s);
 void prof_end(int stage, hipStream_t s);
 
+// While one exists on a thread, that thread's launches record no stage events (for calls that
+// must not create events or grow host-side lists).
+struct ProfSuppress {
+    ProfSuppress();
+    ~ProfSuppress();
+};
+
 struct ProfScope {
     int stage;
     hipStream_t s;

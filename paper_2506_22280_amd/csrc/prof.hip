@@ -38,7 +38,12 @@ static hipEvent_t take_event()
     return e;
 }
 
-bool prof_on() { return g_on; }
+static thread_local int t_suppress = 0;
+
+bool prof_on() { return g_on && t_suppress == 0; }
+
+ProfSuppress::ProfSuppress() { ++t_suppress; }
+ProfSuppress::~ProfSuppress() { --t_suppress; }
 
 void prof_begin(int stage, hipStream_t s)
 {
