@@ -83,11 +83,16 @@ typedef struct digs_grid {
 } digs_grid;
 
 /* Launch tuning; NULL selects the defaults. */
+#define DIGS_MAX_SLICES 16
 typedef struct digs_tuning {
     float cull_radius;       /* Mahalanobis cut-off of each Gaussian's footprint (default 5)   */
     int64_t capacity;        /* (Gaussian, tile) instances per call (default 16*N*T)           */
     int splat_waves;         /* forward splat: waves per 16x16 tile, 4 (8x8 each) or 1 (default 4) */
-    int bwd_waves;           /* reserved (0 or 4)                                              */
+    int slices;              /* workgroups per tile list in the splats, 1..DIGS_MAX_SLICES; 0: by
+                                shape (1 when the call has >= 2048 (view, tile) items, else
+                                enough for about 4096 workgroups, at most 8). Another value adds
+                                the same terms in another order (results bitwise reproducible
+                                for one value). With slices > 1 the splats are not persistent. */
     int persistent;          /* 1: splats run as persistent kernels over per-XCD work queues of
                                 (view, tile) items; 0: one workgroup per item (default 0)      */
 } digs_tuning;
@@ -232,6 +237,11 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
  * one-workgroup-per-item splats; all give bitwise-identical results) and keeps the fastest
  * forward + backward. Synchronises its own stream; allocates the workspace (hipMalloc).
  * digs_plan_fwd / digs_plan_bwd: replay on `stream` (bwd reuses the last fwd's binning).
+ * digs_plan_fwd_views: the forward without its per-Gaussian stage (the cell order of the means and
+ * the FFD at the canonical means, Sec. 3.3 Eq. 10-11, which do not depend on the views): it takes
+ * that stage from the last digs_plan_fwd, so it is valid only while the Gaussian and lattice
+ * buffers hold the values that call read (only angles and w changed since); rendering many views
+ * of one model. DIGS_EINVAL if no digs_plan_fwd has run since the plan was created or resized.
  * digs_plan_check: synchronises `stream`, returns the diagnostics; if an instance overflow
  * happened in any call since the last check it grows the workspace to hold the largest need of
  * those calls (max_instances; the capacity never shrinks), sets *resized = 1, and the caller must
@@ -254,6 +264,7 @@ typedef struct digs_plan_buffers {
 int digs_plan_create(const digs_geom *geom, const digs_grid *grid, int n, int T,
                      const digs_tuning *tuning, const digs_plan_buffers *bufs, digs_plan **out);
 int digs_plan_fwd(digs_plan *plan, void *stream);
+int digs_plan_fwd_views(digs_plan *plan, void *stream);
 int digs_plan_bwd(digs_plan *plan, void *stream);
 int digs_plan_check(digs_plan *plan, digs_diag *out, int *resized, void *stream);
 int digs_plan_get_tuning(const digs_plan *plan, digs_tuning *out, float *tune_ms);

@@ -44,7 +44,7 @@ class Grid(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cull_radius", ctypes.c_float), ("capacity", ctypes.c_int64),
-                ("splat_waves", ctypes.c_int), ("bwd_waves", ctypes.c_int),
+                ("splat_waves", ctypes.c_int), ("slices", ctypes.c_int),
                 ("persistent", ctypes.c_int)]
 
 
@@ -129,6 +129,7 @@ _SIGS = {
                                         ctypes.c_int, ctypes.POINTER(Tuning),
                                         ctypes.POINTER(PlanBuffers), ctypes.POINTER(_VP)]),
     "digs_plan_fwd": (ctypes.c_int, [_VP, _VP]),
+    "digs_plan_fwd_views": (ctypes.c_int, [_VP, _VP]),
     "digs_plan_bwd": (ctypes.c_int, [_VP, _VP]),
     "digs_plan_check": (ctypes.c_int, [_VP, ctypes.POINTER(Diag), ctypes.POINTER(ctypes.c_int),
                                        _VP]),
@@ -216,7 +217,7 @@ def make_tuning(t: dict | None):
     T.cull_radius = float(t.get("cull_radius", 0.0))
     T.capacity = int(t.get("capacity", 0))
     T.splat_waves = int(t.get("splat_waves", 0))
-    T.bwd_waves = int(t.get("bwd_waves", 0))
+    T.slices = int(t.get("slices", 0))
     T.persistent = int(t.get("persistent", 0))
     return T
 
@@ -586,6 +587,11 @@ class Plan:
 
     def fwd(self, stream=None):
         _check("digs_plan_fwd", load().digs_plan_fwd(self._h, _stream(stream)))
+
+    def fwd_views(self, stream=None):
+        """The forward of new views of the same model: the per-Gaussian stage is taken from the
+        last fwd() (valid while the Gaussian and lattice buffers are unchanged since it)."""
+        _check("digs_plan_fwd_views", load().digs_plan_fwd_views(self._h, _stream(stream)))
 
     def bwd(self, stream=None):
         _check("digs_plan_bwd", load().digs_plan_bwd(self._h, _stream(stream)))

@@ -72,15 +72,28 @@ DevGrid make_dev_grid(const digs_grid *g)
 
 static int64_t default_capacity(int n, int T) { return (int64_t)16 * n * T + 4096; }
 
+// Workgroups per tile list when the caller leaves it open: a launch with few (view, tile) items
+// (one view, a small detector) leaves most SIMDs with one wave, so its lists are cut into slices
+// until there are about 4096 workgroups, at most 8 per list.
+static int default_slices(int64_t items)
+{
+    if (items >= 2048 || items <= 0) return 1;
+    const int64_t s = (4096 + items - 1) / items;
+    return (int)(s < 8 ? s : 8);
+}
+
 bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
                const digs_tuning *tuning, WsLayout *L, bool fwd_only)
 {
     if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0 || n > DIGS_MAX_GAUSSIANS) return false;
+    if (tuning && (tuning->slices < 0 || tuning->slices > DIGS_MAX_SLICES)) return false;
     memset(L, 0, sizeof(*L));
     const DevGeom G = make_dev_geom(geom);
     L->n = n;
     L->T = T;
     L->R = grid->R;
+    L->slices = (tuning && tuning->slices > 0) ? tuning->slices
+                                               : default_slices((int64_t)T * G.ntiles);
     // tile binning: smaller workgroups when the launch would have fewer than ~1024 of them
     {
         const int64_t full = (int64_t)(T > 0 ? T : 1) * ((n + DIGS_BIN_ITEMS - 1) / DIGS_BIN_ITEMS);
@@ -140,6 +153,9 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->tacc = take(bwd * sizeof(float) * (13 + 12 * (size_t)grid->R) * L->tchunks * N);
     L->order = take(sizeof(uint32_t) * N);
     L->gq = take(bwd * sizeof(float) * L->gq_stride * N);
+    L->spart = take(L->slices > 1 ? sizeof(float) * L->slices * (size_t)(T > 0 ? T : 1) *
+                                        G.ntiles * DIGS_TILE_PX
+                                  : 0);
     L->total = off;
     return true;
 }
@@ -209,8 +225,8 @@ int render_prepare(const digs_geom *geom, const digs_grid *grid, const float *co
     if (tuning && (tuning->capacity < 0 || !(tuning->cull_radius >= 0.0f) ||
                    (tuning->splat_waves != 0 && tuning->splat_waves != 1 &&
                     tuning->splat_waves != 4) ||
-                   tuning->bwd_waves < 0 || tuning->bwd_waves > 4 || tuning->persistent < 0 ||
-                   tuning->persistent > 1))
+                   tuning->slices < 0 || tuning->slices > DIGS_MAX_SLICES ||
+                   tuning->persistent < 0 || tuning->persistent > 1))
         return DIGS_EINVAL;
     if (T > 0 && n > 0 && (!coef || !mu || !scale || !quat || !rho || !angles || !w))
         return DIGS_EINVAL;
@@ -230,17 +246,15 @@ int render_prepare(const digs_geom *geom, const digs_grid *grid, const float *co
     a->T = T;
     a->cull = (tuning && tuning->cull_radius > 0.0f) ? tuning->cull_radius : 5.0f;
     a->splat_waves = (tuning && tuning->splat_waves) ? tuning->splat_waves : 4;
-    a->bwd_waves = (tuning && tuning->bwd_waves) ? tuning->bwd_waves : 4;
     a->persistent = tuning ? tuning->persistent : 0;
     a->ws = (char *)ws;
     return DIGS_OK;
 }
 
-extern "C" int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *coef,
-                                int n, const float *mu, const float *scale, const float *quat,
-                                const float *rho, int T, const float *angles, const float *w,
-                                float *proj, void *ws, size_t ws_bytes,
-                                const digs_tuning *tuning, void *stream)
+int project_fwd_impl(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+                     const float *mu, const float *scale, const float *quat, const float *rho,
+                     int T, const float *angles, const float *w, float *proj, void *ws,
+                     size_t ws_bytes, const digs_tuning *tuning, bool views_only, void *stream)
 {
     RenderArgs a;
     int rc = render_prepare(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, ws,
@@ -250,9 +264,19 @@ extern "C" int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, co
     if (!proj) return DIGS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) return check(render_zero(proj, (size_t)T * geom->nu * geom->nv, s));
-    hipError_t e = render_forward_setup(a, s);
+    hipError_t e = views_only ? render_forward_views(a, s) : render_forward_setup(a, s);
     if (e == hipSuccess) e = render_forward_splat(a, proj, s);
     return check(e);
+}
+
+extern "C" int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *coef,
+                                int n, const float *mu, const float *scale, const float *quat,
+                                const float *rho, int T, const float *angles, const float *w,
+                                float *proj, void *ws, size_t ws_bytes,
+                                const digs_tuning *tuning, void *stream)
+{
+    return project_fwd_impl(geom, grid, coef, n, mu, scale, quat, rho, T, angles, w, proj, ws,
+                            ws_bytes, tuning, false, stream);
 }
 
 extern "C" int digs_project_bwd(const digs_geom *geom, const digs_grid *grid, const float *coef,

@@ -161,16 +161,18 @@ struct RadixSrc {
 
 // Count, scan and place (see above); the scan runs over (slice, key, block) counts.
 // items: items per workgroup, DIGS_BIN_ITEMS or DIGS_BIN_ITEMS_SMALL (nblk = ceil(items of a
-// slice / items))
+// slice / items)). stages: time the three launches as their own stages (false when the caller
+// times the whole binning as one stage)
 template <class Src>
 static inline hipError_t launch_binning(const Src &src, int slices, int nbins, int nblk, int nbits,
                                         uint32_t *cnt, size_t cnt_elems, uint32_t *scratch,
-                                        hipStream_t s, int items = DIGS_BIN_ITEMS)
+                                        hipStream_t s, int items = DIGS_BIN_ITEMS,
+                                        bool stages = true)
 {
     const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
     const bool small = items == DIGS_BIN_ITEMS_SMALL;
     {
-        ProfScope ps(PS_BIN_COUNT, s);
+        ProfScope ps(stages ? PS_BIN_COUNT : -1, s);
         if (small)
             hipLaunchKernelGGL((k_bin_count<Src, DIGS_BIN_ITEMS_SMALL>), dim3(nblk, slices),
                                dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk);
@@ -181,12 +183,12 @@ static inline hipError_t launch_binning(const Src &src, int slices, int nbins, i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     {
-        ProfScope ps(PS_SCAN, s);
+        ProfScope ps(stages ? PS_SCAN : -1, s);
         e = launch_exclusive_scan(cnt, cnt_elems, scratch, s);
     }
     if (e != hipSuccess) return e;
     {
-        ProfScope ps(PS_BIN_FILL, s);
+        ProfScope ps(stages ? PS_BIN_FILL : -1, s);
         if (small)
             hipLaunchKernelGGL((k_bin_fill<Src, DIGS_BIN_ITEMS_SMALL>), dim3(nblk, slices),
                                dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk, nbits);

@@ -25,11 +25,13 @@ struct WsLayout {
     size_t order;      // [N] u32 the Gaussian at each position of cell order (per-Gaussian arrays
                        //     of a call, records included, are laid out in cell order)
     size_t gq;         // [N][6 + 12R] f32 per-Gaussian coefficient-gradient sources, cell order
+    size_t spart;      // [slices][T][ntiles][256] f32 forward partial images (slices > 1 only)
     size_t total;
     // derived sizes
     int n, T, R, nblk, ntiles, ncells, gq_stride;
     int bin_items;     // Gaussians per tile-binning workgroup (nblk = ceil(n / bin_items))
     int tpc, tchunks;  // views per chunk of the per-Gaussian adjoint, and the number of chunks
+    int slices;        // workgroups per tile list in the splats (1: the whole list)
     size_t cap;
     size_t scratch_elems;
 };
@@ -65,11 +67,19 @@ struct RenderArgs {
     const float *basis;   // per-Gaussian motion basis [R][12][N] instead of the FFD, or null
     int n, T;
     float cull;
-    int splat_waves, bwd_waves, persistent;
+    int splat_waves, persistent;
     char *ws;
     WsLayout L;
 };
 hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s);   // a1-a4
+hipError_t render_forward_canonical(const RenderArgs &a, hipStream_t s);   // a1 (per Gaussian)
+hipError_t render_forward_views(const RenderArgs &a, hipStream_t s);       // a2-a4 (per view)
+// digs_project_fwd; with views_only the per-Gaussian stage in ws is taken as it is (it must come
+// from an earlier call on ws with the same Gaussians and lattice)
+int project_fwd_impl(const digs_geom *geom, const digs_grid *grid, const float *coef, int n,
+                     const float *mu, const float *scale, const float *quat, const float *rho,
+                     int T, const float *angles, const float *w, float *proj, void *ws,
+                     size_t ws_bytes, const digs_tuning *tuning, bool views_only, void *stream);
 hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s);  // a5
 // g_coef: dL/dcoef, or with a.basis dL/dbasis [R][12][N]
 hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,

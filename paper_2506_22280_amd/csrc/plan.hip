@@ -22,8 +22,9 @@ struct digs_plan {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
-    hipGraph_t gf = nullptr, gb = nullptr;
-    hipGraphExec_t ef = nullptr, eb = nullptr;
+    hipGraph_t gf = nullptr, gb = nullptr, gv = nullptr;
+    hipGraphExec_t ef = nullptr, eb = nullptr, ev = nullptr;
+    bool canonical = false;   // the workspace holds the per-Gaussian stage of the buffers' Gaussians
     float tune_ms[DIGS_TUNE_CANDIDATES][2];
 };
 
@@ -33,10 +34,13 @@ static void drop_graphs(digs_plan *p)
 {
     if (p->ef) (void)hipGraphExecDestroy(p->ef);
     if (p->eb) (void)hipGraphExecDestroy(p->eb);
+    if (p->ev) (void)hipGraphExecDestroy(p->ev);
     if (p->gf) (void)hipGraphDestroy(p->gf);
     if (p->gb) (void)hipGraphDestroy(p->gb);
-    p->ef = p->eb = nullptr;
-    p->gf = p->gb = nullptr;
+    if (p->gv) (void)hipGraphDestroy(p->gv);
+    p->ef = p->eb = p->ev = nullptr;
+    p->gf = p->gb = p->gv = nullptr;
+    p->canonical = false;
 }
 
 static int plan_alloc(digs_plan *p)
@@ -57,11 +61,12 @@ static int plan_alloc(digs_plan *p)
     return digs_reset_diagnostics(p->ws, p->cap);
 }
 
-static int run_fwd(digs_plan *p, hipStream_t s)
+static int run_fwd(digs_plan *p, hipStream_t s, bool views_only = false)
 {
     const digs_plan_buffers &b = p->b;
-    return digs_project_fwd(&p->geom, &p->grid, b.coef, p->n, b.mu, b.scale, b.quat, b.rho, p->T,
-                            b.angles, b.w, b.proj, p->ws, p->ws_bytes, &p->tuning, s);
+    return project_fwd_impl(&p->geom, &p->grid, b.coef, p->n, b.mu, b.scale, b.quat, b.rho,
+                            p->T, b.angles, b.w, b.proj, p->ws, p->ws_bytes, &p->tuning,
+                            views_only, s);
 }
 
 static int run_bwd(digs_plan *p, hipStream_t s)
@@ -74,8 +79,9 @@ static int run_bwd(digs_plan *p, hipStream_t s)
 }
 
 // Record one launch sequence on the plan's own stream as a graph (stage timing is switched off
-// while recording so that no event nodes enter the graph).
-static int capture(digs_plan *p, bool fwd)
+// while recording so that no event nodes enter the graph). which: 0 forward, 1 backward,
+// 2 forward of the per-view stages only.
+static int capture(digs_plan *p, int which)
 {
     const int prof = digs_profile_enable(-1);
     digs_profile_enable(0);
@@ -83,7 +89,8 @@ static int capture(digs_plan *p, bool fwd)
     hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     int rc = hip_rc(e);
     if (rc == DIGS_OK) {
-        rc = fwd ? run_fwd(p, p->cap) : run_bwd(p, p->cap);
+        rc = which == 0 ? run_fwd(p, p->cap) : which == 2 ? run_fwd(p, p->cap, true)
+                                                          : run_bwd(p, p->cap);
         e = hipStreamEndCapture(p->cap, &g);
         if (rc == DIGS_OK) rc = hip_rc(e);
     }
@@ -98,9 +105,12 @@ static int capture(digs_plan *p, bool fwd)
         (void)hipGraphDestroy(g);
         return digs_set_hip_error(e);
     }
-    if (fwd) {
+    if (which == 0) {
         p->gf = g;
         p->ef = x;
+    } else if (which == 2) {
+        p->gv = g;
+        p->ev = x;
     } else {
         p->gb = g;
         p->eb = x;
@@ -153,6 +163,11 @@ static int time_tuning(digs_plan *p, float *fwd_ms, float *bwd_ms)
 static int autotune(digs_plan *p)
 {
     memset(&p->tuning, 0, sizeof(p->tuning));
+    {   // the list slices the shape calls for, made explicit
+        WsLayout L;
+        if (!ws_layout(&p->geom, &p->grid, p->n, p->T, &p->tuning, &L)) return DIGS_EINVAL;
+        p->tuning.slices = L.slices;
+    }
     int rc = plan_alloc(p);
     if (rc != DIGS_OK) return rc;
     if (p->n == 0 || p->T == 0) return DIGS_OK;
@@ -243,11 +258,27 @@ extern "C" int digs_plan_fwd(digs_plan *p, void *stream)
     if (p->T == 0) return DIGS_OK;
     hipStream_t s = (hipStream_t)stream;
     if (!p->ef) {
-        int rc = capture(p, true);
+        int rc = capture(p, 0);
         if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
         if (rc != DIGS_OK) return rc;
     }
-    return hip_rc(hipGraphLaunch(p->ef, s));
+    const int rc = hip_rc(hipGraphLaunch(p->ef, s));
+    if (rc == DIGS_OK) p->canonical = true;
+    return rc;
+}
+
+extern "C" int digs_plan_fwd_views(digs_plan *p, void *stream)
+{
+    if (!p) return DIGS_EINVAL;
+    if (p->T == 0) return DIGS_OK;
+    if (!p->canonical) return DIGS_EINVAL;   // no digs_plan_fwd on this workspace yet
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->ev) {
+        int rc = capture(p, 2);
+        if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
+        if (rc != DIGS_OK) return rc;
+    }
+    return hip_rc(hipGraphLaunch(p->ev, s));
 }
 
 extern "C" int digs_plan_bwd(digs_plan *p, void *stream)
@@ -257,7 +288,7 @@ extern "C" int digs_plan_bwd(digs_plan *p, void *stream)
     if (!p->b.grad_proj && p->n > 0 && p->T > 0) return DIGS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (!p->eb) {
-        int rc = capture(p, false);
+        int rc = capture(p, 1);
         if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
         if (rc != DIGS_OK) return rc;
     }

@@ -29,15 +29,16 @@ struct ProfSuppress {
     ~ProfSuppress();
 };
 
+// stage < 0: no timing
 struct ProfScope {
     int stage;
     hipStream_t s;
     ProfScope(int st, hipStream_t ss) : stage(st), s(ss)
     {
-        if (prof_on()) prof_begin(stage, s);
+        if (stage >= 0 && prof_on()) prof_begin(stage, s);
     }
     ~ProfScope()
     {
-        if (prof_on()) prof_end(stage, s);
+        if (stage >= 0 && prof_on()) prof_end(stage, s);
     }
 };

@@ -627,6 +627,20 @@ __device__ __forceinline__ void map_block(int b, int ntiles, int T, int &t, int 
     }
 }
 
+// Entries [begin, end) of one tile list cut into nsl slices of `round` -entry multiples (the
+// last ones may be short or empty); slice sl keeps its part.
+__device__ __forceinline__ void slice_range(uint32_t &begin, uint32_t &end, int sl, int nsl,
+                                            uint32_t round)
+{
+    if (nsl <= 1) return;
+    const uint64_t len = end - begin;
+    uint64_t per = (len + (uint64_t)nsl - 1u) / (uint64_t)nsl;
+    per = (per + round - 1u) / round * round;
+    const uint64_t b = min(len, per * (uint64_t)sl), e = min(len, per * (uint64_t)(sl + 1));
+    end = begin + (uint32_t)e;
+    begin = begin + (uint32_t)b;
+}
+
 // ------------------------------------------------------------------------------------------
 // a5: forward splat. One workgroup per (view, tile), one wave per 8x8 pixel block (with
 // WAVES == 1 a single wave takes the tile's four blocks in turn). The wave walks the tile's list
@@ -714,13 +728,16 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// With nsl > 1 the workgroup renders slice sl of the tile's list into its own partial image
+// spart[sl][t][tile][256] (without the |e| factor); k_slice_reduce adds the slices in order.
 template <int WAVES, bool EWA>
 __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ list,
                                                const uint32_t *__restrict__ cnt, int nblk,
                                                unsigned cap, float *__restrict__ proj,
-                                               uint32_t (*ids)[3][FWD_QUEUE])
+                                               uint32_t (*ids)[3][FWD_QUEUE], int sl, int nsl,
+                                               int T, float *__restrict__ spart)
 {
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
@@ -729,6 +746,7 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
     uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
+    slice_range(begin, end, sl, nsl, DIGS_WAVE);
     const float4 *rt = rec + (size_t)t * n * 4;
     // the wave's three queues: Gaussians that meet rows 0-7 of the block, only rows 0-3, only 4-7
     uint32_t(*qs)[FWD_QUEUE] = ids[wave];
@@ -792,7 +810,10 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
 #pragma unroll
         for (int r = 1; r < 8; ++r) v = (gslot == r) ? acc[r] : v;
         const int px = bx + col, py = by + gslot;
-        if (px < G.nu && py < G.nv) {
+        if (nsl > 1) {
+            const int p = (py - ty * DIGS_TILE) * DIGS_TILE + (px - tx * DIGS_TILE);
+            spart[(((size_t)sl * T + t) * G.ntiles + tile) * DIGS_TILE_PX + p] = v;
+        } else if (px < G.nu && py < G.nv) {
             // exact: times the pixel's ray length |e| (EWA: |e*| is in each amplitude)
             if constexpr (!EWA) {
                 const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
@@ -821,18 +842,48 @@ __device__ __forceinline__ int next_item(uint32_t *__restrict__ queue, int home,
     return -1;
 }
 
+// blockIdx.x: (view, tile); blockIdx.y: slice of the tile's list (gridDim.y slices)
 template <int WAVES, bool EWA>
 __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd(DevGeom G, int n, int T,
                                                           const float4 *__restrict__ rec,
                                                           const uint32_t *__restrict__ list,
                                                           const uint32_t *__restrict__ cnt,
                                                           int nblk, unsigned cap,
-                                                          float *__restrict__ proj)
+                                                          float *__restrict__ proj,
+                                                          float *__restrict__ spart)
 {
     __shared__ uint32_t ids[WAVES][3][FWD_QUEUE];
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
-    splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
+    splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids, blockIdx.y,
+                               gridDim.y, T, spart);
+}
+
+// The slices' partial images added in slice order, times the pixel's ray length |e| (exact
+// model; EWA: |e*| is in each amplitude): one thread per pixel.
+template <bool EWA>
+__global__ __launch_bounds__(256) void k_slice_reduce(DevGeom G, int T, int nsl,
+                                                      const float *__restrict__ spart,
+                                                      float *__restrict__ proj)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t npx = (size_t)G.nu * G.nv;
+    if (i >= npx * T) return;
+    const int t = (int)(i / npx);
+    const int rem = (int)(i - (size_t)t * npx);
+    const int py = rem / G.nu, px = rem - py * G.nu;
+    const int tile = (py / DIGS_TILE) * G.tiles_x + px / DIGS_TILE;
+    const int p = (py % DIGS_TILE) * DIGS_TILE + px % DIGS_TILE;
+    const size_t stride = (size_t)T * G.ntiles * DIGS_TILE_PX;
+    const float *src = spart + ((size_t)t * G.ntiles + tile) * DIGS_TILE_PX + p;
+    float v = src[0];
+    for (int s = 1; s < nsl; ++s) v += src[(size_t)s * stride];
+    if constexpr (!EWA) {
+        const float xu = ((float)px - 0.5f * (float)(G.nu - 1)) * G.pitch_u + G.off_u;
+        const float yv = ((float)py - 0.5f * (float)(G.nv - 1)) * G.pitch_v + G.off_v;
+        v *= sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
+    }
+    proj[i] = v;
 }
 
 // Persistent variant: a grid sized to the machine loops over the work queues.
@@ -853,7 +904,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_splat_fwd_persist(
         if (item < 0) break;
         int t, tile;
         map_block(item, G.ntiles, T, t, tile);
-        splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids);
+        splat_fwd_tile<WAVES, EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, proj, ids, 0, 1, T,
+                                   nullptr);
     }
 }
 
@@ -1140,6 +1192,8 @@ __device__ __forceinline__ void splat_bwd_write(int n, int t, int tx, int ty, ui
     }
 }
 
+// With nsl > 1 the workgroup takes slice sl of the tile's list (every entry's partial is still
+// complete: an entry is in one slice, and its four blocks are summed in order as before).
 template <bool EWA>
 __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
@@ -1148,7 +1202,8 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                                                unsigned cap, const int4 *__restrict__ rect,
                                                const uint32_t *__restrict__ goff,
                                                const float *__restrict__ grad_proj,
-                                               float4 *__restrict__ part, BwdShared &sh)
+                                               float4 *__restrict__ part, BwdShared &sh,
+                                               int sl = 0, int nsl = 1)
 {
     float *gpx = sh.gpx;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
@@ -1172,6 +1227,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
     uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
+    slice_range(begin, end, sl, nsl, 4 * DIGS_WAVE);
     const float4 *rt = rec + (size_t)t * n * 4;
     const int tx0 = tx * DIGS_TILE, ty0 = ty * DIGS_TILE;
     uint32_t *pq0 = sh.pairs[wave][0];   // pairs over all 8 rows of the block
@@ -1256,7 +1312,7 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
     splat_bwd_tile<EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part,
-                        sh);
+                        sh, blockIdx.y, gridDim.y);
 }
 
 template <bool EWA>
@@ -1866,6 +1922,7 @@ static hipError_t setup_dispatch(const RenderArgs &a, hipStream_t s)
 // each other in memory.
 static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
 {
+    ProfScope ps(PS_CELL_SORT, s);
     hipError_t e;
     const int n = a.n;
     uint32_t *ka = WS(a, keys_a, uint32_t *), *va = WS(a, vals_a, uint32_t *);
@@ -1884,7 +1941,8 @@ static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
         src.items = n;
         src.shift = shift;
         e = launch_binning(src, 1, 256, nblk_r, 8, WS(a, rhist, uint32_t *),
-                           (size_t)256 * nblk_r, WS(a, scratch, uint32_t *), s);
+                           (size_t)256 * nblk_r, WS(a, scratch, uint32_t *), s, DIGS_BIN_ITEMS,
+                           false);
         if (e != hipSuccess) return e;
         uint32_t *t0 = ka; ka = kb; kb = t0;
         t0 = va; va = vb; vb = t0;
@@ -1896,14 +1954,11 @@ static hipError_t cell_sort(const RenderArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
+// The per-Gaussian stage (cell order, the Gaussians gathered into it, the FFD at the canonical
+// means): a function of the Gaussians and the lattice alone, shared by every view of a call.
+hipError_t render_forward_canonical(const RenderArgs &a, hipStream_t s)
 {
     hipError_t e;
-    const size_t cnt_elems = (size_t)a.T * a.geom.ntiles * a.L.nblk;
-    uint32_t *cnt = WS(a, cnt, uint32_t *);
-    hipLaunchKernelGGL(k_diag_begin, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *),
-                       (unsigned long long)a.L.cap, cnt + cnt_elems);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = cell_sort(a, s)) != hipSuccess) return e;
     {
         ProfScope ps(PS_FFD, s);
@@ -1912,6 +1967,24 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
                            a.coef, a.basis, a.n, a.mu, a.scale, a.quat, a.rho,
                            WS(a, order, const uint32_t *), WS(a, uv, float *), WS(a, gsort, float *));
     }
+    return hipGetLastError();
+}
+
+hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
+{
+    hipError_t e = render_forward_canonical(a, s);
+    if (e != hipSuccess) return e;
+    return render_forward_views(a, s);
+}
+
+// The per-view stages: the warp and projected records, instance offsets and the tile lists.
+hipError_t render_forward_views(const RenderArgs &a, hipStream_t s)
+{
+    hipError_t e;
+    const size_t cnt_elems = (size_t)a.T * a.geom.ntiles * a.L.nblk;
+    uint32_t *cnt = WS(a, cnt, uint32_t *);
+    hipLaunchKernelGGL(k_diag_begin, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *),
+                       (unsigned long long)a.L.cap, cnt + cnt_elems);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         ProfScope ps(PS_SETUP, s);
@@ -1999,6 +2072,18 @@ static void launch_splat_fwd(const RenderArgs &a, float *proj, uint32_t *queue, 
                              hipStream_t s)
 {
     const unsigned cap = (unsigned)a.L.cap;
+    const int nsl = a.L.slices;
+    if (nsl > 1) {   // list slices into partial images, then their fixed-order sum
+        float *spart = WS(a, spart, float *);
+        hipLaunchKernelGGL((k_splat_fwd<WAVES, EWA>), dim3((unsigned)items, (unsigned)nsl),
+                           dim3(64 * WAVES), 0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
+                           WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
+                           cap, proj, spart);
+        const size_t npx = (size_t)a.T * a.geom.nu * a.geom.nv;
+        hipLaunchKernelGGL((k_slice_reduce<EWA>), dim3((unsigned)((npx + 255) / 256)), dim3(256),
+                           0, s, a.geom, a.T, nsl, (const float *)spart, proj);
+        return;
+    }
     if (a.persistent)
         hipLaunchKernelGGL((k_splat_fwd_persist<WAVES, EWA>),
                            dim3(persistent_grid(k_splat_fwd_persist<WAVES, EWA>, 64 * WAVES,
@@ -2010,14 +2095,14 @@ static void launch_splat_fwd(const RenderArgs &a, float *proj, uint32_t *queue, 
         hipLaunchKernelGGL((k_splat_fwd<WAVES, EWA>), dim3((unsigned)items), dim3(64 * WAVES), 0, s,
                            a.geom, a.n, a.T, WS(a, rec, const float4 *),
                            WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
-                           cap, proj);
+                           cap, proj, (float *)nullptr);
 }
 
 hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
 {
     const size_t items = (size_t)a.geom.ntiles * a.T;
     uint32_t *queue = WS(a, queue, uint32_t *);
-    if (a.persistent) {
+    if (a.persistent && a.L.slices <= 1) {
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2086,7 +2171,7 @@ template <bool EWA>
 static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32_t *queue,
                              size_t items, hipStream_t s)
 {
-    if (a.persistent)
+    if (a.persistent && a.L.slices <= 1)
         hipLaunchKernelGGL(k_splat_bwd_persist<EWA>,
                            dim3(persistent_grid(k_splat_bwd_persist<EWA>, 256, items)), dim3(256),
                            0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
@@ -2095,7 +2180,8 @@ static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32
                            WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
                            queue);
     else
-        hipLaunchKernelGGL(k_splat_bwd<EWA>, dim3((unsigned)items), dim3(256), 0, s, a.geom, a.n,
+        hipLaunchKernelGGL(k_splat_bwd<EWA>, dim3((unsigned)items, (unsigned)a.L.slices), dim3(256),
+                           0, s, a.geom, a.n,
                            a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
                            WS(a, rect, const int4 *), WS(a, gcount, const uint32_t *), grad_proj,
@@ -2111,7 +2197,7 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
     {
         const size_t items = (size_t)a.geom.ntiles * a.T;
         uint32_t *queue = WS(a, queue, uint32_t *);
-        if (a.persistent) {
+        if (a.persistent && a.L.slices <= 1) {
             hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }

@@ -284,9 +284,11 @@ def perturbed_init(prob, rng, pos_mm=0.5, rho_frac=0.3, coef_mm=0.05, motion="ze
 
 def experiment(prob, iters: int, views_per_iter: int = 1, eval_views=None, vgrid=None,
                noise: bool = True, seed: int = 0, motion: str = "zero", lr: dict | None = None,
-               log=None) -> dict:
+               log=None, eval_at=()) -> dict:
     """Render the measured views of `prob` (ground-truth motion), optionally with the paper's
-    noise model, run the loop from a perturbed start and score it before and after."""
+    noise model, run the loop from a perturbed start and score it before and after. eval_at:
+    iteration counts inside the run at which the volume is also scored (the learning rates decay
+    over the whole run of `iters`); time per iteration excludes the scoring."""
     from . import synth
     dev = torch.device("cuda")
 
@@ -315,14 +317,23 @@ def experiment(prob, iters: int, views_per_iter: int = 1, eval_views=None, vgrid
     if vgrid is None:
         vgrid = dict(nx=96, ny=96, nz=96, origin=[-126.0] * 3, spacing=[2.65] * 3)
     before = evaluate(rec, truth, eval_views, vgrid)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses = rec.run(iters, log_every=max(iters // 10, 1), log=log)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
+    marks = sorted({int(k) for k in eval_at if 0 < int(k) < iters}) + [iters]
+    sec, done, losses, scores = 0.0, 0, [], {}
+    for mark in marks:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses += rec.run(mark - done, log_every=max(iters // 10, 1), log=log)
+        torch.cuda.synchronize()
+        sec += time.perf_counter() - t0
+        done = mark
+        if mark != iters:
+            scores[str(mark)] = evaluate(rec, truth, eval_views, vgrid)
     after = evaluate(rec, truth, eval_views, vgrid)
     rec.close()
-    return {"iters": iters, "views_per_iter": views_per_iter, "seconds": round(sec, 3),
-            "ms_per_iter": round(sec / iters * 1e3, 4), "loss_first_last": [losses[0][1],
-                                                                           losses[-1][1]],
-            "plan_resized": rec.resized, "before": before, "after": after}
+    out = {"iters": iters, "views_per_iter": views_per_iter, "seconds": round(sec, 3),
+           "ms_per_iter": round(sec / iters * 1e3, 4), "loss_first_last": [losses[0][1],
+                                                                          losses[-1][1]],
+           "plan_resized": rec.resized, "before": before, "after": after}
+    if scores:
+        out["during"] = scores
+    return out

@@ -76,15 +76,17 @@ def test_project_fwd_tiny_all_pixels():
 
 
 def test_project_fwd_ragged_tiles_and_single_wave():
-    _print("case: project_fwd small phantom 90x75 (ragged tiles), 8 views, both splat shapes")
+    _print("case: project_fwd small phantom 90x75 (ragged tiles), 8 views, both splat shapes, "
+           "1, 3 and (by shape) 8 list slices")
     p = synth.small_phantom()
     t = problem_tensors(p)
     ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
     for waves in (4, 1):
-        proj, _ = _fwd(p, t, tuning=dict(splat_waves=waves))
-        for k in range(ref.shape[0]):
-            err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
-            assert err <= 1e-4, (waves, k, err)
+        for slices in (1, 3, 0):
+            proj, _ = _fwd(p, t, tuning=dict(splat_waves=waves, slices=slices))
+            for k in range(ref.shape[0]):
+                err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+                assert err <= 1e-4, (waves, slices, k, err)
 
 
 def test_project_fwd_full_size_sampled():

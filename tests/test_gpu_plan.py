@@ -85,16 +85,32 @@ def test_plan_replays_equal_eager(nviews):
 
 
 def test_every_tuning_candidate_gives_the_same_bits():
-    _print("case: forward/backward under every launch shape the autotuner chooses from")
+    _print("case: forward/backward under every launch shape the autotuner chooses from, and "
+           "under list slices")
     p = synth.small_phantom(n=2048, nviews=8, seed=6)
     b = _buffers(p, np.arange(8))
-    ref_proj, ref_g = _eager(p, b)
+    ref_proj, ref_g = _eager(p, b, tuning=dict(slices=1))
     for waves in (4, 1):
         for persistent in (0, 1):
-            proj, g = _eager(p, b, tuning=dict(splat_waves=waves, persistent=persistent))
+            proj, g = _eager(p, b, tuning=dict(splat_waves=waves, persistent=persistent,
+                                               slices=1))
             assert torch.equal(proj, ref_proj), (waves, persistent)
             for k in _GRADS:
                 assert torch.equal(g[k], ref_g[k]), (waves, persistent, k)
+    # list slices: the same terms added in another order (rounding only), and the same bits on
+    # a repeated call
+    for slices in (2, 3, 8, 16):
+        for waves in (4, 1):
+            proj, g = _eager(p, b, tuning=dict(splat_waves=waves, slices=slices))
+            err = float((proj - ref_proj).abs().max() / ref_proj.abs().max())
+            assert err <= 1e-6, (slices, waves, err)
+            for k in _GRADS:
+                gerr = float((g[k] - ref_g[k]).abs().max() / ref_g[k].abs().max())
+                assert gerr <= 1e-5, (slices, waves, k, gerr)
+            proj2, g2 = _eager(p, b, tuning=dict(splat_waves=waves, slices=slices))
+            assert torch.equal(proj2, proj)
+            for k in _GRADS:
+                assert torch.equal(g2[k], g[k]), (slices, waves, k)
 
 
 def test_plan_overflow_is_detected_and_recovered():
@@ -163,3 +179,29 @@ def test_new_workspace_diagnostics_start_clear():
     d = ws.diagnostics()
     assert d["overflow"] == 0 and d["nonfinite"] == 0 and d["folded"] == 0, d
     assert d["behind_source"] == 0 and d["wide"] == 0 and d["max_instances"] == d["instances"]
+
+
+def test_plan_views_only_forward_equals_full_forward():
+    _print("case: plan forward of the per-view stages only, after new views are written; the "
+           "backward after it; equal to eager calls with the plan's tuning")
+    p = synth.small_phantom(n=2048, nviews=8, seed=10)
+    b = _buffers(p, np.arange(4))
+    with _lib.Plan(p.geom, p.grid, p.n, 4, b) as plan:
+        with pytest.raises(_lib.DigsError):
+            plan.fwd_views()          # no per-Gaussian stage yet
+        plan.fwd()
+        tun = {k: v for k, v in plan.tuning()[0].items() if k != "cull_radius"}
+        for first in (4, 2):
+            a2, w2 = p.views(np.arange(first, first + 4))
+            b["angles"].copy_(dev(a2))
+            b["w"].copy_(dev(w2))
+            plan.fwd_views()
+            plan.bwd()
+            diag, resized = plan.check()
+            assert not resized and diag["overflow"] == 0
+            got = b["proj"].clone()
+            gg = {k: b[k].clone() for k in _GRADS}
+            ref_proj, ref_g = _eager(p, b, tuning=tun)
+            assert torch.equal(got, ref_proj), first
+            for k in _GRADS:
+                assert torch.equal(gg[k], ref_g[k]), (first, k)
