@@ -144,6 +144,123 @@ __global__ __launch_bounds__(256) void k_dvf_rows(DevGrid g, const float *__rest
     }
 }
 
+// One workgroup per 64 (x) x 16 (y) x 8 (z) voxel slab, for voxels much finer than the lattice.
+// Stage 0 combines the ranks once for the lattice block the slab needs, C[k][j][i] = sum_r w_r
+// d^r[k][j][i] (each control point read once per slab, not once per z-slice and rank); then, per
+// z-slice, stage 1 applies the z pieces to every lattice column, stage 2 the y pieces per voxel
+// row and stage 3 the x pieces per voxel, whose three components are written once each
+// (coalesced along x). The z, y and x piece weights are computed once per slab.
+#define SLAB_Z 8
+#define SLAB_CMAX 3072   // floats of the rank-combined lattice block (nz * ny * nx * 3)
+
+__global__ __launch_bounds__(256) void k_dvf_slab(DevGrid g, const float *__restrict__ coef,
+                                                  const float *__restrict__ w, DevVGrid v,
+                                                  float *__restrict__ dvf)
+{
+    __shared__ float C[SLAB_CMAX];
+    __shared__ float4 P[DVF_JMAX][DVF_LMAX];   // (x, y, z) components, w unused: one 16-byte
+    __shared__ float4 L[DVF_ROWS][DVF_LMAX];   // LDS read per B-spline tap
+    __shared__ float By[DVF_ROWS][4];
+    __shared__ int fyr[DVF_ROWS];
+    const int x0 = blockIdx.x * DVF_ROW, y0 = blockIdx.y * DVF_ROWS, z0 = blockIdx.z * SLAB_Z;
+    const int xl = min(x0 + DVF_ROW, v.nx) - 1, yl = min(y0 + DVF_ROWS, v.ny) - 1;
+    const int zl = min(z0 + SLAB_Z, v.nz) - 1;
+    const int ilo = lattice_floor((v.ox + (float)x0 * v.sx - g.ox) / g.hx, g.nx) - 1;
+    const int ihi = lattice_floor((v.ox + (float)xl * v.sx - g.ox) / g.hx, g.nx) + 2;
+    const int jlo = lattice_floor((v.oy + (float)y0 * v.sy - g.oy) / g.hy, g.ny) - 1;
+    const int jhi = lattice_floor((v.oy + (float)yl * v.sy - g.oy) / g.hy, g.ny) + 2;
+    const int klo = lattice_floor((v.oz + (float)z0 * v.sz - g.oz) / g.hz, g.nz) - 1;
+    const int khi = lattice_floor((v.oz + (float)zl * v.sz - g.oz) / g.hz, g.nz) + 2;
+    // the host checks that the block fits; the clamps keep every access inside the arrays
+    const int nL = min(ihi - ilo + 1, DVF_LMAX), nJ = min(jhi - jlo + 1, DVF_JMAX);
+    const int nK = max(1, min(khi - klo + 1, SLAB_CMAX / (3 * nL * nJ)));
+    const size_t rank_stride = (size_t)g.nz * g.ny * g.nx * 3;
+    // stage 0: the ranks combined, one lattice value per thread-step (a, i fastest: contiguous
+    // in the lattice's layout)
+    for (int e = threadIdx.x; e < nK * nJ * nL * 3; e += 256) {
+        const int a = e % 3, i = (e / 3) % nL, j = (e / (3 * nL)) % nJ, k = e / (3 * nL * nJ);
+        const size_t o = (((size_t)clampi(klo + k, g.nz) * g.ny + clampi(jlo + j, g.ny)) * g.nx +
+                          clampi(ilo + i, g.nx)) * 3 + a;
+        float acc = 0.0f;
+        for (int rk = 0; rk < g.R; ++rk) acc = fmaf(w[rk], coef[rk * rank_stride + o], acc);
+        C[e] = acc;
+    }
+    if (threadIdx.x < DVF_ROWS) {
+        const int y = min(y0 + (int)threadIdx.x, v.ny - 1);
+        const float qy = (v.oy + (float)y * v.sy - g.oy) / g.hy;
+        float b[4];
+        bspline4(qy - floorf(qy), b);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) By[threadIdx.x][m] = b[m];
+        fyr[threadIdx.x] = lattice_floor(qy, g.ny) - 1 - jlo;
+    }
+    // the x pieces of this thread's column
+    const int x = x0 + (int)(threadIdx.x % DVF_ROW);
+    const float qx = (v.ox + (float)min(x, v.nx - 1) * v.sx - g.ox) / g.hx;
+    const int fx = lattice_floor(qx, g.nx);
+    float Bx[4];
+    bspline4(qx - floorf(qx), Bx);
+    int li[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) li[l] = min(max(fx - 1 + l - ilo, 0), nL - 1);
+    const size_t plane = (size_t)v.nz * v.ny * v.nx;
+    __syncthreads();
+    for (int z = z0; z <= zl; ++z) {
+        const float qz = (v.oz + (float)z * v.sz - g.oz) / g.hz;
+        const int kz = lattice_floor(qz, g.nz) - 1 - klo;
+        float Bz[4];
+        bspline4(qz - floorf(qz), Bz);
+        // stage 1: z pieces per lattice column (thread-step = one column's three components)
+        for (int e = threadIdx.x; e < nJ * nL; e += 256) {
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const float *c = C + min(max(kz + n, 0), nK - 1) * (nJ * nL * 3) + 3 * e;
+                acc.x = fmaf(Bz[n], c[0], acc.x);
+                acc.y = fmaf(Bz[n], c[1], acc.y);
+                acc.z = fmaf(Bz[n], c[2], acc.z);
+            }
+            P[e / nL][e % nL] = acc;
+        }
+        __syncthreads();
+        // stage 2: y pieces per voxel row
+        for (int e = threadIdx.x; e < DVF_ROWS * nL; e += 256) {
+            const int i = e % nL, r = e / nL;
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const float4 p = P[min(max(fyr[r] + m, 0), nJ - 1)][i];
+                const float b = By[r][m];
+                acc.x = fmaf(b, p.x, acc.x);
+                acc.y = fmaf(b, p.y, acc.y);
+                acc.z = fmaf(b, p.z, acc.z);
+            }
+            L[r][i] = acc;
+        }
+        __syncthreads();
+        // stage 3: x pieces; thread = column x, rows r, r + 4, r + 8, r + 12
+        if (x < v.nx) {
+#pragma unroll
+            for (int k = 0; k < DVF_ROWS / 4; ++k) {
+                const int r = (int)(threadIdx.x / DVF_ROW) + 4 * k, y = y0 + r;
+                if (y > yl) break;
+                float u[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const float4 q = L[r][li[l]];
+                    u[0] = fmaf(Bx[l], q.x, u[0]);
+                    u[1] = fmaf(Bx[l], q.y, u[1]);
+                    u[2] = fmaf(Bx[l], q.z, u[2]);
+                }
+                const size_t o = ((size_t)z * v.ny + y) * v.nx + x;
+                dvf[o] = u[0];
+                dvf[plane + o] = u[1];
+                dvf[2 * plane + o] = u[2];
+            }
+        }
+    }
+}
+
 // Any voxel spacing: the full 64-point stencil per voxel.
 __global__ __launch_bounds__(256) void k_dvf_points(DevGrid g, const float *__restrict__ coef,
                                                     const float *__restrict__ w, DevVGrid v,
@@ -174,9 +291,17 @@ extern "C" int digs_dvf_grid(const digs_grid *grid, const float *coef, const flo
     const DevGrid g = make_dev_grid(grid);
     const DevVGrid v = make_dev_vgrid(vg);
     hipStream_t s = (hipStream_t)stream;
-    // the patch kernel's LDS holds the lattice columns of a 64 x 16 voxel patch
-    if ((double)(DVF_ROW - 1) * v.sx / g.hx + 5.0 <= (double)DVF_LMAX &&
-        (double)(DVF_ROWS - 1) * v.sy / g.hy + 5.0 <= (double)DVF_JMAX) {
+    // the slab kernel's LDS holds the lattice block of a 64 x 16 x 8 voxel slab, the patch
+    // kernel's the lattice columns of a 64 x 16 voxel patch
+    const double nLx = (double)(DVF_ROW - 1) * v.sx / g.hx + 5.0;
+    const double nJy = (double)(DVF_ROWS - 1) * v.sy / g.hy + 5.0;
+    const double nKz = (double)(SLAB_Z - 1) * v.sz / g.hz + 5.0;
+    if (nLx <= (double)DVF_LMAX && nJy <= (double)DVF_JMAX &&
+        floor(nKz) * floor(nJy) * floor(nLx) * 3.0 <= (double)SLAB_CMAX) {
+        const dim3 blocks((v.nx + DVF_ROW - 1) / DVF_ROW, (v.ny + DVF_ROWS - 1) / DVF_ROWS,
+                          (v.nz + SLAB_Z - 1) / SLAB_Z);
+        hipLaunchKernelGGL(k_dvf_slab, blocks, dim3(256), 0, s, g, coef, w, v, dvf);
+    } else if (nLx <= (double)DVF_LMAX && nJy <= (double)DVF_JMAX) {
         const dim3 blocks((v.nx + DVF_ROW - 1) / DVF_ROW, (v.ny + DVF_ROWS - 1) / DVF_ROWS, v.nz);
         hipLaunchKernelGGL(k_dvf_rows, blocks, dim3(256), 0, s, g, coef, w, v, dvf);
     } else {

@@ -26,10 +26,12 @@ def _centres(v, idx):
                      v["origin"][2] + z * v["spacing"][2]])
 
 
-@pytest.mark.parametrize("spacing", [1.0, 3.0, 25.0])
+@pytest.mark.parametrize("spacing", [1.0, 3.0, 8.0, 25.0])
 def test_dvf_grid_matches_oracle(spacing):
-    _print("case: dvf_grid, phantom lattice, %g mm voxels (ragged grid, rows and points paths)"
-           % spacing)
+    """Voxels of 1 and 3 mm on the 20 mm lattice take the slab kernel, 8 mm the patch kernel and
+    25 mm the per-voxel stencil."""
+    _print("case: dvf_grid, phantom lattice, %g mm voxels (ragged grid, slab, patch and points "
+           "paths)" % spacing)
     p = synth.small_phantom(seed=2)
     n = int(np.ceil(160.0 / spacing))
     v = dict(nx=n + 3, ny=n - 5, nz=max(n // 2, 1), origin=[-80.0, -85.0, -60.0],
