@@ -90,7 +90,7 @@ typedef struct digs_tuning {
     int splat_waves;         /* forward splat: waves per 16x16 tile, 4 (8x8 each) or 1 (default 4) */
     int slices;              /* workgroups per tile list in the splats, 1..DIGS_MAX_SLICES; 0: by
                                 shape (1 when the call has >= 2048 (view, tile) items, else
-                                enough for about 4096 workgroups, at most 8). Another value adds
+                                enough for about 4096 workgroups, at most 16). Another value adds
                                 the same terms in another order (results bitwise reproducible
                                 for one value). With slices > 1 the splats are not persistent. */
     int persistent;          /* 1: splats run as persistent kernels over per-XCD work queues of

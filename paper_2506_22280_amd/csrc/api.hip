@@ -74,12 +74,13 @@ static int64_t default_capacity(int n, int T) { return (int64_t)16 * n * T + 409
 
 // Workgroups per tile list when the caller leaves it open: a launch with few (view, tile) items
 // (one view, a small detector) leaves most SIMDs with one wave, so its lists are cut into slices
-// until there are about 4096 workgroups, at most 8 per list.
+// until there are about 4096 workgroups, at most DIGS_MAX_SLICES per list (one 256x256 view of
+// 50k Gaussians: forward 0.28 ms with one slice, 0.19 with 8, 0.17 with 16).
 static int default_slices(int64_t items)
 {
     if (items >= 2048 || items <= 0) return 1;
     const int64_t s = (4096 + items - 1) / items;
-    return (int)(s < 8 ? s : 8);
+    return (int)(s < DIGS_MAX_SLICES ? s : DIGS_MAX_SLICES);
 }
 
 bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
