@@ -1357,8 +1357,12 @@ __global__ void k_queue_reset(uint32_t *q)
 // P_r = sum_t w[t][r] gmu' (3) and Q_r = sum_t w[t][r] gK (9)
 #define TACC_FIELDS(R) (13 + 12 * (R))
 
+// Ranks 1-3 keep the w-weighted sums P_r, Q_r in LDS (one column per thread, 12R x 1 KB per
+// workgroup) instead of registers: the kernel then fits 168 VGPRs, three waves per SIMD instead of
+// two (its loads of the instance partials are latency-bound). Higher ranks keep them in registers
+// (more LDS would cost more occupancy than it frees).
 template <int NR>
-__global__ __launch_bounds__(256) void k_tn_bwd(
+__global__ __launch_bounds__(256, NR <= 3 ? 3 : 1) void k_tn_bwd(
     DevGeom G, int n, int T, int tpc, const float *__restrict__ gs,
     const float *__restrict__ angles, const float *__restrict__ w, const float *__restrict__ uv,
     const int4 *__restrict__ rect,
@@ -1393,16 +1397,20 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
 #pragma unroll
         for (int k = 0; k < 9; ++k) V[r][k] = uv[((size_t)3 * NR + r * 9 + k) * n + ii];
     }
-    float gsum[3] = {0.f, 0.f, 0.f}, gRS[9], grho = 0.0f, P[NR][3], Q[NR][9];
+    constexpr bool kLdsPQ = NR <= 3;
+    constexpr int kPQ = kLdsPQ ? 12 * NR : 1;
+    __shared__ float pq_lds[kPQ][256];
+    float pq_reg[kLdsPQ ? 1 : 12 * NR];
+    // P_r[a] at index 3r + a, Q_r[k] at 3NR + 9r + k
+    auto pq = [&](int idx) -> float & {
+        if constexpr (kLdsPQ) return pq_lds[idx][threadIdx.x];
+        else return pq_reg[idx];
+    };
+    float gsum[3] = {0.f, 0.f, 0.f}, gRS[9], grho = 0.0f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) gRS[k] = 0.0f;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) P[r][a] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Q[r][k] = 0.0f;
-    }
+    for (int k = 0; k < 12 * NR; ++k) pq(k) = 0.0f;
     for (int t = t0; t < t1; ++t) {
         const size_t o = (size_t)t * n + ii;
         const int cntk = valid ? TileRect::from(rect[o]).count() : 0;
@@ -1575,9 +1583,10 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) P[r][a] = fmaf(wt[r], out[a], P[r][a]);
+                for (int a = 0; a < 3; ++a) pq(3 * r + a) = fmaf(wt[r], out[a], pq(3 * r + a));
 #pragma unroll
-                for (int k = 0; k < 9; ++k) Q[r][k] = fmaf(wt[r], out[3 + k], Q[r][k]);
+                for (int k = 0; k < 9; ++k)
+                    pq(3 * NR + 9 * r + k) = fmaf(wt[r], out[3 + k], pq(3 * NR + 9 * r + k));
             }
         }
 #pragma unroll
@@ -1597,9 +1606,9 @@ __global__ __launch_bounds__(256) void k_tn_bwd(
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) dst[(13 + 12 * r + a) * fs] = P[r][a];
+            for (int a = 0; a < 3; ++a) dst[(13 + 12 * r + a) * fs] = pq(3 * r + a);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) dst[(16 + 12 * r + k) * fs] = Q[r][k];
+            for (int k = 0; k < 9; ++k) dst[(16 + 12 * r + k) * fs] = pq(3 * NR + 9 * r + k);
         }
     }
 }
