@@ -45,7 +45,8 @@ BWD_FLOP, BWD_VALU, BWD_TRANS = 23, 17, 2
 TRANS_SLOTS = 2
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes per cycle x clock
 # MI355X's published dense FP32 vector peak (the roofline's peak); it counts packed FP32 FMAs
-# (two per lane per cycle), which this build does not emit, so the unpacked FMA rate is half of it
+# (two per lane per cycle), which the library's kernels do not use (packed FP32 is switched off
+# when they are compiled), so their unpacked FMA rate is half of it
 FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per projection of one fwd+bwd step (see the design notes): Gaussians read

@@ -370,7 +370,7 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
 
 
 def main(argv=None):
-    """Run the learned-warm-start experiment. Default: the survey-scale configuration (200k
+    """Run the learned-warm-start experiment. Default: the full-scale configuration (200k
     Gaussians, 512x384 at 0.8 mm, 1,320 views, training phantoms 0-14, held-out 100-102, 64x64
     network input from 8x6 block means)."""
     import argparse
