@@ -61,9 +61,9 @@ ALGO_BYTES_PER_STEP = ALGO_BYTES_PER_PROJ * 64   # 129.7 MB per 64-view fwd+bwd 
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while the sources are unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2363017.0 * (524288.0 / 262167.0625) * 1024,
-           "write_bytes": 6585514.1 * 1.000 * 1024,
-           "sources_sha256": "d98e87fed3c1e45a526ca1e5ba73de476be600a420036d4e3421e87fe9182a3f"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2365717.2 * (524288.0 / 262166.875) * 1024,
+           "write_bytes": 6586309.0 * 1.000 * 1024,
+           "sources_sha256": "68b780bdd861b6d6f73e0bf500e569b051cf2c31feb2b7620a9eab561fe48e89"}
 
 
 def sources_digest() -> str:
