@@ -84,6 +84,18 @@ def traffic_bytes():
     return int(TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"])
 
 
+def tuning_candidates(tune_ms):
+    """The autotuner's timings by name: tile shape, forward waves per tile, persistent splats
+    (candidate c: tile shape c // 4, launch shape c % 4); shapes it did not try are left out."""
+    names = {}
+    for c, ms in enumerate(tune_ms):
+        tw, th = ((16, 16), (32, 8), (8, 8))[c // 4]
+        w_, p_ = ((4, 0), (4, 1), (1, 0), (1, 1))[c % 4]
+        if ms[0] > 0:
+            names["t%dx%d_w%d_p%d" % (tw, th, w_, p_)] = [round(x, 3) for x in ms]
+    return names
+
+
 def op_mix_peak_tflops(flop, valu, trans):
     """FLOP/s at full unpacked VALU issue for the kernel's per-pair operation mix (each
     transcendental issues at half rate, two slots): a secondary reference, not the roofline's."""
@@ -183,7 +195,8 @@ def single_view_leg(dev):
             "ms_per_view_scan_views_only": round(views, 4),
             "views_per_s_scan_views_only": round(1e3 / views, 1),
             "stage_ms_per_view_eager": stages,
-            "tuning": {k: tuning[k] for k in ("splat_waves", "persistent", "slices")}}
+            "tuning": {k: tuning[k] for k in ("tile_w", "tile_h", "splat_waves", "persistent",
+                                              "slices")}}
 
 
 def volume_leg(dev):
@@ -308,7 +321,8 @@ def large_leg(dev, steps: int, warmup: int):
     return {"gaussians": p.n, "detector": [p.geom["nu"], p.geom["nv"]], "batch": B,
             "ms_per_step": round(dt * 1e3, 3), "projections_per_s": round(B / dt, 2),
             "instances_per_view": int(inst / B),
-            "tuning": {k: tuning[k] for k in ("splat_waves", "persistent", "capacity")}}
+            "tuning": {k: tuning[k] for k in ("tile_w", "tile_h", "splat_waves", "persistent",
+                                              "capacity")}}
 
 
 def recon_leg(iters: int = 50_000):
@@ -392,7 +406,7 @@ def ewa_leg(p, est, ang, wts, meas, steps: int, warmup: int, ref, exact_ms: floa
     return {"ms_per_step": round(dt * 1e3, 3), "projections_per_s": round(B / dt, 2),
             "speedup_vs_exact": round(exact_ms / (dt * 1e3), 3),
             "max_dev_vs_exact_rel_to_max": round(dev_max, 6),
-            "tuning": {k: tuning[k] for k in ("splat_waves", "persistent")}}
+            "tuning": {k: tuning[k] for k in ("tile_w", "tile_h", "splat_waves", "persistent")}}
 
 
 def main():
@@ -495,7 +509,8 @@ def main():
     # per-kernel timing: the same steps, launched eagerly with the plan's tuning, every kernel
     # stage bracketed by HIP events on its launch stream
     eager_tuning = dict(splat_waves=tuning["splat_waves"], persistent=tuning["persistent"],
-                        capacity=tuning["capacity"], slices=tuning["slices"])
+                        capacity=tuning["capacity"], slices=tuning["slices"],
+                        tile_w=tuning["tile_w"], tile_h=tuning["tile_h"])
 
     def eager_step(k):
         kb = k % len(batches)
@@ -544,11 +559,9 @@ def main():
                       "global_batch": B, "gaussians": n, "detector": [G["nu"], G["nv"]],
                       "parallelism": "single GPU"}}
     out["sources_sha256"] = sources_digest()
-    out["tuning"] = {"chosen": {k: tuning[k] for k in ("splat_waves", "persistent", "capacity",
-                                                       "slices")},
-                     "candidates_fwd_bwd_ms": {"w%d_p%d" % (w_, p_): [round(x, 3) for x in ms]
-                                               for (w_, p_), ms in zip(((4, 0), (4, 1), (1, 0),
-                                                                        (1, 1)), tune_ms)}}
+    out["tuning"] = {"chosen": {k: tuning[k] for k in ("tile_w", "tile_h", "splat_waves",
+                                                       "persistent", "capacity", "slices")},
+                     "candidates_fwd_bwd_ms": tuning_candidates(tune_ms)}
     out["hbm_roofline_end_to_end"] = {
         "algorithmic_bytes_per_projection": int(ALGO_BYTES_PER_PROJ),
         "achieved_GBs": round(value * ALGO_BYTES_PER_PROJ / 1e9, 3),

@@ -47,7 +47,7 @@ extern "C" {
 #define DIGS_ESCRATCH (-6) /* digs_project_fwd_noalloc: the problem does not fit the fixed array */
 
 #define DIGS_MAX_RANK 8
-#define DIGS_MAX_TILES 4096 /* detector tiles (16x16 pixels) per projection                   */
+#define DIGS_MAX_TILES 4096 /* detector tiles per projection, at the call's tile shape            */
 #define DIGS_MAX_GAUSSIANS 16777215 /* 2^24 - 1 Gaussians per call                               */
 
 /* Cone-beam CT geometry of a circular orbit about z (the paper's acquisition, Sec. 4.1).
@@ -57,7 +57,7 @@ extern "C" {
  * y_j = (j - (nv-1)/2) pitch_v. Projections are stored proj[t][j][i]. */
 typedef struct digs_geom {
     float sid, sdd;          /* source-isocentre, source-detector distances (mm), sdd > sid > 0 */
-    int nu, nv;              /* detector columns, rows (>0; ceil(nu/16)*ceil(nv/16) <= 4096)  */
+    int nu, nv;              /* detector columns, rows (>0; at most DIGS_MAX_TILES tiles)      */
     float pitch_u, pitch_v;  /* pixel pitch (mm, >0)                                           */
     float off_u, off_v;      /* detector offset along e_u, e_v (mm)                            */
     int model;               /* projection model, DIGS_MODEL_EXACT (0) or DIGS_MODEL_EWA (1)   */
@@ -87,7 +87,8 @@ typedef struct digs_grid {
 typedef struct digs_tuning {
     float cull_radius;       /* Mahalanobis cut-off of each Gaussian's footprint (default 5)   */
     int64_t capacity;        /* (Gaussian, tile) instances per call (default 16*N*T)           */
-    int splat_waves;         /* forward splat: waves per 16x16 tile, 4 (8x8 each) or 1 (default 4) */
+    int splat_waves;         /* forward splat: waves per tile, 4 (one per 8x8 block, at most as
+                                many as the tile has blocks) or 1 (default 4)                  */
     int slices;              /* workgroups per tile list in the splats, 1..DIGS_MAX_SLICES; 0: by
                                 shape (1 when the call has >= 2048 (view, tile) items, else
                                 enough for about 4096 workgroups, at most 16). Another value adds
@@ -95,6 +96,12 @@ typedef struct digs_tuning {
                                 for one value). With slices > 1 the splats are not persistent. */
     int persistent;          /* 1: splats run as persistent kernels over per-XCD work queues of
                                 (view, tile) items; 0: one workgroup per item (default 0)      */
+    int tile_w, tile_h;      /* detector tile in pixels; 0, 0: 16 x 16. A tile is one, two or
+                                four blocks of 8 x 8 pixels: 16x16, 32x8, 8x32, 16x8, 8x16 or 8x8,
+                                with at most DIGS_MAX_TILES tiles per projection. The tile shape
+                                sets which (Gaussian, tile) instances exist and the lists' order
+                                of work, so another shape adds the same terms in another order
+                                (and needs another instance capacity). */
 } digs_tuning;
 
 /* Diagnostics counted by the kernels (read after the work has run). */
@@ -165,7 +172,8 @@ int digs_project_fwd(const digs_geom *geom, const digs_grid *grid, const float *
                      int T, const float *angles, const float *w, float *proj, void *ws,
                      size_t ws_bytes, const digs_tuning *tuning, void *stream);
 
-#define DIGS_BWD_REUSE_FWD 1  /* ws holds the state of a digs_project_fwd with identical inputs */
+#define DIGS_BWD_REUSE_FWD 1  /* ws holds the state of a digs_project_fwd with identical inputs
+                                 and tuning */
 
 /* digs_project_fwd_noalloc -- digs_project_fwd for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
@@ -232,10 +240,14 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
  *
  * digs_plan_create: tuning != NULL fixes the launch tuning; tuning == NULL runs the autotuner,
  * which renders the buffers' current contents (they must hold valid inputs, and grad_proj valid
- * dL/dproj if given) to size the instance capacity (1.25 x the measured need + 4096), then times
- * each of DIGS_TUNE_CANDIDATES launch shapes (forward splat 4 or 1 waves per tile x persistent or
- * one-workgroup-per-item splats; all give bitwise-identical results) and keeps the fastest
- * forward + backward. Synchronises its own stream; allocates the workspace (hipMalloc).
+ * dL/dproj if given). For each tile shape 16x16, 32x8 and 8x8 that the detector allows it sizes
+ * the instance capacity from a measured forward (1.25 x the need + 4096) and times four launch
+ * shapes (forward splat 4 or 1 waves per tile x persistent or one-workgroup-per-item splats;
+ * within one tile shape all give bitwise-identical results); it keeps the fastest forward +
+ * backward, a tile shape other than 16x16 only if it is more than 3% faster than the best 16x16
+ * candidate (tile shapes sum in different orders, so a near tie should not flip between runs).
+ * The list slices follow from the chosen shape. Synchronises its own stream; allocates the
+ * workspace (hipMalloc).
  * digs_plan_fwd / digs_plan_bwd: replay on `stream` (bwd reuses the last fwd's binning).
  * digs_plan_fwd_views: the forward without its per-Gaussian stage (the cell order of the means and
  * the FFD at the canonical means, Sec. 3.3 Eq. 10-11, which do not depend on the views): it takes
@@ -247,9 +259,11 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
  * those calls (max_instances; the capacity never shrinks), sets *resized = 1, and the caller must
  * repeat the calls made since the last check.
  * digs_plan_get_tuning: the tuning in use and, if tune_ms != NULL, the autotuner's timings
- * tune_ms[c][0] (forward) and tune_ms[c][1] (backward) in ms per candidate c.
+ * tune_ms[c][0] (forward) and tune_ms[c][1] (backward) in ms per candidate c: tile shape c / 4
+ * (16x16, 32x8, 8x8; zeros for a shape not tried), launch shape c % 4 (waves 4, 4, 1, 1 x
+ * persistent 0, 1, 0, 1).
  * Errors: DIGS_EINVAL, DIGS_ENOMEM, DIGS_EHIP. */
-#define DIGS_TUNE_CANDIDATES 4
+#define DIGS_TUNE_CANDIDATES 12
 
 typedef struct digs_plan digs_plan;
 

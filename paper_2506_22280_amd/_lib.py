@@ -45,7 +45,7 @@ class Grid(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("cull_radius", ctypes.c_float), ("capacity", ctypes.c_int64),
                 ("splat_waves", ctypes.c_int), ("slices", ctypes.c_int),
-                ("persistent", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -80,7 +80,7 @@ class PlanBuffers(ctypes.Structure):
         "g_scale", "g_quat", "g_rho", "g_coef", "g_w")]
 
 
-TUNE_CANDIDATES = 4
+TUNE_CANDIDATES = 12   # 3 tile shapes x 4 launch shapes
 _VP = ctypes.c_void_p
 _lib = None
 
@@ -219,6 +219,8 @@ def make_tuning(t: dict | None):
     T.splat_waves = int(t.get("splat_waves", 0))
     T.slices = int(t.get("slices", 0))
     T.persistent = int(t.get("persistent", 0))
+    T.tile_w = int(t.get("tile_w", 0))
+    T.tile_h = int(t.get("tile_h", 0))
     return T
 
 

@@ -32,11 +32,26 @@ static bool geom_ok(const digs_geom *g)
         !isfinite(g->off_v) || g->nu > 65535 || g->nv > 65535 ||
         (g->model != DIGS_MODEL_EXACT && g->model != DIGS_MODEL_EWA))
         return false;
-    const long tx = (g->nu + DIGS_TILE - 1) / DIGS_TILE, ty = (g->nv + DIGS_TILE - 1) / DIGS_TILE;
-    return tx * ty <= DIGS_MAX_TILES;
+    return true;
 }
 
-DevGeom make_dev_geom(const digs_geom *g)
+// The tile shape a tuning asks for (16 x 16 by default); false if it is not one of the shapes
+// of one, two or four 8x8 blocks with edges of 8, 16 or 32 pixels.
+static bool tile_shape(const digs_tuning *t, int *tw, int *th)
+{
+    *tw = DIGS_TILE;
+    *th = DIGS_TILE;
+    if (!t || (t->tile_w == 0 && t->tile_h == 0)) return true;
+    auto edge = [](int e) { return e == 8 || e == 16 || e == 32; };
+    if (!edge(t->tile_w) || !edge(t->tile_h) || t->tile_w * t->tile_h > DIGS_TILE_PX) return false;
+    *tw = t->tile_w;
+    *th = t->tile_h;
+    return true;
+}
+
+static int log2_edge(int e) { return e == 8 ? 3 : (e == 16 ? 4 : 5); }
+
+DevGeom make_dev_geom(const digs_geom *g, int tw, int th)
 {
     DevGeom d;
     d.sid = g->sid;
@@ -47,8 +62,14 @@ DevGeom make_dev_geom(const digs_geom *g)
     d.pitch_v = g->pitch_v;
     d.off_u = g->off_u;
     d.off_v = g->off_v;
-    d.tiles_x = (g->nu + DIGS_TILE - 1) / DIGS_TILE;
-    d.tiles_y = (g->nv + DIGS_TILE - 1) / DIGS_TILE;
+    d.tile_w = tw;
+    d.tile_h = th;
+    d.tile_lw = log2_edge(tw);
+    d.tile_lh = log2_edge(th);
+    d.tile_bx = tw / 8;
+    d.tile_nb = (tw / 8) * (th / 8);
+    d.tiles_x = (g->nu + tw - 1) / tw;
+    d.tiles_y = (g->nv + th - 1) / th;
     d.ntiles = d.tiles_x * d.tiles_y;
     d.ewa = g->model == DIGS_MODEL_EWA ? 1 : 0;
     return d;
@@ -88,8 +109,11 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
 {
     if (!geom_ok(geom) || !grid_ok(grid) || n < 0 || T < 0 || n > DIGS_MAX_GAUSSIANS) return false;
     if (tuning && (tuning->slices < 0 || tuning->slices > DIGS_MAX_SLICES)) return false;
+    int tw, th;
+    if (!tile_shape(tuning, &tw, &th)) return false;
     memset(L, 0, sizeof(*L));
-    const DevGeom G = make_dev_geom(geom);
+    const DevGeom G = make_dev_geom(geom, tw, th);
+    if ((int64_t)G.tiles_x * G.tiles_y > DIGS_MAX_TILES) return false;
     L->n = n;
     L->T = T;
     L->R = grid->R;
@@ -155,7 +179,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->order = take(sizeof(uint32_t) * N);
     L->gq = take(bwd * sizeof(float) * L->gq_stride * N);
     L->spart = take(L->slices > 1 ? sizeof(float) * L->slices * (size_t)(T > 0 ? T : 1) *
-                                        G.ntiles * DIGS_TILE_PX
+                                        G.ntiles * (size_t)(tw * th)
                                   : 0);
     L->total = off;
     return true;
@@ -233,7 +257,9 @@ int render_prepare(const digs_geom *geom, const digs_grid *grid, const float *co
         return DIGS_EINVAL;
     if (!ws_layout(geom, grid, n, T, tuning, &a->L, fwd_only)) return DIGS_EINVAL;
     if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < a->L.total) return DIGS_ENOWS;
-    a->geom = make_dev_geom(geom);
+    int tw, th;
+    (void)tile_shape(tuning, &tw, &th);   // checked by ws_layout
+    a->geom = make_dev_geom(geom, tw, th);
     a->grid = make_dev_grid(grid);
     a->coef = coef;
     a->basis = nullptr;

@@ -7,8 +7,8 @@
 #include "../../include/digs.h"
 
 #define DIGS_WAVE 64
-#define DIGS_TILE 16                 // detector tile edge (pixels)
-#define DIGS_TILE_PX (DIGS_TILE * DIGS_TILE)
+#define DIGS_TILE 16                 // default detector tile edge (pixels)
+#define DIGS_TILE_PX 256             // pixels of the largest tile (four 8x8 blocks)
 #define DIGS_BIN_ITEMS 1024          // items (Gaussians) per binning workgroup: 4 waves x 256
 #define DIGS_BIN_ITEMS_SMALL 256     // the same when a launch would have few workgroups
 #define DIGS_REC_FLOATS 16           // per-(t,n) projected record, 64 bytes
@@ -31,6 +31,9 @@ struct DevGeom {
     int nu, nv;
     float pitch_u, pitch_v, off_u, off_v;
     int tiles_x, tiles_y, ntiles;
+    // tile shape: tile_w x tile_h pixels (8, 16 or 32 each), a grid of tile_bx x (tile_nb /
+    // tile_bx) blocks of 8x8 pixels with tile_nb in {1, 2, 4}; tile_lw, tile_lh = log2 of the edges
+    int tile_w, tile_h, tile_lw, tile_lh, tile_bx, tile_nb;
     int ewa;                 // projection model: 0 exact line integral, 1 EWA 2D approximation
 };
 

@@ -25,7 +25,7 @@ struct WsLayout {
     size_t order;      // [N] u32 the Gaussian at each position of cell order (per-Gaussian arrays
                        //     of a call, records included, are laid out in cell order)
     size_t gq;         // [N][6 + 12R] f32 per-Gaussian coefficient-gradient sources, cell order
-    size_t spart;      // [slices][T][ntiles][256] f32 forward partial images (slices > 1 only)
+    size_t spart;      // [slices][T][ntiles][tile pixels] f32 forward partial images (slices > 1)
     size_t total;
     // derived sizes
     int n, T, R, nblk, ntiles, ncells, gq_stride;
@@ -41,7 +41,7 @@ struct WsLayout {
 bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
                const digs_tuning *tuning, WsLayout *L, bool fwd_only = false);
 
-DevGeom make_dev_geom(const digs_geom *g);
+DevGeom make_dev_geom(const digs_geom *g, int tile_w, int tile_h);
 DevGrid make_dev_grid(const digs_grid *g);
 
 // scan.hip

@@ -156,47 +156,86 @@ static int time_tuning(digs_plan *p, float *fwd_ms, float *bwd_ms)
     return DIGS_OK;
 }
 
-// The autotuner: size the instance capacity from a measured forward, then time every candidate
-// launch shape (forward splat waves per tile x persistent or one-workgroup-per-item splats) on the
-// caller's data and keep the fastest forward + backward. All candidates compute bitwise-identical
-// results; only their speed differs.
-static int autotune(digs_plan *p)
+// Tile shapes the autotuner tries (pixels), the default first, and the launch shapes it times for
+// each: forward splat waves per tile x persistent or one-workgroup-per-item splats. Candidate c is
+// shape c / 4, launch shape c % 4.
+static const int kTileW[DIGS_TUNE_CANDIDATES / 4] = {16, 32, 8};
+static const int kTileH[DIGS_TUNE_CANDIDATES / 4] = {16, 8, 8};
+static const int kWaves[4] = {4, 4, 1, 1};
+static const int kPersist[4] = {0, 1, 0, 1};
+
+// Drop the workspace and allocate one sized for the current tuning.
+static int plan_realloc(digs_plan *p)
 {
-    memset(&p->tuning, 0, sizeof(p->tuning));
-    {   // the list slices the shape calls for, made explicit
-        WsLayout L;
-        if (!ws_layout(&p->geom, &p->grid, p->n, p->T, &p->tuning, &L)) return DIGS_EINVAL;
-        p->tuning.slices = L.slices;
-    }
-    int rc = plan_alloc(p);
-    if (rc != DIGS_OK) return rc;
-    if (p->n == 0 || p->T == 0) return DIGS_OK;
-    rc = run_fwd(p, p->cap);
-    digs_diag d;
-    if (rc == DIGS_OK) rc = read_diag(p, &d);
-    if (rc != DIGS_OK) return rc;
-    p->tuning.capacity = capacity_for(d.instances);
     if (p->ws) (void)hipFree(p->ws);
     p->ws = nullptr;
     p->ws_bytes = 0;
-    if ((rc = plan_alloc(p)) != DIGS_OK) return rc;
-    static const int kWaves[DIGS_TUNE_CANDIDATES] = {4, 4, 1, 1};
-    static const int kPersist[DIGS_TUNE_CANDIDATES] = {0, 1, 0, 1};
-    int best = 0;
-    float best_ms = 0.0f;
-    for (int c = 0; c < DIGS_TUNE_CANDIDATES; ++c) {
-        p->tuning.splat_waves = kWaves[c];
-        p->tuning.persistent = kPersist[c];
-        rc = time_tuning(p, &p->tune_ms[c][0], &p->tune_ms[c][1]);
+    return plan_alloc(p);
+}
+
+// The autotuner. For each tile shape the call's detector allows: size the instance capacity from a
+// measured forward, then time the four launch shapes on the caller's data. Launch shapes of one
+// tile shape compute bitwise-identical results; tile shapes add the same terms in different
+// orders, so a shape other than the default is kept only when it is faster by more than 3% (a
+// near tie does not flip between runs). The list slices follow from each shape's item count.
+static int autotune(digs_plan *p)
+{
+    const int nshapes = DIGS_TUNE_CANDIDATES / 4;
+    bool shape_ok[DIGS_TUNE_CANDIDATES / 4];
+    int64_t shape_cap[DIGS_TUNE_CANDIDATES / 4];
+    int shape_slices[DIGS_TUNE_CANDIDATES / 4];
+    int best = -1;
+    float best_ms = 0.0f, default_ms = 0.0f;
+    int rc = DIGS_OK;
+    for (int sh = 0; sh < nshapes; ++sh) {
+        memset(&p->tuning, 0, sizeof(p->tuning));
+        p->tuning.tile_w = kTileW[sh];
+        p->tuning.tile_h = kTileH[sh];
+        WsLayout L;
+        shape_ok[sh] = ws_layout(&p->geom, &p->grid, p->n, p->T, &p->tuning, &L);
+        if (!shape_ok[sh]) continue;   // too many tiles of this shape for the detector
+        p->tuning.slices = L.slices;
+        shape_slices[sh] = L.slices;
+        shape_cap[sh] = 0;
+        if ((rc = plan_realloc(p)) != DIGS_OK) return rc;
+        if (p->n == 0 || p->T == 0) {
+            if (sh == 0) return DIGS_OK;
+            continue;
+        }
+        rc = run_fwd(p, p->cap);
+        digs_diag d;
+        if (rc == DIGS_OK) rc = read_diag(p, &d);
         if (rc != DIGS_OK) return rc;
-        const float ms = p->tune_ms[c][0] + p->tune_ms[c][1];
-        if (c == 0 || ms < best_ms) {
-            best = c;
-            best_ms = ms;
+        p->tuning.capacity = capacity_for(d.instances);
+        shape_cap[sh] = p->tuning.capacity;
+        if ((rc = plan_realloc(p)) != DIGS_OK) return rc;
+        float shape_best = 0.0f;
+        for (int v = 0; v < 4; ++v) {
+            const int c = 4 * sh + v;
+            p->tuning.splat_waves = kWaves[v];
+            p->tuning.persistent = kPersist[v];
+            rc = time_tuning(p, &p->tune_ms[c][0], &p->tune_ms[c][1]);
+            if (rc != DIGS_OK) return rc;
+            const float ms = p->tune_ms[c][0] + p->tune_ms[c][1];
+            if (v == 0 || ms < shape_best) shape_best = ms;
+            if (sh == 0) default_ms = shape_best;
+            const bool better = sh == 0 ? (best < 0 || ms < best_ms)
+                                        : (ms < best_ms && ms < 0.97f * default_ms);
+            if (better) {
+                best = c;
+                best_ms = ms;
+            }
         }
     }
-    p->tuning.splat_waves = kWaves[best];
-    p->tuning.persistent = kPersist[best];
+    memset(&p->tuning, 0, sizeof(p->tuning));
+    const int sh = best < 0 ? 0 : best / 4, v = best < 0 ? 0 : best % 4;
+    p->tuning.tile_w = kTileW[sh];
+    p->tuning.tile_h = kTileH[sh];
+    p->tuning.slices = shape_slices[sh];
+    p->tuning.capacity = shape_cap[sh];
+    p->tuning.splat_waves = kWaves[v];
+    p->tuning.persistent = kPersist[v];
+    if ((rc = plan_realloc(p)) != DIGS_OK) return rc;
     return digs_reset_diagnostics(p->ws, p->cap);
 }
 

@@ -352,7 +352,9 @@ struct TileRect {
         q.w = tx1 - q.tx0 + 1;
         q.h = ty1 - q.ty0 + 1;
         q.R = (tx1 >= q.tx0 && ty1 >= q.ty0) ? q.w * q.h : 0;
-        q.m = q.R >= 32 ? ~0u : ((uint32_t)r.z & ((1u << q.R) - 1u));
+        // (a rectangle of exactly 32 tiles keeps its whole 32-bit mask)
+        q.m = q.R > 32 ? ~0u
+                       : (q.R == 32 ? (uint32_t)r.z : ((uint32_t)r.z & ((1u << q.R) - 1u)));
         return q;
     }
     __device__ int count() const { return R > 32 ? R : __popc(m); }
@@ -378,22 +380,23 @@ struct TileRect {
 };
 
 // Instance mask of a footprint rectangle of R <= 32 tiles (see TileRect): in each row of tiles,
-// the tiles whose 16 columns meet the ellipse's x-extent over the row's 16 pixel rows. (This
+// the tiles whose tw columns meet the ellipse's x-extent over the row's th pixel rows. (This
 // keeps every tile in which a list entry could mark an 8x8 block; a kept tile with no such block
 // only costs an empty entry.)
-__device__ uint32_t footprint_tiles(const Footprint &fp, int tx0, int ty0, int w, int h)
+__device__ uint32_t footprint_tiles(const Footprint &fp, int tx0, int ty0, int w, int h, int tw,
+                                    int th)
 {
     FootEll fe;
     fe.init(fp.a00, fp.a01, fp.a11, fp.cx, fp.cy);
     if (!fe.ell) return ~0u;
     uint32_t m = 0u;
+    const float inv = 1.0f / (float)tw;   // exact: tw is a power of two
     for (int r = 0; r < h; ++r) {
-        const float y0 = (float)((ty0 + r) * DIGS_TILE);
+        const float y0 = (float)((ty0 + r) * th);
         float L, R;
-        if (!fe.strip(y0, y0 + (float)(DIGS_TILE - 1), L, R)) continue;
-        // columns c with (tx0 + c) 16 <= R and (tx0 + c) 16 + 15 >= L
-        const float inv = 1.0f / (float)DIGS_TILE;
-        const int c0 = max(0, (int)ceilf(fmaxf((L - (float)(DIGS_TILE - 1)) * inv, -1.0f)) - tx0);
+        if (!fe.strip(y0, y0 + (float)(th - 1), L, R)) continue;
+        // columns c with (tx0 + c) tw <= R and (tx0 + c) tw + tw - 1 >= L
+        const int c0 = max(0, (int)ceilf(fmaxf((L - (float)(tw - 1)) * inv, -1.0f)) - tx0);
         const int c1 = min(w - 1, (int)floorf(fminf(R * inv, 65536.0f)) - tx0);
         if (c0 <= c1) m |= (((1u << (c1 - c0)) << 1) - 1u) << (r * w + c0);
     }
@@ -467,13 +470,13 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
         uint32_t count = 0;
         int4 rr = make_int4(1, 0, 0, 0);
         if (valid && ok && x0 <= x1 && y0 <= y1) {
-            const int tx0 = x0 / DIGS_TILE, tx1 = x1 / DIGS_TILE;
-            const int ty0 = y0 / DIGS_TILE, ty1 = y1 / DIGS_TILE;
+            const int tx0 = x0 >> G.tile_lw, tx1 = x1 >> G.tile_lw;
+            const int ty0 = y0 >> G.tile_lh, ty1 = y1 >> G.tile_lh;
             const int w = tx1 - tx0 + 1, h = ty1 - ty0 + 1;
             count = (uint32_t)(w * h);
             uint32_t m = ~0u;
             if (w * h <= 32) {
-                m = footprint_tiles(fp, tx0, ty0, w, h);
+                m = footprint_tiles(fp, tx0, ty0, w, h, G.tile_w, G.tile_h);
                 if (w * h < 32) m &= (1u << (w * h)) - 1u;
                 count = (uint32_t)__popc(m);
             }
@@ -517,12 +520,36 @@ __global__ __launch_bounds__(256) void k_setup(DevGeom G, int n, int T,
 
 // ------------------------------------------------------------------------------------------
 // a4: binning sources. A tile list entry is the Gaussian's index in the low 24 bits; above it two
-// bits per 8x8 pixel block b of the tile (blocks in row-major order: block column b & 1, block row
-// b >> 1): bit LIST_BLOCK_SHIFT + 2b is set when the cut-off footprint ellipse meets rows 0-3 of
-// the block, the next bit when it meets rows 4-7. The splats evaluate only those rows.
+// bits per 8x8 pixel block b of the tile (at most four blocks, in row-major order: block column
+// b % tile_bx, block row b / tile_bx): bit LIST_BLOCK_SHIFT + 2b is set when the cut-off footprint
+// ellipse meets rows 0-3 of the block, the next bit when it meets rows 4-7. The splats evaluate
+// only those rows.
 #define LIST_INDEX_MASK 0x00FFFFFFu
 #define LIST_BLOCK_SHIFT 24
 
+// Per 8x8 block b of tile (tx, ty) of a TW x TH tile shape, which 4-row halves the cut-off ellipse
+// meets (bits 2b and 2b + 1; blocks in row-major order).
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t block_mask(const FootEll &fe, int tx, int ty)
+{
+    uint32_t m = 0u;
+    const float x0 = (float)(tx * TW), y0 = (float)(ty * TH);
+#pragma unroll
+    for (int s4 = 0; s4 < TH / 4; ++s4) {   // 4-row strips; block row s4 >> 1, half s4 & 1
+        float L, R;
+        if (fe.strip(y0 + (float)(4 * s4), y0 + (float)(4 * s4 + 3), L, R)) {
+            const int b = (s4 >> 1) * (TW / 8), h = s4 & 1;
+#pragma unroll
+            for (int c = 0; c < TW / 8; ++c) {   // block columns
+                const float xb = x0 + (float)(8 * c);
+                if (xb <= R && xb + 7.0f >= L) m |= 1u << (2 * (b + c) + h);
+            }
+        }
+    }
+    return m;
+}
+
+template <int TW, int TH>   // tile shape (pixels)
 struct TileSrc {
     const int4 *rect;        // [T][N] footprint rectangles and instance masks (TileRect)
     const float4 *rec;       // [T][N][4] projected records (footprint conic in rec[2].w, rec[3])
@@ -592,20 +619,8 @@ struct TileSrc {
         // the tile from its key (key / tiles_x in float: exact for keys below 2^21)
         const int ty = (int)(((float)key + 0.5f) * inv_tiles_x);
         const int tx = (int)key - __mul24(ty, tiles_x);
-        uint32_t m = 0xFFu;
-        if (it.fe.ell) {
-            m = 0u;
-            const float x0 = (float)(tx * DIGS_TILE), y0 = (float)(ty * DIGS_TILE);
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {   // 4-row strips; block row s4 >> 1, half s4 & 1
-                float L, R;
-                if (it.fe.strip(y0 + (float)(4 * s4), y0 + (float)(4 * s4 + 3), L, R)) {
-                    const int b = 2 * (s4 >> 1), h = s4 & 1;
-                    if (x0 <= R && x0 + 7.0f >= L) m |= 1u << (2 * b + h);
-                    if (x0 + 8.0f <= R && x0 + 15.0f >= L) m |= 1u << (2 * (b + 1) + h);
-                }
-            }
-        }
+        // (bits of blocks the tile does not have are never read)
+        const uint32_t m = it.fe.ell ? block_mask<TW, TH>(it.fe, tx, ty) : 0xFFu;
         list[pos] = (uint32_t)item | (m << LIST_BLOCK_SHIFT);
     }
 };
@@ -750,9 +765,14 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
     const float4 *rt = rec + (size_t)t * n * 4;
     // the wave's three queues: Gaussians that meet rows 0-7 of the block, only rows 0-3, only 4-7
     uint32_t(*qs)[FWD_QUEUE] = ids[wave];
-    for (int pass = 0; pass < 4 / WAVES; ++pass) {
-        const int blkid = (WAVES == 4) ? wave : pass;
-        const int bx = tx * DIGS_TILE + (blkid & 1) * 8, by = ty * DIGS_TILE + (blkid >> 1) * 8;
+    // WAVES > 1 is launched only with one wave per block of the tile; a single wave takes the
+    // tile's blocks in turn
+    const int lbx = G.tile_lw - 3;   // log2 of the blocks per tile row
+    const int nblocks = WAVES > 1 ? 1 : G.tile_nb;
+    for (int pass = 0; pass < nblocks; ++pass) {
+        const int blkid = WAVES > 1 ? wave : pass;
+        const int bx = tx * G.tile_w + (blkid & (G.tile_bx - 1)) * 8;
+        const int by = ty * G.tile_h + (blkid >> lbx) * 8;
         const float fi = (float)(bx + col), fby = (float)by;
         float acc[8], accn[8];
 #pragma unroll
@@ -811,8 +831,8 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
         for (int r = 1; r < 8; ++r) v = (gslot == r) ? acc[r] : v;
         const int px = bx + col, py = by + gslot;
         if (nsl > 1) {
-            const int p = (py - ty * DIGS_TILE) * DIGS_TILE + (px - tx * DIGS_TILE);
-            spart[(((size_t)sl * T + t) * G.ntiles + tile) * DIGS_TILE_PX + p] = v;
+            const int p = (py - ty * G.tile_h) * G.tile_w + (px - tx * G.tile_w);
+            spart[(((size_t)sl * T + t) * G.ntiles + tile) * (G.tile_w * G.tile_h) + p] = v;
         } else if (px < G.nu && py < G.nv) {
             // exact: times the pixel's ray length |e| (EWA: |e*| is in each amplitude)
             if constexpr (!EWA) {
@@ -872,10 +892,11 @@ __global__ __launch_bounds__(256) void k_slice_reduce(DevGeom G, int T, int nsl,
     const int t = (int)(i / npx);
     const int rem = (int)(i - (size_t)t * npx);
     const int py = rem / G.nu, px = rem - py * G.nu;
-    const int tile = (py / DIGS_TILE) * G.tiles_x + px / DIGS_TILE;
-    const int p = (py % DIGS_TILE) * DIGS_TILE + px % DIGS_TILE;
-    const size_t stride = (size_t)T * G.ntiles * DIGS_TILE_PX;
-    const float *src = spart + ((size_t)t * G.ntiles + tile) * DIGS_TILE_PX + p;
+    const int tile = (py >> G.tile_lh) * G.tiles_x + (px >> G.tile_lw);
+    const int p = (py & (G.tile_h - 1)) * G.tile_w + (px & (G.tile_w - 1));
+    const int tpx = G.tile_w * G.tile_h;
+    const size_t stride = (size_t)T * G.ntiles * tpx;
+    const float *src = spart + ((size_t)t * G.ntiles + tile) * tpx + p;
     float v = src[0];
     for (int s = 1; s < nsl; ++s) v += src[(size_t)s * stride];
     if constexpr (!EWA) {
@@ -929,9 +950,11 @@ __global__ __launch_bounds__(256) void k_count_pairs(DevGeom G, int n, int T, fl
     uint32_t begin = cnt[cidx], end = cnt[cidx + nblk];
     begin = min(begin, cap);
     end = min(max(end, begin), cap);
-    const int bx = tx * DIGS_TILE + (wave & 1) * 8, by = ty * DIGS_TILE + (wave >> 1) * 8;
+    const int bx = tx * G.tile_w + (wave & (G.tile_bx - 1)) * 8;
+    const int by = ty * G.tile_h + (wave >> (G.tile_lw - 3)) * 8;
     const int px = bx + (lane & 7), py = by + (lane >> 3);
     const bool on_det = px < G.nu && py < G.nv;
+    if (wave >= G.tile_nb) begin = end;   // the tile has fewer blocks than waves
     const float c2r2 = (-0.72134752044448170f) * cull * cull;   // exp2 argument at the cut-off
     unsigned long long in_fp = 0, eval_f = 0;
     for (uint32_t k = begin; k < end; ++k) {
@@ -992,10 +1015,11 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 //  4 S_quu, 5 S_quv, 6 S_qvv  sum A_q du^2, du dv, dv^2   (A_q = dL/dq)
 //  7 S_qu, 8 S_qv, 9 S_q      sum A_q du, dv, 1
 //  10 S_Eu, 11 S_Ev           sum A_E du, dv
-#define GPX_STRIDE 18
+// dL/dI of the tile in LDS: rows of tile_w + 2 floats (18 for 16-pixel rows)
+#define GPX_FLOATS 320              // the largest tile's rows: 32 x (8 + 2) or 16 x 18 or 8 x 34
 #define BWD_QUEUE (5 * DIGS_WAVE)   // carried (< 64) + one chunk's pairs (<= 256)
 struct BwdShared {
-    float gpx[DIGS_TILE * GPX_STRIDE];
+    float gpx[GPX_FLOATS];
     uint32_t pairs[4][2][BWD_QUEUE];       // (entry slot << 3) | (half << 2) | block
     uint32_t gid[4][2 * DIGS_WAVE];        // Gaussian of each entry slot
     float accS[4][2 * DIGS_WAVE][13];      // moment sums of each entry slot
@@ -1003,8 +1027,9 @@ struct BwdShared {
 
 // Evaluates queued pairs [j0, j0 + cnt) of the wave (cnt <= 64), one per lane, over NROWS rows of
 // the pair's block (with NROWS == 4 the half that bit 2 of the pair names), and adds their moment
-// sums into the entries' slots. EWA: q = 1 (no dL/dq moments), one exp2 per pixel.
-template <bool EWA, int NROWS>
+// sums into the entries' slots (NB blocks per tile). EWA: q = 1 (no dL/dq moments), one exp2 per
+// pixel. TW: tile width in pixels (the LDS rows of dL/dI hold TW + 2 floats).
+template <bool EWA, int NROWS, int TW, int NB>
 __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ pq,
                                                 const uint32_t *__restrict__ gid,
@@ -1014,6 +1039,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     // products are not contracted into sums here: each product feeds several sums, and a
     // contraction would compute it twice
 #pragma clang fp contract(off)
+    constexpr int GPX_STRIDE = TW + 2, BXL = TW == 8 ? 0 : (TW == 16 ? 1 : 2);
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int lane = lane_id();
     const bool active = lane < cnt;
@@ -1028,7 +1054,8 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     }
     // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
     // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
-    const int lbx = (blk & 1) * 8, lby = (blk >> 1) * 8 + (NROWS == 4 ? (int)((pr >> 2) & 1u) * 4 : 0);
+    const int lbx = (blk & ((1 << BXL) - 1)) * 8;
+    const int lby = (blk >> BXL) * 8 + (NROWS == 4 ? (int)((pr >> 2) & 1u) * 4 : 0);
     const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
     const float Cq = r1.w, CE = r0.z, Gvv = fabsf(r2.y);
     const float s1 = fmaf(2.0f, du0, 1.0f), t1 = fmaf(2.0f, dv0, 1.0f);
@@ -1163,7 +1190,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     }
     // add into the entry's slot, one block at a time (an entry has at most one pair per block)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NB; ++b) {
         if (active && blk == b) {
             float *dst = accS[slot];
 #pragma unroll
@@ -1193,8 +1220,8 @@ __device__ __forceinline__ void splat_bwd_write(int n, int t, int tx, int ty, ui
 }
 
 // With nsl > 1 the workgroup takes slice sl of the tile's list (every entry's partial is still
-// complete: an entry is in one slice, and its four blocks are summed in order as before).
-template <bool EWA>
+// complete: an entry is in one slice, and its blocks are summed in order as before).
+template <bool EWA, int TW, int TH>
 __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, int tile,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ list,
@@ -1205,12 +1232,13 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                                                float4 *__restrict__ part, BwdShared &sh,
                                                int sl = 0, int nsl = 1)
 {
+    constexpr int GPX_STRIDE = TW + 2, NB = (TW / 8) * (TH / 8);
     float *gpx = sh.gpx;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = uniform((int)(threadIdx.x / DIGS_WAVE)), lane = lane_id();
-    {
+    if ((int)threadIdx.x < TW * TH) {   // one thread per pixel of the tile
         const int p = threadIdx.x;
-        const int px = tx * DIGS_TILE + (p & 15), py = ty * DIGS_TILE + (p >> 4);
+        const int px = tx * TW + (p % TW), py = ty * TH + p / TW;
         float gv = 0.0f;
         if (px < G.nu && py < G.nv) {
             gv = grad_proj[((size_t)t * G.nv + py) * G.nu + px];
@@ -1220,7 +1248,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
                 gv *= sqrtf(G.sdd * G.sdd + xu * xu + yv * yv);
             }
         }
-        gpx[(p >> 4) * GPX_STRIDE + (p & 15)] = gv;
+        gpx[(p / TW) * GPX_STRIDE + (p % TW)] = gv;
     }
     __syncthreads();
     const size_t cidx = ((size_t)t * G.ntiles + tile) * nblk;
@@ -1229,7 +1257,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
     end = min(max(end, begin), cap);
     slice_range(begin, end, sl, nsl, 4 * DIGS_WAVE);
     const float4 *rt = rec + (size_t)t * n * 4;
-    const int tx0 = tx * DIGS_TILE, ty0 = ty * DIGS_TILE;
+    const int tx0 = tx * TW, ty0 = ty * TH;
     uint32_t *pq0 = sh.pairs[wave][0];   // pairs over all 8 rows of the block
     uint32_t *pq1 = sh.pairs[wave][1];   // pairs over 4 rows (one half of the block)
     uint32_t *gid = sh.gid[wave];
@@ -1251,7 +1279,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         int np0 = pend0, np1 = pend1;
         const unsigned long long lt = lanemask_lt();
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) {
+        for (int blk = 0; blk < NB; ++blk) {
             const uint32_t h = valid ? (ent >> (LIST_BLOCK_SHIFT + 2 * blk)) & 3u : 0u;
             const bool whole = h == 3u, half = h == 1u || h == 2u;
             const unsigned long long mw = __ballot(whole), mh = __ballot(half);
@@ -1268,11 +1296,11 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         if (done0 == 0 && pend0 > 0) done0 = np0;
         if (done1 == 0 && pend1 > 0) done1 = np1;
         for (int j = 0; j < done0; j += DIGS_WAVE)
-            splat_bwd_group<EWA, 8>(rt, pq0, gid, accS, gpx, j, min(DIGS_WAVE, done0 - j), tx0,
-                                    ty0);
+            splat_bwd_group<EWA, 8, TW, NB>(rt, pq0, gid, accS, gpx, j,
+                                            min(DIGS_WAVE, done0 - j), tx0, ty0);
         for (int j = 0; j < done1; j += DIGS_WAVE)
-            splat_bwd_group<EWA, 4>(rt, pq1, gid, accS, gpx, j, min(DIGS_WAVE, done1 - j), tx0,
-                                    ty0);
+            splat_bwd_group<EWA, 4, TW, NB>(rt, pq1, gid, accS, gpx, j,
+                                            min(DIGS_WAVE, done1 - j), tx0, ty0);
         if (it > 0 && prev_valid)
             splat_bwd_write(n, t, tx, ty, prev_g, accS[(ring ^ DIGS_WAVE) + lane], cap, rect, goff,
                             part);
@@ -1290,15 +1318,15 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         prev_valid = valid;
         prev_g = g;
     }
-    if (pend0 > 0) splat_bwd_group<EWA, 8>(rt, pq0, gid, accS, gpx, 0, pend0, tx0, ty0);
-    if (pend1 > 0) splat_bwd_group<EWA, 4>(rt, pq1, gid, accS, gpx, 0, pend1, tx0, ty0);
+    if (pend0 > 0) splat_bwd_group<EWA, 8, TW, NB>(rt, pq0, gid, accS, gpx, 0, pend0, tx0, ty0);
+    if (pend1 > 0) splat_bwd_group<EWA, 4, TW, NB>(rt, pq1, gid, accS, gpx, 0, pend1, tx0, ty0);
     if (it > 0 && prev_valid)
         splat_bwd_write(n, t, tx, ty, prev_g, accS[((it - 1) & 1) * DIGS_WAVE + lane], cap, rect,
                         goff, part);
     wave_sync_lds();
 }
 
-template <bool EWA>
+template <bool EWA, int TW, int TH>
 __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
                                                    const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ list,
@@ -1311,11 +1339,11 @@ __global__ __launch_bounds__(256) void k_splat_bwd(DevGeom G, int n, int T,
     __shared__ BwdShared sh;
     int t, tile;
     map_block(blockIdx.x, G.ntiles, T, t, tile);
-    splat_bwd_tile<EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj, part,
-                        sh, blockIdx.y, gridDim.y);
+    splat_bwd_tile<EWA, TW, TH>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj,
+                                part, sh, blockIdx.y, gridDim.y);
 }
 
-template <bool EWA>
+template <bool EWA, int TW, int TH>
 __global__ __launch_bounds__(256) void k_splat_bwd_persist(
     DevGeom G, int n, int T, const float4 *__restrict__ rec, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ cnt, int nblk, unsigned cap, const int4 *__restrict__ rect,
@@ -1333,8 +1361,8 @@ __global__ __launch_bounds__(256) void k_splat_bwd_persist(
         if (item < 0) break;
         int t, tile;
         map_block(item, G.ntiles, T, t, tile);
-        splat_bwd_tile<EWA>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff, grad_proj,
-                            part, sh);
+        splat_bwd_tile<EWA, TW, TH>(G, n, t, tile, rec, list, cnt, nblk, cap, rect, goff,
+                                    grad_proj, part, sh);
     }
 }
 
@@ -1986,6 +2014,23 @@ hipError_t render_forward_setup(const RenderArgs &a, hipStream_t s)
     return render_forward_views(a, s);
 }
 
+// The tile lists of the call's (view, Gaussian) instances, binned for a TW x TH tile shape.
+template <int TW, int TH>
+static hipError_t bin_tiles(const RenderArgs &a, uint32_t *cnt, size_t cnt_elems,
+                            uint32_t *scratch, hipStream_t s)
+{
+    TileSrc<TW, TH> src;
+    src.rect = WS(a, rect, const int4 *);
+    src.rec = WS(a, rec, const float4 *);
+    src.list = WS(a, list, uint32_t *);
+    src.cap = a.L.cap;
+    src.items = a.n;
+    src.tiles_x = a.geom.tiles_x;
+    src.inv_tiles_x = 1.0f / (float)a.geom.tiles_x;
+    return launch_binning(src, a.T, a.geom.ntiles, a.L.nblk, bits_for(a.geom.ntiles), cnt,
+                          cnt_elems + 1, scratch, s, a.L.bin_items);
+}
+
 // The per-view stages: the warp and projected records, instance offsets and the tile lists.
 hipError_t render_forward_views(const RenderArgs &a, hipStream_t s)
 {
@@ -2016,16 +2061,13 @@ hipError_t render_forward_views(const RenderArgs &a, hipStream_t s)
         e = launch_exclusive_scan(WS(a, gcount, uint32_t *), (size_t)a.T * a.n, scratch, s);
     }
     if (e != hipSuccess) return e;
-    TileSrc src;
-    src.rect = WS(a, rect, const int4 *);
-    src.rec = WS(a, rec, const float4 *);
-    src.list = WS(a, list, uint32_t *);
-    src.cap = a.L.cap;
-    src.items = a.n;
-    src.tiles_x = a.geom.tiles_x;
-    src.inv_tiles_x = 1.0f / (float)a.geom.tiles_x;
-    e = launch_binning(src, a.T, a.geom.ntiles, a.L.nblk, bits_for(a.geom.ntiles), cnt,
-                       cnt_elems + 1, scratch, s, a.L.bin_items);
+    const int tw = a.geom.tile_w, th = a.geom.tile_h;
+    if (tw == 16 && th == 16) e = bin_tiles<16, 16>(a, cnt, cnt_elems, scratch, s);
+    else if (tw == 32) e = bin_tiles<32, 8>(a, cnt, cnt_elems, scratch, s);
+    else if (tw == 16) e = bin_tiles<16, 8>(a, cnt, cnt_elems, scratch, s);
+    else if (th == 32) e = bin_tiles<8, 32>(a, cnt, cnt_elems, scratch, s);
+    else if (th == 16) e = bin_tiles<8, 16>(a, cnt, cnt_elems, scratch, s);
+    else e = bin_tiles<8, 8>(a, cnt, cnt_elems, scratch, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_check, dim3(1), dim3(1), 0, s, WS(a, diag, DiagBlock *));
     return hipGetLastError();
@@ -2038,8 +2080,8 @@ template <class K>
 static unsigned persistent_grid(K kernel, int threads, size_t items)
 {
     static int cus = 0;
-    static const void *known[8];
-    static int known_per_cu[8];
+    static const void *known[32];
+    static int known_per_cu[32];
     static int nknown = 0;
     if (cus == 0) {
         int dev = 0;
@@ -2056,7 +2098,7 @@ static unsigned persistent_grid(K kernel, int threads, size_t items)
                 hipSuccess ||
             per_cu <= 0)
             per_cu = 1;
-        if (nknown < 8) {
+        if (nknown < 32) {
             known[nknown] = (const void *)kernel;
             known_per_cu[nknown++] = per_cu;
         }
@@ -2065,15 +2107,28 @@ static unsigned persistent_grid(K kernel, int threads, size_t items)
     return (unsigned)(g < items ? g : items);
 }
 
+template <bool EWA>
+static void prepare_bwd_shapes()
+{
+    (void)persistent_grid(k_splat_bwd_persist<EWA, 16, 16>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<EWA, 32, 8>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<EWA, 8, 32>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<EWA, 16, 8>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<EWA, 8, 16>, 256, 1);
+    (void)persistent_grid(k_splat_bwd_persist<EWA, 8, 8>, 256, 1);
+}
+
 // Run the device queries of the persistent launches now (before any graph capture).
 void render_prepare_launch_shapes()
 {
     (void)persistent_grid(k_splat_fwd_persist<1, false>, 64, 1);
+    (void)persistent_grid(k_splat_fwd_persist<2, false>, 128, 1);
     (void)persistent_grid(k_splat_fwd_persist<4, false>, 256, 1);
     (void)persistent_grid(k_splat_fwd_persist<1, true>, 64, 1);
+    (void)persistent_grid(k_splat_fwd_persist<2, true>, 128, 1);
     (void)persistent_grid(k_splat_fwd_persist<4, true>, 256, 1);
-    (void)persistent_grid(k_splat_bwd_persist<false>, 256, 1);
-    (void)persistent_grid(k_splat_bwd_persist<true>, 256, 1);
+    prepare_bwd_shapes<false>();
+    prepare_bwd_shapes<true>();
 }
 
 template <int WAVES, bool EWA>
@@ -2117,9 +2172,14 @@ hipError_t render_forward_splat(const RenderArgs &a, float *proj, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     ProfScope ps(PS_SPLAT_FWD, s);
-    if (a.splat_waves == 1) {
+    // waves per workgroup: the tuning's, at most one per 8x8 block of the tile
+    const int waves = std::min(a.splat_waves, a.geom.tile_nb);
+    if (waves == 1) {
         if (a.geom.ewa) launch_splat_fwd<1, true>(a, proj, queue, items, s);
         else launch_splat_fwd<1, false>(a, proj, queue, items, s);
+    } else if (waves == 2) {
+        if (a.geom.ewa) launch_splat_fwd<2, true>(a, proj, queue, items, s);
+        else launch_splat_fwd<2, false>(a, proj, queue, items, s);
     } else {
         if (a.geom.ewa) launch_splat_fwd<4, true>(a, proj, queue, items, s);
         else launch_splat_fwd<4, false>(a, proj, queue, items, s);
@@ -2176,25 +2236,41 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
     return e;
 }
 
-template <bool EWA>
+template <bool EWA, int TW, int TH>
 static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32_t *queue,
                              size_t items, hipStream_t s)
 {
     if (a.persistent && a.L.slices <= 1)
-        hipLaunchKernelGGL(k_splat_bwd_persist<EWA>,
-                           dim3(persistent_grid(k_splat_bwd_persist<EWA>, 256, items)), dim3(256),
+        hipLaunchKernelGGL((k_splat_bwd_persist<EWA, TW, TH>),
+                           dim3(persistent_grid(k_splat_bwd_persist<EWA, TW, TH>, 256, items)),
+                           dim3(256),
                            0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
                            WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
                            (unsigned)a.L.cap, WS(a, rect, const int4 *),
                            WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
                            queue);
     else
-        hipLaunchKernelGGL(k_splat_bwd<EWA>, dim3((unsigned)items, (unsigned)a.L.slices), dim3(256),
+        hipLaunchKernelGGL((k_splat_bwd<EWA, TW, TH>),
+                           dim3((unsigned)items, (unsigned)a.L.slices), dim3(256),
                            0, s, a.geom, a.n,
                            a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
                            WS(a, rect, const int4 *), WS(a, gcount, const uint32_t *), grad_proj,
                            WS(a, part, float4 *));
+}
+
+// the backward splat specialised for the call's tile shape
+template <bool EWA>
+static void launch_splat_bwd_shape(const RenderArgs &a, const float *grad_proj, uint32_t *queue,
+                                   size_t items, hipStream_t s)
+{
+    const int tw = a.geom.tile_w, th = a.geom.tile_h;
+    if (tw == 16 && th == 16) launch_splat_bwd<EWA, 16, 16>(a, grad_proj, queue, items, s);
+    else if (tw == 32) launch_splat_bwd<EWA, 32, 8>(a, grad_proj, queue, items, s);
+    else if (tw == 16) launch_splat_bwd<EWA, 16, 8>(a, grad_proj, queue, items, s);
+    else if (th == 32) launch_splat_bwd<EWA, 8, 32>(a, grad_proj, queue, items, s);
+    else if (th == 16) launch_splat_bwd<EWA, 8, 16>(a, grad_proj, queue, items, s);
+    else launch_splat_bwd<EWA, 8, 8>(a, grad_proj, queue, items, s);
 }
 
 hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g_mu,
@@ -2211,8 +2287,8 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         ProfScope ps(PS_SPLAT_BWD, s);
-        if (a.geom.ewa) launch_splat_bwd<true>(a, grad_proj, queue, items, s);
-        else launch_splat_bwd<false>(a, grad_proj, queue, items, s);
+        if (a.geom.ewa) launch_splat_bwd_shape<true>(a, grad_proj, queue, items, s);
+        else launch_splat_bwd_shape<false>(a, grad_proj, queue, items, s);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;

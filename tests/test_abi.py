@@ -81,6 +81,29 @@ def test_host_side_validation_and_sizes():
     assert rc == -2
 
 
+
+def test_tile_shape_validation():
+    """Tile shapes of one, two or four 8x8 blocks with edges 8, 16 or 32 are accepted, others
+    rejected (workspace size 0), and a shape whose tiles exceed DIGS_MAX_TILES too."""
+    from paper_2506_22280_amd import _lib, synth
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libdigs.so is not built")
+    p = synth.tiny()
+    sizes = {}
+    for tw, th in ((16, 16), (32, 8), (8, 32), (16, 8), (8, 16), (8, 8)):
+        sizes[tw, th] = _lib.workspace_size(p.geom, p.grid, p.n, 4, dict(tile_w=tw, tile_h=th))
+        assert sizes[tw, th] > 0, (tw, th)
+    assert sizes[16, 16] == _lib.workspace_size(p.geom, p.grid, p.n, 4, None)
+    for tw, th in ((32, 16), (16, 32), (32, 32), (4, 8), (8, 0), (0, 8), (24, 8), (64, 4)):
+        assert _lib.workspace_size(p.geom, p.grid, p.n, 4, dict(tile_w=tw, tile_h=th)) == 0, \
+            (tw, th)
+    # 8x8 tiles of a 1024x768 detector are more than DIGS_MAX_TILES; 16x16 and 32x8 fit
+    big = dict(p.geom, nu=1024, nv=768)
+    assert _lib.workspace_size(big, p.grid, p.n, 4, dict(tile_w=8, tile_h=8)) == 0
+    assert _lib.workspace_size(big, p.grid, p.n, 4, dict(tile_w=32, tile_h=8)) > 0
+    assert _lib.workspace_size(big, p.grid, p.n, 4, None) > 0
+
+
 def test_binding_rejects_mismatched_shapes():
     """The library indexes each buffer by the sizes passed beside it; the binding checks every
     tensor's shape against them first (host side, before any device call)."""

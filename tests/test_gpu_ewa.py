@@ -26,10 +26,10 @@ def _ewa(p, **kw):
     return p
 
 
-def _fwd(p, t, ws=None):
+def _fwd(p, t, ws=None, tuning=None):
     ws = ws or _lib.Workspace()
     proj = _lib.project_fwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
-                            t["angles"], t["w"], ws)
+                            t["angles"], t["w"], ws, tuning=tuning)
     torch.cuda.synchronize()
     return proj, ws
 
@@ -175,16 +175,20 @@ def test_ewa_plan_replays_equal_eager():
     p = _ewa(synth.tiny(seed=4, n=3000, nviews=8))
     t = problem_tensors(p)
     T = len(p.angles)
-    eager, _ = _fwd(p, t)
     c = torch.randn((T, p.geom["nv"], p.geom["nu"]), device="cuda",
                     generator=torch.Generator("cuda").manual_seed(5))
-    g_eager = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"],
-                               t["rho"], t["angles"], t["w"], c, _lib.Workspace())
-    bufs = dict(t, proj=torch.empty_like(eager), grad_proj=c,
+    bufs = dict(t, proj=torch.empty((T, p.geom["nv"], p.geom["nu"]), device="cuda"), grad_proj=c,
                 g_mu=torch.empty_like(t["mu"]), g_scale=torch.empty_like(t["scale"]),
                 g_quat=torch.empty_like(t["quat"]), g_rho=torch.empty_like(t["rho"]),
                 g_coef=torch.empty_like(t["coef"]), g_w=torch.empty_like(t["w"]))
     with _lib.Plan(p.geom, p.grid, p.n, T, bufs) as plan:
+        # the eager calls with the tile shape and list slices the autotuner chose
+        tun = plan.tuning()[0]
+        shape = {k: tun[k] for k in ("tile_w", "tile_h", "slices")}
+        eager, _ = _fwd(p, t, tuning=shape)
+        g_eager = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"],
+                                   t["rho"], t["angles"], t["w"], c, _lib.Workspace(),
+                                   tuning=shape)
         for _ in range(3):
             plan.fwd()
             plan.bwd()

@@ -50,11 +50,13 @@ def test_plan_replays_equal_eager(nviews):
     p = synth.small_phantom(n=2048, nviews=nviews, seed=4)
     idx = np.arange(nviews)
     b = _buffers(p, idx)
-    ref_proj, ref_g = _eager(p, b)
     with _lib.Plan(p.geom, p.grid, p.n, nviews, b) as plan:
         tuning, ms = plan.tuning()
         _print("chosen", tuning, "timings", ms)
         assert tuning["capacity"] > 0
+        # eager calls with the tile shape and list slices the autotuner chose
+        shape = {k: tuning[k] for k in ("tile_w", "tile_h", "slices")}
+        ref_proj, ref_g = _eager(p, b, tuning=shape)
         for rep in range(3):
             b["proj"].fill_(-1.0)
             for k in _GRADS:
@@ -66,7 +68,7 @@ def test_plan_replays_equal_eager(nviews):
             for k in _GRADS:
                 assert torch.equal(b[k], ref_g[k]), (rep, k)
             # eager work of the program itself between replays
-            _eager(p, b)
+            _eager(p, b, tuning=shape)
         # a new batch: other views written into the same buffers
         p2 = synth.small_phantom(n=2048, nviews=2 * nviews, seed=4)
         a2, w2 = p2.views(np.arange(nviews, 2 * nviews))
@@ -78,7 +80,7 @@ def test_plan_replays_equal_eager(nviews):
         assert not resized and diag["overflow"] == 0
         got = b["proj"].clone()
         gg = {k: b[k].clone() for k in _GRADS}
-        ref2_proj, ref2_g = _eager(p, b)
+        ref2_proj, ref2_g = _eager(p, b, tuning=shape)
         assert torch.equal(got, ref2_proj)
         for k in _GRADS:
             assert torch.equal(gg[k], ref2_g[k]), k

@@ -117,7 +117,9 @@ def test_loop_repeats_a_window_whose_renders_overflowed():
     meas = _lib.project_fwd(p.geom, p.grid, d(p.coef), d(p.mu), d(p.scale), d(p.quat),
                             d(p.rho), d(p.angles), d(p.w), ws).clone()
     outs, resized = [], []
-    for tuning in (dict(capacity=64), None):
+    # the same tile shape in both runs (the autotuner may pick another, which sums in another
+    # order); the second run's capacity is ample
+    for tuning in (dict(capacity=64), dict(capacity=64 * p.n)):
         rec = recon.Reconstruction(p, meas, recon.perturbed_init(p, np.random.default_rng(5)),
                                    iters=60, seed=7, tuning=tuning)
         losses = rec.run(60, log_every=20, check_every=20)
