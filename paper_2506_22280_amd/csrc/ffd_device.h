@@ -66,13 +66,35 @@ __device__ __forceinline__ T pick4(const T (&v)[4], int n)
     return n == 0 ? v[0] : (n == 1 ? v[1] : (n == 2 ? v[2] : v[3]));
 }
 
+// Where the control points of the lattice are read from. A source's row(r, k, j) points at
+// control point (0, j, k) of rank r, so that row(r, k, j) + 3 i is point (i, j, k) (three floats).
+// LatticeRows: the caller's coefficient array in device memory, coef[R][nz][ny][nx][3].
+struct LatticeRows {
+    const float *coef;
+    int nx, ny, nz;
+    __device__ const float *row(int r, int k, int j) const
+    {
+        return coef + ((((size_t)r * nz + k) * ny + j) * nx) * 3;
+    }
+};
+
+// BrickRows: a box of control points [x0, x0 + bx) x [y0, y0 + by) x [z0, z0 + bz) of every rank
+// staged in LDS as b[R][bz][by][bx][3] (see stage_brick); only points inside the box are valid.
+struct BrickRows {
+    const float *b;
+    int x0, y0, z0, bx, by, bz;
+    __device__ const float *row(int r, int k, int j) const
+    {
+        return b + ((((r * bz + (k - z0)) * by + (j - y0)) * bx) - x0) * 3;
+    }
+};
+
 // u_r and grad u_r (row-major, J[3a+b] = du_a/dx_b) of one rank at the stencil's point.
 // With NZ < 4, only the stencil's z index nz0 (its partial sum; the caller adds the four).
-template <int NZ = 4>
-__device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restrict__ coef, int r,
-                                         const Stencil &s, float u[3], float J[9], int nz0 = 0)
+template <int NZ = 4, class Rows>
+__device__ __forceinline__ void ffd_rank_rows(const Rows &rows, int r, const Stencil &s,
+                                              float u[3], float J[9], int nz0 = 0)
 {
-    const float *base = coef + (size_t)r * g.nz * g.ny * g.nx * 3;
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = 0.f;
 #pragma unroll
@@ -86,7 +108,7 @@ __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restri
         const float dBz = NZ == 4 ? s.dBz[nn] : pick4(s.dBz, n);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const float *row = base + ((size_t)(kk * g.ny + s.jj[m]) * g.nx) * 3;
+            const float *row = rows.row(r, kk, s.jj[m]);
             float sx[3] = {0.f, 0.f, 0.f}, sdx[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
@@ -110,15 +132,21 @@ __device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restri
     }
 }
 
+template <int NZ = 4>
+__device__ __forceinline__ void ffd_rank(const DevGrid &g, const float *__restrict__ coef, int r,
+                                         const Stencil &s, float u[3], float J[9], int nz0 = 0)
+{
+    ffd_rank_rows<NZ>(LatticeRows{coef, g.nx, g.ny, g.nz}, r, s, u, J, nz0);
+}
+
 // sum_{a,b} Q[3a+b] * d^2 u_a / dx_b dx_c for one rank (the term of dL/dmu through K(mu)),
-// accumulated into h[c] (over the stencil's z indices n0..n1-1). The z and y loops stay rolled (registers); their per-index values are
-// selected.
-__device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
-                                                          const float *__restrict__ coef, int r,
+// accumulated into h[c] (over the stencil's z indices n0..n1-1). The z and y loops stay rolled
+// (registers); their per-index values are selected.
+template <class Rows>
+__device__ __forceinline__ void ffd_rank_hessian_contract(const Rows &rows, int r,
                                                           const Stencil &s, const float Q[9],
                                                           float h[3], int n0 = 0, int n1 = 4)
 {
-    const float *base = coef + (size_t)r * g.nz * g.ny * g.nx * 3;
 #pragma unroll 1
     for (int n = n0; n < n1; ++n) {
         const int kk = pick4(s.kk, n);
@@ -127,7 +155,7 @@ __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
         for (int m = 0; m < 4; ++m) {
             const int jj = pick4(s.jj, m);
             const float By = pick4(s.By, m), dBy = pick4(s.dBy, m), d2By = pick4(s.d2By, m);
-            const float *row = base + ((size_t)(kk * g.ny + jj) * g.nx) * 3;
+            const float *row = rows.row(r, kk, jj);
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
                 const float *d = row + s.ii[l] * 3;
@@ -147,4 +175,54 @@ __device__ __forceinline__ void ffd_rank_hessian_contract(const DevGrid &g,
             }
         }
     }
+}
+
+// The control points that a workgroup's Gaussians reach, staged in LDS (`lds`, at most `cap`
+// floats): every thread passes its Gaussian's stencil (valid false for a thread without one),
+// and the box of the stencils' clamped lattice indices is loaded for every rank, row by row
+// (rows of the box are contiguous runs of the lattice). red: 24 ints of LDS for the reduction.
+// Returns false, for the whole workgroup, when the box needs more than `cap` floats or no thread
+// has a Gaussian (the caller then reads the lattice in device memory). Every thread of the
+// workgroup must call it (it synchronises the workgroup); blockDim.x is a multiple of 64, at most
+// 256.
+__device__ __forceinline__ bool stage_brick(const DevGrid &g, const float *__restrict__ coef,
+                                            const Stencil &s, bool valid, float *lds, int cap,
+                                            int *red, BrickRows &b)
+{
+    int v[6] = {valid ? s.ii[0] : INT_MAX, valid ? s.jj[0] : INT_MAX, valid ? s.kk[0] : INT_MAX,
+                valid ? -s.ii[3] : INT_MAX, valid ? -s.jj[3] : INT_MAX,
+                valid ? -s.kk[3] : INT_MAX};   // minima of the low ends and of minus the high ends
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] = min(v[k], __shfl_xor(v[k], off, 64));
+    const int wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) red[wave * 6 + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        v[k] = red[k];
+        for (int w = 1; w < nwaves; ++w) v[k] = min(v[k], red[w * 6 + k]);
+    }
+    __syncthreads();   // red may be reused after the call
+    if (v[0] == INT_MAX) return false;   // no Gaussian in the workgroup
+    b.b = lds;
+    b.x0 = v[0];
+    b.y0 = v[1];
+    b.z0 = v[2];
+    b.bx = -v[3] - v[0] + 1;
+    b.by = -v[4] - v[1] + 1;
+    b.bz = -v[5] - v[2] + 1;
+    const int rowlen = b.bx * 3, nrows = g.R * b.bz * b.by;
+    if ((long long)rowlen * nrows > cap) return false;
+    for (int e = threadIdx.x; e < rowlen * nrows; e += blockDim.x) {
+        const int row = e / rowlen, off = e - row * rowlen;
+        const int r = row / (b.bz * b.by), zy = row - r * (b.bz * b.by);
+        const int z = zy / b.by, y = zy - z * b.by;
+        lds[e] = coef[((((size_t)r * g.nz + b.z0 + z) * g.ny + b.y0 + y) * g.nx + b.x0) * 3 + off];
+    }
+    __syncthreads();
+    return true;
 }

@@ -92,6 +92,7 @@ static hipError_t fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s)
 // gs = [mu (3); scale (3); quat (4); rho] x N, both in cell order (entry i belongs to Gaussian
 // order[i]). With a per-Gaussian basis (the second ablation of Sec. 4.3: the spatial basis
 // stored per Gaussian instead of interpolated from the lattice), U and V are gathered from it.
+#define FFD_BRICK_FLOATS 8192   // LDS for a workgroup's control points, all ranks (32 KB)
 __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *__restrict__ coef,
                                                        const float *__restrict__ basis,
                                                        int n, const float *__restrict__ mu,
@@ -103,13 +104,16 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
                                                        float *__restrict__ gs)
 {
     // four lanes per Gaussian: lane `part` takes the stencil's z index part, and the four partial
-    // sums are added in a fixed order
+    // sums are added in a fixed order. The control points the workgroup's 64 Gaussians reach
+    // (neighbours in cell order) are staged in LDS first.
+    __shared__ float brick[FFD_BRICK_FLOATS];
+    __shared__ int red[24];
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gt >> 2, part = gt & 3;
-    if (i >= n) return;
-    const size_t src = order[i];
+    const bool valid = i < n;
+    const size_t src = order[valid ? i : 0];
     float *U = uv, *V = uv + (size_t)3 * g.R * n;
-    if (part == 0) {
+    if (valid && part == 0) {
         // the Gaussian's parameters, gathered once into cell order: mu (3), scale (3), quat (4),
         // rho
 #pragma unroll
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
         gs[(size_t)10 * n + i] = rho[src];
     }
     if (basis) {
-        if (part != 0) return;
+        if (!valid || part != 0) return;
         for (int r = 0; r < g.R; ++r) {
             const float *b = basis + (size_t)r * 12 * n + src;
 #pragma unroll
@@ -134,9 +138,13 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
     }
     Stencil st;
     make_stencil(g, mu[src], mu[n + src], mu[2 * n + src], st, false);
+    BrickRows br;
+    const bool staged = stage_brick(g, coef, st, valid, brick, FFD_BRICK_FLOATS, red, br);
+    if (!valid) return;
     for (int r = 0; r < g.R; ++r) {
         float u[3], J[9];
-        ffd_rank<1>(g, coef, r, st, u, J, part);
+        if (staged) ffd_rank_rows<1>(br, r, st, u, J, part);
+        else ffd_rank<1>(g, coef, r, st, u, J, part);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             u[a] += __shfl_xor(u[a], 1, DIGS_WAVE);
@@ -352,9 +360,7 @@ struct TileRect {
         q.w = tx1 - q.tx0 + 1;
         q.h = ty1 - q.ty0 + 1;
         q.R = (tx1 >= q.tx0 && ty1 >= q.ty0) ? q.w * q.h : 0;
-        // (a rectangle of exactly 32 tiles keeps its whole 32-bit mask)
-        q.m = q.R > 32 ? ~0u
-                       : (q.R == 32 ? (uint32_t)r.z : ((uint32_t)r.z & ((1u << q.R) - 1u)));
+        q.m = (uint32_t)r.z;   // the set-up stores it restricted to the rectangle's R tiles
         return q;
     }
     __device__ int count() const { return R > 32 ? R : __popc(m); }
@@ -1650,7 +1656,9 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
     float *__restrict__ g_basis)
 {
     // four lanes per Gaussian: lane `part` takes the stencil's z index part in the second-
-    // derivative term (partial sums added in a fixed order); lane 0 writes the results
+    // derivative term (partial sums added in a fixed order); lane 0 writes the results. (The
+    // lattice is read through the caches here: staging the workgroup's control points in LDS, as
+    // the canonical FFD does, made this kernel slower.)
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gt >> 2, part = gt & 3;
     if (i >= n) return;
@@ -1697,10 +1705,10 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(
             }
         const float mu0[3] = {gpar[i], gpar[(size_t)n + i], gpar[(size_t)2 * n + i]};
         make_stencil(grid, mu0[0], mu0[1], mu0[2], st, true);
+        const LatticeRows lr{coef, grid.nx, grid.ny, grid.nz};
         float hs[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            ffd_rank_hessian_contract(grid, coef, r, st, Q[r], hs, part, part + 1);
+        for (int r = 0; r < NR; ++r) ffd_rank_hessian_contract(lr, r, st, Q[r], hs, part, part + 1);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             hs[a] += __shfl_xor(hs[a], 1, DIGS_WAVE);
@@ -2225,9 +2233,9 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
         e = hipGetLastError();
     }
     if (e != hipSuccess || a.basis) return e;   // (a per-Gaussian basis has no lattice gather)
-    const int npts = a.grid.nx * a.grid.ny * a.grid.nz;
     {
         ProfScope ps(PS_COEF_GRAD, s);
+        const int npts = a.grid.nx * a.grid.ny * a.grid.nz;
         hipLaunchKernelGGL(k_coef_grad<NR>, dim3((npts + 3) / 4), dim3(256), 0, s, a.grid,
                            WS(a, gq, const float *), a.L.gq_stride,
                            WS(a, cell_start, const uint32_t *), g_coef);
