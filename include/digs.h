@@ -86,7 +86,8 @@ typedef struct digs_grid {
 #define DIGS_MAX_SLICES 16
 typedef struct digs_tuning {
     float cull_radius;       /* Mahalanobis cut-off of each Gaussian's footprint (default 5)   */
-    int64_t capacity;        /* (Gaussian, tile) instances per call (default 16*N*T)           */
+    int64_t capacity;        /* (Gaussian, tile) instances per call (default 16*N*T at 16x16
+                                tiles, times 256 / tile pixels for smaller tiles)              */
     int splat_waves;         /* forward splat: waves per tile, 4 (one per 8x8 block, at most as
                                 many as the tile has blocks) or 1 (default 4)                  */
     int slices;              /* workgroups per tile list in the splats, 1..DIGS_MAX_SLICES; 0: by

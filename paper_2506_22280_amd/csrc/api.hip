@@ -91,7 +91,11 @@ DevGrid make_dev_grid(const digs_grid *g)
     return d;
 }
 
-static int64_t default_capacity(int n, int T) { return (int64_t)16 * n * T + 4096; }
+// 16 instances per (view, Gaussian) at 16x16 tiles, in proportion for smaller tiles
+static int64_t default_capacity(int n, int T, int tile_px)
+{
+    return (int64_t)16 * (DIGS_TILE_PX / tile_px) * n * T + 4096;
+}
 
 // Workgroups per tile list when the caller leaves it open: a launch with few (view, tile) items
 // (one view, a small detector) leaves most SIMDs with one wave, so its lists are cut into slices
@@ -138,7 +142,8 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
         L->tpc = (Tp + want - 1) / want;
         L->tchunks = (Tp + L->tpc - 1) / L->tpc;
     }
-    int64_t cap = (tuning && tuning->capacity > 0) ? tuning->capacity : default_capacity(n, T);
+    int64_t cap = (tuning && tuning->capacity > 0) ? tuning->capacity
+                                                   : default_capacity(n, T, tw * th);
     if (cap > 0xFFFFFF00ll) cap = 0xFFFFFF00ll;   // list positions are 32-bit
     L->cap = (size_t)cap;
     const size_t N = (size_t)(n > 0 ? n : 1), TN = (size_t)(T > 0 ? T : 1) * N;

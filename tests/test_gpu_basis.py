@@ -49,16 +49,22 @@ def test_basis_fwd_matches_oracle_and_reduces_to_the_lattice():
     assert max_rel_to_max(same.cpu().numpy(), lat.cpu().numpy()) <= 2e-5
 
 
-def test_basis_bwd_matches_oracle():
-    _print("case: basis-model project_bwd small phantom (2048 Gaussians, 90x75, 4 views)")
+@pytest.mark.parametrize("tile", [None, (32, 8), (8, 8)], ids=["16x16", "32x8", "8x8"])
+def test_basis_bwd_matches_oracle(tile):
+    _print("case: basis-model project_bwd small phantom (2048 Gaussians, 90x75, 4 views), tile %s"
+           % (tile or "16x16",))
     p = synth.small_phantom(n=2048, nviews=4, seed=2)
     t = problem_tensors(p)
     rng = np.random.default_rng(10)
     basis = _basis(p, rng)
     c = rng.normal(0.0, 1.0, (4, p.geom["nv"], p.geom["nu"]))
+    tun = dict(tile_w=tile[0], tile_h=tile[1]) if tile else None
+    ws = _lib.Workspace()
     g = _lib.project_basis_bwd(p.geom, p.grid, dev(basis), t["mu"], t["scale"], t["quat"],
-                               t["rho"], t["angles"], t["w"], dev(c), _lib.Workspace())
+                               t["rho"], t["angles"], t["w"], dev(c), ws, tuning=tun)
     torch.cuda.synchronize()
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0, d
     ref = oracle.project_bwd(p.geom, p.grid, None, p.mu, p.scale, p.quat, p.rho, p.angles, p.w,
                              grad_proj=c.astype(np.float32).astype(np.float64), basis=basis)
     check_grads({k: g[k] for k in ref}, ref)

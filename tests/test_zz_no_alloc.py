@@ -43,6 +43,15 @@ def test_noalloc_forward_equals_workspace_forward_twice():
         assert d["instances"] == rd["instances"] > 0
 
 
+def test_noalloc_forward_with_other_tile_shapes():
+    _print("case: no-allocation forward with 32x8 and 8x8 tiles and 3 list slices (tiny problem)")
+    p = synth.tiny(seed=5, n=2048, nviews=4, det=64)
+    for tun in (dict(tile_w=32, tile_h=8), dict(tile_w=8, tile_h=8, slices=3)):
+        got, ref, d, rd = _both(p, tuning=tun)
+        assert torch.equal(got, ref), tun
+        assert d["overflow"] == 0 and d["instances"] == rd["instances"] > 0
+
+
 def test_noalloc_forward_reports_overflow():
     _print("case: no-allocation forward with an instance capacity of 8: overflow reported")
     p = synth.tiny(seed=3, n=256, nviews=2, det=32)
