@@ -93,6 +93,10 @@ static hipError_t fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s)
 // order[i]). With a per-Gaussian basis (the second ablation of Sec. 4.3: the spatial basis
 // stored per Gaussian instead of interpolated from the lattice), U and V are gathered from it.
 #define FFD_BRICK_FLOATS 8192   // LDS for a workgroup's control points, all ranks (32 KB)
+// Staging pays only when other workgroups hide its extra round trip to memory: calls with fewer
+// Gaussians (a few workgroups per CU) read the lattice through the caches (STAGE false).
+#define FFD_STAGE_MIN_GAUSSIANS 65536
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *__restrict__ coef,
                                                        const float *__restrict__ basis,
                                                        int n, const float *__restrict__ mu,
@@ -106,7 +110,7 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
     // four lanes per Gaussian: lane `part` takes the stencil's z index part, and the four partial
     // sums are added in a fixed order. The control points the workgroup's 64 Gaussians reach
     // (neighbours in cell order) are staged in LDS first.
-    __shared__ float brick[FFD_BRICK_FLOATS];
+    __shared__ float brick[STAGE ? FFD_BRICK_FLOATS : 1];
     __shared__ int red[24];
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gt >> 2, part = gt & 3;
@@ -139,7 +143,8 @@ __global__ __launch_bounds__(256) void k_ffd_canonical(DevGrid g, const float *_
     Stencil st;
     make_stencil(g, mu[src], mu[n + src], mu[2 * n + src], st, false);
     BrickRows br;
-    const bool staged = stage_brick(g, coef, st, valid, brick, FFD_BRICK_FLOATS, red, br);
+    const bool staged =
+        STAGE && stage_brick(g, coef, st, valid, brick, FFD_BRICK_FLOATS, red, br);
     if (!valid) return;
     for (int r = 0; r < g.R; ++r) {
         float u[3], J[9];
@@ -2007,7 +2012,9 @@ hipError_t render_forward_canonical(const RenderArgs &a, hipStream_t s)
     if ((e = cell_sort(a, s)) != hipSuccess) return e;
     {
         ProfScope ps(PS_FFD, s);
-        hipLaunchKernelGGL(k_ffd_canonical, dim3((unsigned)(((size_t)4 * a.n + 255) / 256)),
+        auto kernel = a.n >= FFD_STAGE_MIN_GAUSSIANS ? k_ffd_canonical<true>
+                                                     : k_ffd_canonical<false>;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)(((size_t)4 * a.n + 255) / 256)),
                            dim3(256), 0, s, a.grid,
                            a.coef, a.basis, a.n, a.mu, a.scale, a.quat, a.rho,
                            WS(a, order, const uint32_t *), WS(a, uv, float *), WS(a, gsort, float *));

@@ -115,6 +115,28 @@ def test_project_fwd_full_size_sampled():
     assert err.max() <= 1e-4
 
 
+def test_project_many_gaussians_small_detector():
+    """70,000 Gaussians (above the count from which the canonical FFD stages each workgroup's
+    control points in LDS) on a 32x32 detector, 2 views: every pixel, and the adjoint, against the
+    oracle."""
+    _print("case: 70k Gaussians, 32x32, 2 views: fwd every pixel and bwd against the oracle")
+    p = synth.tiny(seed=61, n=70000, nviews=2, det=32)
+    t = problem_tensors(p)
+    proj, ws = _fwd(p, t)
+    d = ws.diagnostics()
+    assert d["overflow"] == 0 and d["nonfinite"] == 0
+    ref = oracle.project(p.geom, p.grid, *oracle_inputs(p))
+    for k in range(ref.shape[0]):
+        err = max_rel_to_max(proj[k].cpu().numpy(), ref[k])
+        assert err <= 1e-4, (k, err)
+    G = np.random.default_rng(62).normal(0, 1, ref.shape).astype(np.float32)
+    out = _lib.project_bwd(p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"],
+                           t["angles"], t["w"], dev(G), ws, reuse_fwd=True)
+    torch.cuda.synchronize()
+    gref = oracle.project_bwd(p.geom, p.grid, *oracle_inputs(p), grad_proj=G)
+    check_grads({k: out[k] for k in gref}, gref)
+
+
 def test_project_deterministic_and_batch_invariant():
     _print("case: bitwise repeatability; batched equals one view per launch")
     p = synth.small_phantom(seed=3)
