@@ -622,8 +622,7 @@ def main():
         ws_out = warmstart.experiment(n, G["nu"], G["nv"], G["pitch_u"], len(p.angles),
                                       Gd["spacing"][0], list(range(15)), [100, 101, 102],
                                       G["nv"] // 64, G["nu"] // 64, views_per_seed=None,
-                                      epochs=60, log=lambda m: print(m, file=sys.stderr,
-                                                                     flush=True))
+                                      log=lambda m: print(m, file=sys.stderr, flush=True))
         out["speedup_vs_plain"] = {
             "value": ws_out["wall_clock_speedup"],
             "meaning": "plain-fit seconds / warm-started-fit seconds to RMS residual <= 1e-3 of "
