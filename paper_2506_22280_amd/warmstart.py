@@ -2,11 +2,12 @@
 
 Plain fit. For views t with measured projections P_t, find the rank-R weights w_t of the low-rank
 motion model (Sec. 3.3, Eq. 9) that minimise 1/2 ||I(w_t) - P_t||^2, with the Gaussians and the
-lattice fixed, by Levenberg-Marquardt. Each step renders, in one digs_project_fwd launch, every
-active view at its trial weights and at R copies with one weight raised by h; digs_lm_normal_eq
-reduces those images to J^T J, J^T res and res.res per view; the 3x3 (R x R) damped solve and the
-accept/reject logic run on the host in FP64. A view is done when its RMS residual falls to `tol`
-times the RMS of its measured projection.
+lattice fixed, by Levenberg-Marquardt. Each iteration renders, in one digs_project_fwd launch,
+every active view at its trial weights; the views whose trial lowered the residual (and did not
+yet meet the tolerance) are then rendered at R copies with one weight raised by h, and
+digs_lm_normal_eq reduces those images to J^T J, J^T res and res.res per view; the 3x3 (R x R)
+damped solve and the accept/reject logic run on the host in FP64. A view is done when its RMS
+residual falls to `tol` times the RMS of its measured projection.
 
 Warm start. A small MLP maps the view downsampled to 64x64 (block means) plus sin and cos of the
 gantry angle to w_t: 4098 -> 256 -> 256 -> R with ReLU, FP32 master weights, every product on the
@@ -73,9 +74,14 @@ def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_s
     alt [T][R] (host, optional): a second start whose residual the first render also evaluates
     (one more image per view); a view whose alt start leaves the smaller residual continues
     from it instead.
-    Returns (w [T][R] host FP64, steps [T]: LM renders of R + 1 images per view until the view
-    met the tolerance, or max_steps + 1 if it never did, rel [T]: final RMS residual / RMS of the
-    measurement). info, if given, receives "used_alt" [T] (bool)."""
+    Each iteration first renders every active view at its trial weights only; a view whose trial
+    meets the tolerance stops there, a trial that lowers the residual is accepted, and only then
+    are the R raised copies rendered for the Jacobian at the new point (forward differences of
+    step h); a rejected trial keeps the Jacobian and raises the damping.
+    Returns (w [T][R] host FP64, images [T]: images rendered per view until the view met the
+    tolerance (the alt image included), or those of max_steps + 1 iterations if it never did,
+    rel [T]: final RMS residual / RMS of the measurement). info, if given, receives "used_alt"
+    [T] (bool)."""
     T, R = meas.shape[0], scene.R
     npix = meas[0].numel()
     dev = meas.device
@@ -85,71 +91,88 @@ def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_s
     pn = np.sqrt(meas_norm2(meas) / npix)
     target = tol * pn
     hvec = torch.full((R,), h, device=dev)
-    steps = np.full(T, max_steps + 1, dtype=np.int64)
-    rms = np.full(T, np.inf)
+    ones = torch.ones(1, device=dev)
+    images = np.zeros(T, dtype=np.int64)
+    done = np.zeros(T, dtype=bool)
     JtJ = np.zeros((T, R, R)); Jtr = np.zeros((T, R)); rr = np.full(T, np.inf)
     tri = np.triu_indices(R)
     nt = R * (R + 1) // 2
     active = np.arange(T)
     trial = w.copy()
-    for step in range(max_steps + 1):
+
+    def sq_residual(imgs, m):   # sum of squared residuals per image (images [A][nv][nu])
+        return _lib.lm_normal_eq(torch.stack([imgs, imgs], 1), m, ones, 1)[:, 2].double().cpu().numpy()
+
+    for it in range(max_steps + 1):
         if active.size == 0:
             break
         A = active.size
-        # every active view at its trial weights and at the R raised copies (+ the alt start)
-        W = np.repeat(trial[active][:, None, :], R + 1, axis=1)
-        W[:, 1:, :] += h * np.eye(R)[None]
-        W = W.reshape(-1, R)
         idx = torch.as_tensor(active, device=dev)
-        ang = angles[idx].repeat_interleave(R + 1)
-        with_alt = step == 0 and alt is not None
+        m_act = meas[idx].contiguous()
+        # 1. the trial weights of every active view (and at the first iteration the alt start)
+        W = trial[active]
+        ang = angles[idx]
+        with_alt = it == 0 and alt is not None
         if with_alt:
             W = np.concatenate([W, np.asarray(alt, dtype=np.float64)[active]])
-            ang = torch.cat([ang, angles[idx]])
+            ang = torch.cat([ang, ang])
         imgs = scene.render(ang, torch.as_tensor(W, dtype=torch.float32, device=dev))
-        m_act = meas[idx].contiguous()
-        ne = _lib.lm_normal_eq(imgs[:A * (R + 1)], m_act, hvec, R).double().cpu().numpy()
-        if with_alt:
-            a = imgs[A * (R + 1):]
-            r_alt = _lib.lm_normal_eq(torch.stack([a, a], 1), m_act, torch.ones(1, device=dev),
-                                      1)[:, 2].double().cpu().numpy()
+        r2 = sq_residual(imgs[:A], m_act)
+        r2_alt = sq_residual(imgs[A:], m_act) if with_alt else None
+        images[active] += 2 if with_alt else 1
+        base = imgs[:A].clone()          # the image at each view's accepted point
+        accepted = np.zeros(A, dtype=bool)
         for j, t in enumerate(active):
-            Am = np.zeros((R, R)); Am[tri] = ne[j, :nt]; Am = Am + np.triu(Am, 1).T
-            g, r2 = ne[j, nt:nt + R], ne[j, nt + R]
-            if with_alt and r_alt[j] < r2:     # continue from the alt start (Jacobian next)
+            if with_alt and r2_alt[j] < r2[j]:
                 used_alt[t] = True
                 w[t] = np.asarray(alt, dtype=np.float64)[t]
-                rr[t] = np.inf
-                rms[t] = np.sqrt(max(r_alt[j], 0.0) / npix)
-                if rms[t] <= target[t] and steps[t] > max_steps:
-                    steps[t] = step + 1
-                continue
-            if step == 0 or r2 < rr[t]:
-                w[t] = trial[t]; JtJ[t] = Am; Jtr[t] = g; rr[t] = r2
-                if step:
+                rr[t] = r2_alt[j]
+                base[j] = imgs[A + j]
+                accepted[j] = True
+            elif r2[j] < rr[t]:
+                w[t] = trial[t]
+                rr[t] = r2[j]
+                accepted[j] = True
+                if it:
                     lam[t] = max(lam[t] / 3.0, 1e-9)
             else:
                 lam[t] *= 4.0
-            rms[t] = np.sqrt(max(rr[t], 0.0) / npix)
-            if rms[t] <= target[t] and steps[t] > max_steps:
-                steps[t] = step + 1
+            if np.sqrt(max(rr[t], 0.0) / npix) <= target[t]:
+                done[t] = True
+        # 2. the Jacobian at the newly accepted points of the views still open
+        need = [j for j in range(A) if accepted[j] and not done[active[j]]]
+        if need and it < max_steps:
+            nsel = torch.as_tensor(need, device=dev)
+            tj = active[need]
+            Wr = np.repeat(w[tj][:, None, :], R, axis=1) + h * np.eye(R)[None]
+            raised = scene.render(angles[torch.as_tensor(tj, device=dev)].repeat_interleave(R),
+                                  torch.as_tensor(Wr.reshape(-1, R), dtype=torch.float32,
+                                                  device=dev))
+            images[tj] += R
+            stack = torch.cat([base[nsel][:, None], raised.view(len(need), R, *raised.shape[1:])],
+                              1).reshape(-1, *raised.shape[1:])
+            ne = _lib.lm_normal_eq(stack, meas[torch.as_tensor(tj, device=dev)].contiguous(), hvec,
+                                   R).double().cpu().numpy()
+            for k, t in enumerate(tj):
+                Am = np.zeros((R, R)); Am[tri] = ne[k, :nt]; Am = Am + np.triu(Am, 1).T
+                JtJ[t] = Am
+                Jtr[t] = ne[k, nt:nt + R]
+        # 3. the next trial of every view still open (a rejected one: the same point, more damping)
         still = []
         for t in active:
-            if rms[t] <= target[t]:
+            if done[t]:
                 continue
-            if not np.isfinite(rr[t]):            # switched to the alt start: render it fully
+            M = JtJ[t] + lam[t] * np.diag(np.maximum(np.diag(JtJ[t]), 1e-12))
+            try:
+                trial[t] = w[t] + np.linalg.solve(M, -Jtr[t])
+            except np.linalg.LinAlgError:
                 trial[t] = w[t]
-            else:
-                M = JtJ[t] + lam[t] * np.diag(np.maximum(np.diag(JtJ[t]), 1e-12))
-                try:
-                    trial[t] = w[t] + np.linalg.solve(M, -Jtr[t])
-                except np.linalg.LinAlgError:
-                    trial[t] = w[t]
             still.append(t)
         active = np.asarray(still, dtype=np.int64)
     if info is not None:
         info["used_alt"] = used_alt
-    return w, steps, rms / np.maximum(pn, 1e-300)
+    rms = np.sqrt(np.maximum(rr, 0.0) / npix)
+    return w, images, rms / np.maximum(pn, 1e-300)
 
 
 # ------------------------------------------------------------------------------------------------
@@ -265,7 +288,7 @@ def warm_fit(scene: Scene, net: WarmStartNet, angles, meas, w_plain0, fy: int, f
     """The warm-started fit: the network's prediction starts the LM fit, and its first render also
     evaluates the plain start (one more image per view); a view whose plain start leaves the
     smaller residual continues from it (the plain fit is the fallback). Returns
-    (w, steps, rel, seconds, fallbacks) with feature extraction, inference and the whole fit
+    (w, images, rel, seconds, fallbacks) with feature extraction, inference and the whole fit
     inside the timed span."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -273,10 +296,10 @@ def warm_fit(scene: Scene, net: WarmStartNet, angles, meas, w_plain0, fy: int, f
     w_pred = net.predict(X)
     w_plain = np.broadcast_to(np.asarray(w_plain0, dtype=np.float64), w_pred.shape)
     info = {}
-    w, steps, rel = lm_fit(scene, angles, meas, w_pred, alt=w_plain, info=info, **kw)
+    w, images, rel = lm_fit(scene, angles, meas, w_pred, alt=w_plain, info=info, **kw)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    return w, steps, rel, sec, int(info["used_alt"].sum())
+    return w, images, rel, sec, int(info["used_alt"].sum())
 
 
 # ------------------------------------------------------------------------------------------------
@@ -329,7 +352,7 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log("trained on %d pairs in %.1f s; loss %.4f -> %.4f" % (len(W), t_train, hist[0], hist[-1]))
-    res = dict(plain_steps=[], warm_steps=[], plain_s=0.0, warm_s=0.0, plain_conv=0, warm_conv=0,
+    res = dict(plain_images=[], warm_images=[], plain_s=0.0, warm_s=0.0, plain_conv=0, warm_conv=0,
                fallbacks=0, views=0)
     for seed in test_seeds:
         p = synth.lung_phantom("warm_%d" % seed, n, det_u, det_v, pitch, nviews, 3, h_lattice,
@@ -350,23 +373,22 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
             _, sw, rw, sec, fb = warm_fit(scene, net, ang, meas, wmean, fy, fx, tol=tol,
                                           max_steps=max_steps)
             res["warm_s"] += sec
-            res["plain_steps"].append(sp)
-            res["warm_steps"].append(sw)
+            res["plain_images"].append(sp)
+            res["warm_images"].append(sw)
             res["plain_conv"] += int((rp <= tol).sum())
             res["warm_conv"] += int((rw <= tol).sum())
             res["fallbacks"] += fb
             res["views"] += len(idx)
         log("test phantom %d done" % seed)
         del scene
-    ps, ws_ = np.concatenate(res["plain_steps"]), np.concatenate(res["warm_steps"])
-    R = 3
+    ps, ws_ = np.concatenate(res["plain_images"]), np.concatenate(res["warm_images"])
     return {"gaussians": n, "detector": [det_u, det_v], "tolerance": tol,
             "train_pairs": int(len(W)), "label_fit_s": round(t_label, 2),
             "train_s": round(t_train, 2), "loss_first_last": [hist[0], hist[-1]],
             "test_views": res["views"],
-            "plain": {"mean_images_per_view": float((R + 1) * ps.mean()),
+            "plain": {"mean_images_per_view": float(ps.mean()),
                       "converged": res["plain_conv"], "seconds": round(res["plain_s"], 3)},
-            "warm": {"mean_images_per_view": float((R + 1) * ws_.mean() + 1),
+            "warm": {"mean_images_per_view": float(ws_.mean()),
                      "converged": res["warm_conv"], "seconds": round(res["warm_s"], 3),
                      "fallbacks": res["fallbacks"]},
             "wall_clock_speedup": round(res["plain_s"] / max(res["warm_s"], 1e-9), 3)}
