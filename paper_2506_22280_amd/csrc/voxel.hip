@@ -144,14 +144,14 @@ __global__ __launch_bounds__(256) void k_dvf_rows(DevGrid g, const float *__rest
     }
 }
 
-// One workgroup per 64 (x) x 16 (y) x 8 (z) voxel slab, for voxels much finer than the lattice.
+// One workgroup per 64 (x) x 16 (y) x 16 (z) voxel slab, for voxels much finer than the lattice.
 // Stage 0 combines the ranks once for the lattice block the slab needs, C[k][j][i] = sum_r w_r
 // d^r[k][j][i] (each control point read once per slab, not once per z-slice and rank); then, per
 // z-slice, stage 1 applies the z pieces to every lattice column, stage 2 the y pieces per voxel
 // row and stage 3 the x pieces per voxel, whose three components are written once each
 // (coalesced along x). The z, y and x piece weights are computed once per slab.
-#define SLAB_Z 8
-#define SLAB_CMAX 3072   // floats of the rank-combined lattice block (nz * ny * nx * 3)
+#define SLAB_Z 16
+#define SLAB_CMAX 4096   // floats of the rank-combined lattice block (nz * ny * nx * 3)
 
 __global__ __launch_bounds__(256) void k_dvf_slab(DevGrid g, const float *__restrict__ coef,
                                                   const float *__restrict__ w, DevVGrid v,
@@ -291,7 +291,7 @@ extern "C" int digs_dvf_grid(const digs_grid *grid, const float *coef, const flo
     const DevGrid g = make_dev_grid(grid);
     const DevVGrid v = make_dev_vgrid(vg);
     hipStream_t s = (hipStream_t)stream;
-    // the slab kernel's LDS holds the lattice block of a 64 x 16 x 8 voxel slab, the patch
+    // the slab kernel's LDS holds the lattice block of a 64 x 16 x 16 voxel slab, the patch
     // kernel's the lattice columns of a 64 x 16 voxel patch
     const double nLx = (double)(DVF_ROW - 1) * v.sx / g.hx + 5.0;
     const double nJy = (double)(DVF_ROWS - 1) * v.sy / g.hy + 5.0;
