@@ -633,6 +633,7 @@ def main():
             "test_views": ws_out["test_views"], "train_pairs": ws_out["train_pairs"],
             "fallbacks": ws_out["warm"]["fallbacks"],
             "fallback_share": round(ws_out["warm"]["fallbacks"] / max(ws_out["test_views"], 1), 4),
+            "plain_start_checked_above_rel_residual": round(ws_out["warm"]["alt_above"], 5),
             "label_fit_s": ws_out["label_fit_s"], "train_s": ws_out["train_s"]}
     if not args.no_cpu_baseline:
         params = tuple(est[k].double().cpu().numpy() for k in ("mu", "scale", "quat", "rho")) + (

@@ -68,11 +68,13 @@ def meas_norm2(meas):
     return _lib.lm_normal_eq(zeros, meas, h, 1)[:, 2].double().cpu().numpy()
 
 
-def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_steps: int = 30,
-           h: float = 0.05, lam0: float = 1e-3, info: dict | None = None):
+def lm_fit(scene: Scene, angles, meas, start, alt=None, alt_above: float | None = None,
+           tol: float = 1e-3, max_steps: int = 30, h: float = 0.05, lam0: float = 1e-3,
+           info: dict | None = None):
     """Fit w for every view. angles [T] and meas [T][nv][nu] on the device; start [T][R] (host).
-    alt [T][R] (host, optional): a second start whose residual the first render also evaluates
-    (one more image per view); a view whose alt start leaves the smaller residual continues
+    alt [T][R] (host, optional): a second start, rendered once the start's residual is known for
+    the views whose relative residual at the start is at least alt_above (every view if None;
+    one more image per such view); a view whose alt start leaves the smaller residual continues
     from it instead.
     Each iteration first renders every active view at its trial weights only; a view whose trial
     meets the tolerance stops there, a trial that lowers the residual is accepted, and only then
@@ -81,7 +83,7 @@ def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_s
     Returns (w [T][R] host FP64, images [T]: images rendered per view until the view met the
     tolerance (the alt image included), or those of max_steps + 1 iterations if it never did,
     rel [T]: final RMS residual / RMS of the measurement). info, if given, receives "used_alt"
-    [T] (bool)."""
+    [T] (bool) and "rel_start" [T] (the relative residual at the start)."""
     T, R = meas.shape[0], scene.R
     npix = meas[0].numel()
     dev = meas.device
@@ -99,6 +101,7 @@ def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_s
     nt = R * (R + 1) // 2
     active = np.arange(T)
     trial = w.copy()
+    rel_start = np.full(T, np.inf)
 
     def sq_residual(imgs, m):   # sum of squared residuals per image (images [A][nv][nu])
         return _lib.lm_normal_eq(torch.stack([imgs, imgs], 1), m, ones, 1)[:, 2].double().cpu().numpy()
@@ -109,25 +112,33 @@ def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_s
         A = active.size
         idx = torch.as_tensor(active, device=dev)
         m_act = meas[idx].contiguous()
-        # 1. the trial weights of every active view (and at the first iteration the alt start)
-        W = trial[active]
-        ang = angles[idx]
-        with_alt = it == 0 and alt is not None
-        if with_alt:
-            W = np.concatenate([W, np.asarray(alt, dtype=np.float64)[active]])
-            ang = torch.cat([ang, ang])
-        imgs = scene.render(ang, torch.as_tensor(W, dtype=torch.float32, device=dev))
-        r2 = sq_residual(imgs[:A], m_act)
-        r2_alt = sq_residual(imgs[A:], m_act) if with_alt else None
-        images[active] += 2 if with_alt else 1
-        base = imgs[:A].clone()          # the image at each view's accepted point
+        # 1. the trial weights of every active view (at the first iteration, then the alt start
+        # of the views whose start left a relative residual of at least alt_above)
+        imgs = scene.render(angles[idx], torch.as_tensor(trial[active], dtype=torch.float32,
+                                                         device=dev))
+        r2 = sq_residual(imgs, m_act)
+        images[active] += 1
+        base = imgs.clone()              # the image at each view's accepted point
+        r2_alt = {}
+        if it == 0:
+            rel_start = np.sqrt(np.maximum(r2, 0.0) / npix) / np.maximum(pn, 1e-300)
+            if alt is not None:
+                sel = [j for j in range(A) if alt_above is None or rel_start[j] >= alt_above]
+                if sel:
+                    ta = active[sel]
+                    aimg = scene.render(angles[torch.as_tensor(ta, device=dev)],
+                                        torch.as_tensor(np.asarray(alt, dtype=np.float64)[ta],
+                                                        dtype=torch.float32, device=dev))
+                    ra = sq_residual(aimg, meas[torch.as_tensor(ta, device=dev)].contiguous())
+                    images[ta] += 1
+                    r2_alt = {j: (k, ra[k]) for k, j in enumerate(sel)}
         accepted = np.zeros(A, dtype=bool)
         for j, t in enumerate(active):
-            if with_alt and r2_alt[j] < r2[j]:
+            if j in r2_alt and r2_alt[j][1] < r2[j]:
                 used_alt[t] = True
                 w[t] = np.asarray(alt, dtype=np.float64)[t]
-                rr[t] = r2_alt[j]
-                base[j] = imgs[A + j]
+                rr[t] = r2_alt[j][1]
+                base[j] = aimg[r2_alt[j][0]]
                 accepted[j] = True
             elif r2[j] < rr[t]:
                 w[t] = trial[t]
@@ -171,6 +182,7 @@ def lm_fit(scene: Scene, angles, meas, start, alt=None, tol: float = 1e-3, max_s
         active = np.asarray(still, dtype=np.int64)
     if info is not None:
         info["used_alt"] = used_alt
+        info["rel_start"] = rel_start
     rms = np.sqrt(np.maximum(rr, 0.0) / npix)
     return w, images, rms / np.maximum(pn, 1e-300)
 
@@ -284,19 +296,21 @@ def raw_features(proj, angles, fy: int, fx: int):
     return _lib.downsample(proj, fy, fx, angles=angles)
 
 
-def warm_fit(scene: Scene, net: WarmStartNet, angles, meas, w_plain0, fy: int, fx: int, **kw):
-    """The warm-started fit: the network's prediction starts the LM fit, and its first render also
-    evaluates the plain start (one more image per view); a view whose plain start leaves the
-    smaller residual continues from it (the plain fit is the fallback). Returns
-    (w, images, rel, seconds, fallbacks) with feature extraction, inference and the whole fit
-    inside the timed span."""
+def warm_fit(scene: Scene, net: WarmStartNet, angles, meas, w_plain0, fy: int, fx: int,
+             alt_above: float | None = None, **kw):
+    """The warm-started fit: the network's prediction starts the LM fit; the views whose predicted
+    start leaves a relative residual of at least alt_above (every view if None) also render the
+    plain start (one more image per such view), and a view whose plain start leaves the smaller
+    residual continues from it (the plain fit is the fallback). Returns (w, images, rel, seconds,
+    fallbacks) with feature extraction, inference and the whole fit inside the timed span."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     X = net.features(meas, angles, fy, fx)
     w_pred = net.predict(X)
     w_plain = np.broadcast_to(np.asarray(w_plain0, dtype=np.float64), w_pred.shape)
     info = {}
-    w, images, rel = lm_fit(scene, angles, meas, w_pred, alt=w_plain, info=info, **kw)
+    w, images, rel = lm_fit(scene, angles, meas, w_pred, alt=w_plain, alt_above=alt_above,
+                            info=info, **kw)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     return w, images, rel, sec, int(info["used_alt"].sum())
@@ -316,7 +330,7 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
     epochs of 128 with the floor at 1x). Returns a summary dict."""
     from . import synth
     rng = np.random.default_rng(12345)
-    Xs, Ws, wmean = [], [], None
+    Xs, Ws, wmean, rel_plain = [], [], None, []
     t_label = 0.0
     for seed in train_seeds:
         p = synth.lung_phantom("warm_%d" % seed, n, det_u, det_v, pitch, nviews, 3, h_lattice,
@@ -333,10 +347,12 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
             meas = scene.render(ang, torch.as_tensor(p.w[idx], device="cuda")).clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            info = {}
             w, steps, rel = lm_fit(scene, ang, meas, np.tile(wmean, (len(idx), 1)), tol=tol,
-                                   max_steps=max_steps)
+                                   max_steps=max_steps, info=info)
             torch.cuda.synchronize()
             t_label += time.perf_counter() - t0
+            rel_plain.append(info["rel_start"])
             ok = rel <= tol
             conv += int(ok.sum())
             Xs.append(raw_features(meas, ang, fy, fx)[torch.as_tensor(ok, device="cuda")])
@@ -344,6 +360,10 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
         log("train phantom %d: %d/%d plain fits converged" % (seed, conv, len(views)))
         del scene
     X = torch.cat(Xs).contiguous()
+    # a warm-started view also renders the plain start only if its predicted start leaves a
+    # relative residual above the plain start's 5th percentile over the training views (below
+    # it the plain start is very unlikely to be the better one)
+    alt_above = float(np.percentile(np.concatenate(rel_plain), 5.0))
     W = np.concatenate(Ws)
     net = WarmStartNet(X.shape[1], 3, 256, seed=0)
     net.std_floor = std_floor
@@ -370,8 +390,8 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
                                max_steps=max_steps)
             torch.cuda.synchronize()
             res["plain_s"] += time.perf_counter() - t0
-            _, sw, rw, sec, fb = warm_fit(scene, net, ang, meas, wmean, fy, fx, tol=tol,
-                                          max_steps=max_steps)
+            _, sw, rw, sec, fb = warm_fit(scene, net, ang, meas, wmean, fy, fx,
+                                          alt_above=alt_above, tol=tol, max_steps=max_steps)
             res["warm_s"] += sec
             res["plain_images"].append(sp)
             res["warm_images"].append(sw)
@@ -388,7 +408,7 @@ def experiment(n: int, det_u: int, det_v: int, pitch: float, nviews: int, h_latt
             "test_views": res["views"],
             "plain": {"mean_images_per_view": float(ps.mean()),
                       "converged": res["plain_conv"], "seconds": round(res["plain_s"], 3)},
-            "warm": {"mean_images_per_view": float(ws_.mean()),
+            "warm": {"mean_images_per_view": float(ws_.mean()), "alt_above": alt_above,
                      "converged": res["warm_conv"], "seconds": round(res["warm_s"], 3),
                      "fallbacks": res["fallbacks"]},
             "wall_clock_speedup": round(res["plain_s"] / max(res["warm_s"], 1e-9), 3)}
