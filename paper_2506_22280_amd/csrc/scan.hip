@@ -2,8 +2,9 @@
 //
 // Used for the (projection, tile, Gaussian-block) instance counts of the tile binning, the
 // per-Gaussian instance offsets, and the digit histograms of the cell sort. Each workgroup
-// scans 2048 elements (256 threads x 8 consecutive elements); the block totals are scanned
-// recursively and added back.
+// scans 2048 elements (256 threads x 8 consecutive elements). With at most 2048 blocks, a
+// second launch adds to each block the sum of the block totals before it (each workgroup sums
+// them itself); with more, the block totals are scanned recursively and added back.
 #include "kernels.h"
 
 #define SCAN_THREADS 256
@@ -63,6 +64,34 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(uint32_t *__restrict_
     }
 }
 
+// Adds to block b of data the sum of bsum[0..b) (b < SCAN_BLOCK: one pass over at most 2048
+// totals per workgroup, summed in a fixed order).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add_prefix(uint32_t *__restrict__ data,
+                                                                  size_t n,
+                                                                  const uint32_t *__restrict__ bsum)
+{
+    __shared__ uint32_t wave_tot[SCAN_THREADS / DIGS_WAVE];
+    const int b = blockIdx.x;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        const int i = (int)threadIdx.x * SCAN_PER_THREAD + k;
+        if (i < b) v += bsum[i];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, DIGS_WAVE);
+    if (lane_id() == 0) wave_tot[threadIdx.x / DIGS_WAVE] = v;
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / DIGS_WAVE; ++w) add += wave_tot[w];
+    const size_t base = (size_t)b * SCAN_BLOCK;
+    for (int k = threadIdx.x; k < SCAN_BLOCK; k += SCAN_THREADS) {
+        const size_t i = base + k;
+        if (i < n) data[i] += add;
+    }
+}
+
 size_t scan_scratch_elems(size_t n)
 {
     size_t total = 0;
@@ -81,6 +110,11 @@ hipError_t launch_exclusive_scan(uint32_t *data, size_t n, uint32_t *scratch, hi
                        nb > 1 ? scratch : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nb == 1) return e;
+    if (nb <= SCAN_BLOCK) {
+        hipLaunchKernelGGL(k_scan_add_prefix, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data,
+                           n, (const uint32_t *)scratch);
+        return hipGetLastError();
+    }
     e = launch_exclusive_scan(scratch, nb, scratch + nb, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n,
