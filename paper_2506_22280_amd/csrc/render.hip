@@ -1020,12 +1020,16 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // two chunks in turn; once the pairs of a chunk are all evaluated (by the end of the next chunk's
 // step, with a partial group if no full one forms), its entries are written as the instances'
 // partials, at each instance's slot in Gaussian-major order (so that the per-Gaussian reduction
-// reads each Gaussian's partials contiguously):
-//  0 S_amp = sum g r 2^x      (dL/damp)
-//  1 S_Euu, 2 S_Euv, 3 S_Evv  sum A_E du^2, du dv, dv^2   (A_E = dL/dE, E natural)
-//  4 S_quu, 5 S_quv, 6 S_qvv  sum A_q du^2, du dv, dv^2   (A_q = dL/dq)
-//  7 S_qu, 8 S_qv, 9 S_q      sum A_q du, dv, 1
-//  10 S_Eu, 11 S_Ev           sum A_E du, dv
+// reads each Gaussian's partials contiguously). Per pixel, with a = g r 2^x r^2 (EWA: g 2^x),
+// dL/dE = -amp/2 a and dL/dq = -amp/2 a (1 + 2 ln2 x); the partial holds the sums without the
+// factor -amp/2, which is the same for every pixel of a (view, Gaussian) and is applied once by
+// the adjoint of the set-up, which also forms the dL/dq sums from those of a and a x:
+//  0 sum g r 2^x  (dL/damp)
+//  1, 2, 3    sum a du^2, a du dv, a dv^2
+//  4, 5, 6    sum a x du^2, a x du dv, a x dv^2  (exact model only; EWA: 0)
+//  7, 8       sum a x du, a x dv                  (exact only)
+//  9          sum a (1 + 2 ln2 x)                 (exact only)
+//  10, 11     sum a du, a dv
 // dL/dI of the tile in LDS: rows of tile_w + 2 floats (18 for 16-pixel rows)
 #define GPX_FLOATS 320              // the largest tile's rows: 32 x (8 + 2) or 16 x 18 or 8 x 34
 #define BWD_QUEUE (5 * DIGS_WAVE)   // carried (< 64) + one chunk's pairs (<= 256)
@@ -1034,6 +1038,7 @@ struct BwdShared {
     uint32_t pairs[4][2][BWD_QUEUE];       // (entry slot << 3) | (half << 2) | block
     uint32_t gid[4][2 * DIGS_WAVE];        // Gaussian of each entry slot
     float accS[4][2 * DIGS_WAVE][13];      // moment sums of each entry slot
+    int pend[2][4];                        // each wave's pairs left at the end of the tile
 };
 
 // Evaluates queued pairs [j0, j0 + cnt) of the wave (cnt <= 64), one per lane, over NROWS rows of
@@ -1070,14 +1075,14 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     const float du0 = (float)(tx0 + lbx) - r0.x, dv0 = (float)(ty0 + lby) - r0.y;
     const float Cq = r1.w, CE = r0.z, Gvv = fabsf(r2.y);
     const float s1 = fmaf(2.0f, du0, 1.0f), t1 = fmaf(2.0f, dv0, 1.0f);
-    // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2, applied at the end), the
+    // Per pixel, with a = g r 2^x r^2 (dL/dE up to the factor -amp/2), the
     // lane accumulates a and a x weighted by 1, c and c^2 (c = 0..7, the column inside the block,
     // a compile-time constant) over all its rows. The row moments come from prefix sums: with P_r
     // the sum through row r, sum_r r c_r = (R-1) P_{R-1} - sum_{r<R-1} P_r and
     // sum_r r^2 c_r = (R-1)^2 P_{R-1} - sum_{r<R-1} (2r+1) P_r, so a row costs three adds per
     // accumulated quantity; dv = dv0 + r and the column offset du0 are applied at the end. dL/dq
     // (up to the same factor) is b = a (1 + 2 ln2 x): its moments are those of a plus 2 ln2 times
-    // those of a x. Each row starts from q and E at its first pixel, carried down the rows by
+    // those of a x (formed by the adjoint of the set-up, except the constant one). Each row starts from q and E at its first pixel, carried down the rows by
     // their differences (q and E are quadratic in du and dv).
     const float ddq = 2.0f * Cq, dde = 2.0f * CE;
     float er = fmaf(du0, fmaf(CE, du0, r0.w * dv0), r1.x * (dv0 * dv0));
@@ -1114,14 +1119,13 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         const float R0 = fmaf(Rm, e0, -Q0), R1 = fmaf(Rm, e1, -Q1), RR0 = fmaf(Rm * Rm, e0, -W0);
         const float EV0 = fmaf(dv0, e0, R0), EV1 = fmaf(dv0, e1, R1);
         const float EW0 = fmaf(dv0, fmaf(dv0, e0, 2.0f * R0), RR0);
-        const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
         S[0] = e0;
-        S[1] = cA * fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);
-        S[2] = cA * fmaf(du0, EV0, EV1);
-        S[3] = cA * EW0;
+        S[1] = fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);
+        S[2] = fmaf(du0, EV0, EV1);
+        S[3] = EW0;
         S[4] = S[5] = S[6] = S[7] = S[8] = S[9] = 0.0f;
-        S[10] = cA * fmaf(du0, e0, e1);
-        S[11] = cA * EV0;
+        S[10] = fmaf(du0, e0, e1);
+        S[11] = EV0;
     } else {
         const float Bq0 = fmaf(r2.x, dv0, r1.y);
         float qr = fmaf(du0, fmaf(Cq, du0, Bq0), fmaf(dv0, fmaf(Gvv, dv0, r1.z), 1.0f));
@@ -1181,23 +1185,19 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         const float EW0 = fmaf(dv0, fmaf(dv0, e0, 2.0f * Re0), RRe0);
         const float XV0 = fmaf(dv0, x0, Rx0), XV1 = fmaf(dv0, x1, Rx1);
         const float XW0 = fmaf(dv0, fmaf(dv0, x0, 2.0f * Rx0), RRx0);
-        const float k2 = 2.0f * LN2;
-        const float Q0 = fmaf(k2, x0, e0), Q1 = fmaf(k2, x1, e1), Q2 = fmaf(k2, x2, e2);
-        const float QV0 = fmaf(k2, XV0, EV0), QV1 = fmaf(k2, XV1, EV1), QW0 = fmaf(k2, XW0, EW0);
-        // the twelve moment sums (du = du0 + c), with the factor -amp/2
-        const float cA = -0.5f * copysignf(exp2f(r2.z), r2.y);
+        // the twelve partial sums (du = du0 + c)
         S[0] = S0;
-        S[1] = cA * fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);    // sum dE du^2
-        S[2] = cA * fmaf(du0, EV0, EV1);                        // sum dE du dv
-        S[3] = cA * EW0;                                        // sum dE dv^2
-        S[4] = cA * fmaf(du0, fmaf(du0, Q0, 2.0f * Q1), Q2);    // sum dq du^2
-        S[5] = cA * fmaf(du0, QV0, QV1);                        // sum dq du dv
-        S[6] = cA * QW0;                                        // sum dq dv^2
-        S[7] = cA * fmaf(du0, Q0, Q1);                          // sum dq du
-        S[8] = cA * QV0;                                        // sum dq dv
-        S[9] = cA * Q0;                                         // sum dq
-        S[10] = cA * fmaf(du0, e0, e1);                         // sum dE du
-        S[11] = cA * EV0;                                       // sum dE dv
+        S[1] = fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);   // sum a du^2
+        S[2] = fmaf(du0, EV0, EV1);                        // sum a du dv
+        S[3] = EW0;                                        // sum a dv^2
+        S[4] = fmaf(du0, fmaf(du0, x0, 2.0f * x1), x2);   // sum a x du^2
+        S[5] = fmaf(du0, XV0, XV1);                        // sum a x du dv
+        S[6] = XW0;                                        // sum a x dv^2
+        S[7] = fmaf(du0, x0, x1);                          // sum a x du
+        S[8] = XV0;                                        // sum a x dv
+        S[9] = fmaf(2.0f * LN2, x0, e0);                   // sum a (1 + 2 ln2 x)
+        S[10] = fmaf(du0, e0, e1);                         // sum a du
+        S[11] = EV0;                                       // sum a dv
     }
     // add into the entry's slot, one block at a time (an entry has at most one pair per block)
 #pragma unroll
@@ -1329,8 +1329,44 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         prev_valid = valid;
         prev_g = g;
     }
-    if (pend0 > 0) splat_bwd_group<EWA, 8, TW, NB>(rt, pq0, gid, accS, gpx, 0, pend0, tx0, ty0);
-    if (pend1 > 0) splat_bwd_group<EWA, 4, TW, NB>(rt, pq1, gid, accS, gpx, 0, pend1, tx0, ty0);
+    // The waves' last pairs (fewer than 64 per queue each, all of their last chunk) are pooled in
+    // wave order and evaluated by wave 0 in fewer, fuller groups; the pooled pairs name their
+    // entry slots across the four waves (slot + 128 wave), and a single wave evaluates them all,
+    // so no two groups that add into one slot run at once.
+    if (lane == 0) {
+        sh.pend[0][wave] = pend0;
+        sh.pend[1][wave] = pend1;
+    }
+    const uint32_t wslot = (uint32_t)(wave * 2 * DIGS_WAVE) << 3;
+    const uint32_t keep0 = lane < pend0 ? pq0[lane] + wslot : 0u;
+    const uint32_t keep1 = lane < pend1 ? pq1[lane] + wslot : 0u;
+    __syncthreads();
+    int o0 = 0, o1 = 0, n0 = 0, n1 = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int c0 = sh.pend[0][w], c1 = sh.pend[1][w];
+        if (w < wave) {
+            o0 += c0;
+            o1 += c1;
+        }
+        n0 += c0;
+        n1 += c1;
+    }
+    uint32_t *pool0 = sh.pairs[0][0], *pool1 = sh.pairs[0][1];   // 4 x 63 < BWD_QUEUE entries
+    if (lane < pend0) pool0[o0 + lane] = keep0;
+    if (lane < pend1) pool1[o1 + lane] = keep1;
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll 1
+        for (int j = 0; j < n0; j += DIGS_WAVE)
+            splat_bwd_group<EWA, 8, TW, NB>(rt, pool0, sh.gid[0], sh.accS[0], gpx, j,
+                                            min(DIGS_WAVE, n0 - j), tx0, ty0);
+#pragma unroll 1
+        for (int j = 0; j < n1; j += DIGS_WAVE)
+            splat_bwd_group<EWA, 4, TW, NB>(rt, pool1, sh.gid[0], sh.accS[0], gpx, j,
+                                            min(DIGS_WAVE, n1 - j), tx0, ty0);
+    }
+    __syncthreads();
     if (it > 0 && prev_valid)
         splat_bwd_write(n, t, tx, ty, prev_g, accS[((it - 1) & 1) * DIGS_WAVE + lane], cap, rect,
                         goff, part);
@@ -1492,6 +1528,26 @@ __global__ __launch_bounds__(256, NR <= 3 ? 3 : 1) void k_tn_bwd(
             SetupFwd f;
             setup_forward<NR>(G, mu0, inv_s, Rm, U, V, wt, rh, vt, f);
             float out[TN_FIELDS];
+            // the moment sums of dL/dE and dL/dq: the partials' sums of a, a x times -amp/2 (the
+            // record's amplitude), dL/dq's from a (1 + 2 ln2 x)
+            {
+                const float cA = -0.5f * (f.amp * f.ee), k2 = 2.0f * LN2;
+                const float quu = fmaf(k2, S[4], S[1]), quv = fmaf(k2, S[5], S[2]);
+                const float qvv = fmaf(k2, S[6], S[3]), qu = fmaf(k2, S[7], S[10]);
+                const float qv = fmaf(k2, S[8], S[11]);
+                S[4] = cA * quu;
+                S[5] = cA * quv;
+                S[6] = cA * qvv;
+                S[7] = cA * qu;
+                S[8] = cA * qv;
+                S[9] *= cA;
+                S[1] *= cA;
+                S[2] *= cA;
+                S[3] *= cA;
+                S[10] *= cA;
+                S[11] *= cA;
+                if (G.ewa) S[4] = S[5] = S[6] = S[7] = S[8] = S[9] = 0.0f;
+            }
             // record gradients from the moment sums
             const float gHuu = S[1], gHuv = 2.0f * S[2], gHvv = S[3];
             // (EWA: g and G are the constant zero, and the record's amplitude is amp |e*|)
