@@ -20,16 +20,24 @@
 // ITEMS: items per workgroup (DIGS_BIN_ITEMS, or DIGS_BIN_ITEMS_SMALL for launches with few
 // workgroups); each wave takes ITEMS / BIN_WAVES of them, 64 per step
 
-// lanes whose key equals this lane's key (among active lanes)
+// lanes whose key equals this lane's key (among active lanes), from the ballots of its bits. A bit
+// that all active lanes share (the usual case for the high bits of nearby keys) selects nothing
+// and is skipped (a uniform branch on its ballot).
 __device__ __forceinline__ unsigned long long wave_match(unsigned key, bool active, int nbits)
 {
-    unsigned long long m = __ballot(active);
+    const unsigned long long act = __ballot(active);
+    unsigned mlo = (unsigned)act, mhi = (unsigned)(act >> 32);
     for (int b = 0; b < nbits; ++b) {
-        const bool bit = (key >> b) & 1u;
-        const unsigned long long ones = __ballot(active && bit);
-        m &= bit ? ones : ~ones;
+        const unsigned bit = (key >> b) & 1u;
+        const unsigned long long ones = __ballot(bit != 0u) & act;
+        if (ones != 0ull && ones != act) {
+            asm volatile("");   // keeps this a (uniform) branch rather than a select
+            const unsigned nb = bit - 1u;   // lanes with the bit keep ones, the others ~ones
+            mlo &= (unsigned)ones ^ nb;
+            mhi &= (unsigned)(ones >> 32) ^ nb;
+        }
     }
-    return m;
+    return ((unsigned long long)mhi << 32) | mlo;
 }
 
 template <class Src, int ITEMS>
