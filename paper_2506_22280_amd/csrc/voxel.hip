@@ -138,9 +138,9 @@ __global__ __launch_bounds__(256) void k_dvf_rows(DevGrid g, const float *__rest
 #pragma unroll
             for (int a = 0; a < 3; ++a) u[a] = fmaf(Bx[l], L[r][li[l]][a], u[a]);
         const size_t o = ((size_t)z * v.ny + y) * v.nx + x;
-        dvf[o] = u[0];
-        dvf[plane + o] = u[1];
-        dvf[2 * plane + o] = u[2];
+        __builtin_nontemporal_store(u[0], dvf + o);   // streaming stores: written once
+        __builtin_nontemporal_store(u[1], dvf + plane + o);
+        __builtin_nontemporal_store(u[2], dvf + 2 * plane + o);
     }
 }
 
@@ -253,9 +253,10 @@ __global__ __launch_bounds__(256) void k_dvf_slab(DevGrid g, const float *__rest
                     u[2] = fmaf(Bx[l], q.z, u[2]);
                 }
                 const size_t o = ((size_t)z * v.ny + y) * v.nx + x;
-                dvf[o] = u[0];
-                dvf[plane + o] = u[1];
-                dvf[2 * plane + o] = u[2];
+                // streaming stores: the field is written once and not read back here
+                __builtin_nontemporal_store(u[0], dvf + o);
+                __builtin_nontemporal_store(u[1], dvf + plane + o);
+                __builtin_nontemporal_store(u[2], dvf + 2 * plane + o);
             }
         }
     }
@@ -279,9 +280,9 @@ __global__ __launch_bounds__(256) void k_dvf_points(DevGrid g, const float *__re
         ffd_rank(g, coef, rk, st, u, J);
         for (int a = 0; a < 3; ++a) acc[a] = fmaf(w[rk], u[a], acc[a]);
     }
-    dvf[o] = acc[0];
-    dvf[plane + o] = acc[1];
-    dvf[2 * plane + o] = acc[2];
+    __builtin_nontemporal_store(acc[0], dvf + o);   // streaming stores: written once
+    __builtin_nontemporal_store(acc[1], dvf + plane + o);
+    __builtin_nontemporal_store(acc[2], dvf + 2 * plane + o);
 }
 
 extern "C" int digs_dvf_grid(const digs_grid *grid, const float *coef, const float *w,
