@@ -495,12 +495,17 @@ def main():
     if resized:                      # the capacity grew: warm the re-captured graphs up again
         for k in range(args.warmup):
             step(k)
+    # HIP events between the steps (on the stream the plan replays on) give the per-step spread
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    evs[0].record()
     for k in range(args.steps):
         step(args.warmup + k)
+        evs[k + 1].record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    per_step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
     diag, resized = plan.check()
     if resized or diag["overflow"] or diag["nonfinite"]:
         raise SystemExit("diagnostics report a problem in the timed steps: %s" % diag)
@@ -558,6 +563,11 @@ def main():
                                   "views, rank-3 FFD on 29^3 (10 mm)",
                       "global_batch": B, "gaussians": n, "detector": [G["nu"], G["nv"]],
                       "parallelism": "single GPU"}}
+    out["ms_per_step_events"] = {
+        "median": round(float(np.median(per_step_ms)), 3),
+        "p10": round(float(np.percentile(per_step_ms, 10)), 3),
+        "p90": round(float(np.percentile(per_step_ms, 90)), 3),
+        "meaning": "HIP events between the timed steps on the plan's stream"}
     out["sources_sha256"] = sources_digest()
     out["tuning"] = {"chosen": {k: tuning[k] for k in ("tile_w", "tile_h", "splat_waves",
                                                        "persistent", "capacity", "slices")},

@@ -172,6 +172,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->scratch = take(sizeof(uint32_t) * sc);
     L->list = take(sizeof(uint32_t) * L->cap);
     const size_t bwd = fwd_only ? 0 : 1;   // the backward's arrays
+    L->goff = take(bwd * sizeof(uint32_t) * TN);
     L->part = take(bwd * sizeof(float) * DIGS_PART_FLOATS * L->cap);
     L->gwpart = take(bwd * sizeof(float) * (size_t)(T > 0 ? T : 1) * grid->R * nparts);
     L->keys_a = take(sizeof(uint32_t) * N);

@@ -12,11 +12,12 @@ struct WsLayout {
     size_t gsort;      // [11][N] f32: mu, scale, quat, rho of the Gaussians in cell order
     size_t rec;        // [T][N][16] f32 projected records
     size_t rect;       // [T][N] int4 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16) and instance mask
-    size_t gcount;     // [T][N] u32 instances per (t,n), scanned in place to instance offsets
+    size_t gcount;     // [T][N] u32 instances per (t,n) (the forward's set-up)
+    size_t goff;       // [T][N] u32 instance offsets: exclusive scan of gcount (the backward's)
     size_t cnt;        // [T][ntiles][nblk] u32 per-block tile counts, scanned in place
     size_t scratch;    // scan block sums
     size_t list;       // [cap] u32 Gaussian index of each instance, grouped by (t, tile)
-    size_t part;       // [cap][12] f32 backward partial sums, instance (t,n,k) at gcount[t][n]+k
+    size_t part;       // [cap][12] f32 backward partial sums, instance (t,n,k) at goff[t][n]+k
     size_t gwpart;     // [T][R][4*ceil(N/256)] f32 per-wave partial sums of dL/dw
     size_t keys_a, vals_a, keys_b, vals_b;  // [N] u32 cell sort ping-pong
     size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
@@ -46,7 +47,9 @@ DevGrid make_dev_grid(const digs_grid *g);
 
 // scan.hip
 size_t scan_scratch_elems(size_t n);
-hipError_t launch_exclusive_scan(uint32_t *data, size_t n, uint32_t *scratch, hipStream_t s);
+// exclusive prefix sum of src (default: data itself) into data
+hipError_t launch_exclusive_scan(uint32_t *data, size_t n, uint32_t *scratch, hipStream_t s,
+                                 const uint32_t *src = nullptr);
 
 // ffd.hip
 hipError_t launch_ffd_eval(const DevGrid &g, const float *coef, int n, const float *x, int T,

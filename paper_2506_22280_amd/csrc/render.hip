@@ -2126,12 +2126,8 @@ hipError_t render_forward_views(const RenderArgs &a, hipStream_t s)
     }
     if (e != hipSuccess) return e;
     uint32_t *scratch = WS(a, scratch, uint32_t *);
-    // per-(t,n) instance offsets (Gaussian-major), then the tile lists
-    {
-        ProfScope ps(PS_SCAN, s);
-        e = launch_exclusive_scan(WS(a, gcount, uint32_t *), (size_t)a.T * a.n, scratch, s);
-    }
-    if (e != hipSuccess) return e;
+    // the tile lists (the per-(t,n) instance offsets, which only the backward needs, are its
+    // first step)
     const int tw = a.geom.tile_w, th = a.geom.tile_h;
     if (tw == 16 && th == 16) e = bin_tiles<16, 16>(a, cnt, cnt_elems, scratch, s);
     else if (tw == 32) e = bin_tiles<32, 8>(a, cnt, cnt_elems, scratch, s);
@@ -2272,7 +2268,7 @@ static hipError_t backward_dispatch(const RenderArgs &a, float *g_mu, float *g_s
         hipLaunchKernelGGL(k_tn_bwd<NR>, dim3(nb, a.L.tchunks), dim3(256), 0, s, a.geom, n, T,
                            a.L.tpc, WS(a, gsort, const float *), a.angles, a.w,
                            WS(a, uv, const float *), WS(a, rect, const int4 *),
-                           WS(a, gcount, const uint32_t *),
+                           WS(a, goff, const uint32_t *),
                            WS(a, part, const float4 *),
                            (unsigned)a.L.cap, WS(a, tacc, float *), WS(a, gwpart, float *),
                            nparts);
@@ -2318,7 +2314,7 @@ static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32
                            0, s, a.geom, a.n, a.T, WS(a, rec, const float4 *),
                            WS(a, list, const uint32_t *), WS(a, cnt, const uint32_t *), a.L.nblk,
                            (unsigned)a.L.cap, WS(a, rect, const int4 *),
-                           WS(a, gcount, const uint32_t *), grad_proj, WS(a, part, float4 *),
+                           WS(a, goff, const uint32_t *), grad_proj, WS(a, part, float4 *),
                            queue);
     else
         hipLaunchKernelGGL((k_splat_bwd<EWA, TW, TH>),
@@ -2326,7 +2322,7 @@ static void launch_splat_bwd(const RenderArgs &a, const float *grad_proj, uint32
                            0, s, a.geom, a.n,
                            a.T, WS(a, rec, const float4 *), WS(a, list, const uint32_t *),
                            WS(a, cnt, const uint32_t *), a.L.nblk, (unsigned)a.L.cap,
-                           WS(a, rect, const int4 *), WS(a, gcount, const uint32_t *), grad_proj,
+                           WS(a, rect, const int4 *), WS(a, goff, const uint32_t *), grad_proj,
                            WS(a, part, float4 *));
 }
 
@@ -2349,6 +2345,14 @@ hipError_t render_backward(const RenderArgs &a, const float *grad_proj, float *g
                            float *g_w, hipStream_t s)
 {
     hipError_t e;
+    // per-(t,n) instance offsets (Gaussian-major) from the forward's instance counts, into their
+    // own array (the counts stay, so a second backward of the same forward finds them)
+    {
+        ProfScope ps(PS_SCAN, s);
+        e = launch_exclusive_scan(WS(a, goff, uint32_t *), (size_t)a.T * a.n,
+                                  WS(a, scratch, uint32_t *), s, WS(a, gcount, const uint32_t *));
+    }
+    if (e != hipSuccess) return e;
     // a6: per-instance moment sums
     {
         const size_t items = (size_t)a.geom.ntiles * a.T;

@@ -2,7 +2,8 @@
 //
 // Used for the (projection, tile, Gaussian-block) instance counts of the tile binning, the
 // per-Gaussian instance offsets, and the digit histograms of the cell sort. Each workgroup
-// scans 2048 elements (256 threads x 8 consecutive elements). With at most 2048 blocks, a
+// scans 2048 elements (256 threads x 8 consecutive elements), from src into data (src may be
+// data itself). With at most 2048 blocks, a
 // second launch adds to each block the sum of the block totals before it (each workgroup sums
 // them itself); with more, the block totals are scanned recursively and added back.
 #include "kernels.h"
@@ -11,7 +12,7 @@
 #define SCAN_PER_THREAD 8
 #define SCAN_BLOCK (SCAN_THREADS * SCAN_PER_THREAD)
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_block(uint32_t *__restrict__ data,
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_block(uint32_t *data, const uint32_t *src,
                                                              size_t n,
                                                              uint32_t *__restrict__ bsum)
 {
@@ -22,7 +23,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_block(uint32_t *__restric
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
         size_t i = base + k;
-        uint32_t x = (i < n) ? data[i] : 0u;
+        uint32_t x = (i < n) ? src[i] : 0u;
         v[k] = run;
         run += x;
     }
@@ -102,12 +103,13 @@ size_t scan_scratch_elems(size_t n)
     return total + 1;
 }
 
-hipError_t launch_exclusive_scan(uint32_t *data, size_t n, uint32_t *scratch, hipStream_t s)
+hipError_t launch_exclusive_scan(uint32_t *data, size_t n, uint32_t *scratch, hipStream_t s,
+                                 const uint32_t *src)
 {
     if (n == 0) return hipSuccess;
     const size_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n,
-                       nb > 1 ? scratch : nullptr);
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data,
+                       src ? src : (const uint32_t *)data, n, nb > 1 ? scratch : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nb == 1) return e;
     if (nb <= SCAN_BLOCK) {
