@@ -60,21 +60,27 @@ ALGO_BYTES_PER_STEP = ALGO_BYTES_PER_PROJ * 64   # 129.7 MB per 64-view fwd+bwd 
 # HBM bytes per launch of k_splat_bwd (the roofline kernel) from two rocprofv3 --pmc runs of this
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
-# library sources whose digest is given; reported only while the sources are unchanged
+# library sources whose digest is given; reported only while their code (comments aside) is unchanged
 TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2219984.3 * (524288.0 / 262167.75) * 1024,
            "write_bytes": 6625403.1 * 1.000 * 1024,
            "sources_sha256": "7884fc03bb8ea99dd702ea68e23363792dbb5648f843382c7621f7d8a05adbb5"}
 
 
 def sources_digest() -> str:
-    """sha256 over the library's HIP sources and headers, in name order."""
+    """sha256 over the library's HIP sources and headers in name order, each with its comments and
+    blank lines removed (a comment edit does not change the kernels the figures were taken on)."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_2506_22280_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
         if name.endswith((".hip", ".h")):
+            text = open(os.path.join(d, name), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)      # block comments
+            text = re.sub(r"//[^\n]*", "", text)                     # line comments
+            code = "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
             h.update(name.encode())
-            h.update(open(os.path.join(d, name), "rb").read())
+            h.update(code.encode())
     return h.hexdigest()
 
 

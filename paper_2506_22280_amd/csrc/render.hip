@@ -1013,7 +1013,8 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 // (block-major) to one of two pair queues in LDS: pairs whose ellipse meets both 4-row halves of
 // the block run over its 8 rows, the others over the one half they meet. Each queue is evaluated
 // 64 pairs at a time, one pair per lane, and its remainder is carried over to the next chunk, so
-// that lanes idle only when a chunk must be finished early (below) and at the end of the tile. A
+// that lanes idle only when a chunk must be finished early (below) and in the tile's last groups
+// (the four waves' remainders, pooled and evaluated by one wave). A
 // lane runs over its pair's 64 (or 32) pixels with forward differences along each row and
 // accumulates twelve moment sums, which are added into the entry's LDS slot in block order (fixed
 // order, no atomics). Entry slots belong to
