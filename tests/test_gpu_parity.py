@@ -137,6 +137,29 @@ def test_project_many_gaussians_small_detector():
     check_grads({k: out[k] for k in gref}, gref)
 
 
+def test_backward_twice_after_one_forward():
+    """Backward calls that reuse one forward leave its intermediates intact: a second and a third
+    backward on the same workspace equal the first, and a backward that recomputes the forward,
+    bit for bit."""
+    _print("case: small phantom, one forward, three reusing backward calls")
+    p = synth.small_phantom(seed=8)
+    t = problem_tensors(p)
+    _, ws = _fwd(p, t)
+    shape = (len(p.angles), p.geom["nv"], p.geom["nu"])
+    rng = np.random.default_rng(81)
+    G1, G2 = dev(rng.normal(0, 1, shape)), dev(rng.normal(0, 1, shape))
+    args = (p.geom, p.grid, t["coef"], t["mu"], t["scale"], t["quat"], t["rho"], t["angles"],
+            t["w"])
+    o1 = _lib.project_bwd(*args, G1, ws, reuse_fwd=True)
+    o2 = _lib.project_bwd(*args, G2, ws, reuse_fwd=True)
+    o3 = _lib.project_bwd(*args, G1, ws, reuse_fwd=True)
+    f2 = _lib.project_bwd(*args, G2, _lib.Workspace())
+    torch.cuda.synchronize()
+    for k in o1:
+        assert torch.equal(o1[k], o3[k]), k
+        assert torch.equal(o2[k], f2[k]), k
+
+
 def test_project_deterministic_and_batch_invariant():
     _print("case: bitwise repeatability; batched equals one view per launch")
     p = synth.small_phantom(seed=3)
