@@ -61,9 +61,9 @@ ALGO_BYTES_PER_STEP = ALGO_BYTES_PER_PROJ * 64   # 129.7 MB per 64-view fwd+bwd 
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while their code (comments aside) is unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2219984.3 * (524288.0 / 262167.75) * 1024,
-           "write_bytes": 6625403.1 * 1.000 * 1024,
-           "sources_sha256": "7884fc03bb8ea99dd702ea68e23363792dbb5648f843382c7621f7d8a05adbb5"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2225010.6 * (524288.0 / 262167.375) * 1024,
+           "write_bytes": 6629280.3 * 1.000 * 1024,
+           "sources_sha256": "fe521986983ac79c0ceb4697d2bd163bb46a2bac1d758b0d73ebc04860cdb143"}
 
 
 def sources_digest() -> str:
