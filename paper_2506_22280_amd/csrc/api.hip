@@ -168,7 +168,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->rec = take(sizeof(float) * DIGS_REC_FLOATS * TN);
     L->rect = take(sizeof(int) * 4 * TN);
     L->gcount = take(sizeof(uint32_t) * TN);
-    L->cnt = take(sizeof(uint32_t) * cnt_elems);
+    L->cnt = take(sizeof(uint32_t) * 2 * cnt_elems);   // counts, then the waves' offsets
     L->scratch = take(sizeof(uint32_t) * sc);
     L->list = take(sizeof(uint32_t) * L->cap);
     const size_t bwd = fwd_only ? 0 : 1;   // the backward's arrays
@@ -179,7 +179,7 @@ bool ws_layout(const digs_geom *geom, const digs_grid *grid, int n, int T,
     L->vals_a = take(sizeof(uint32_t) * N);
     L->keys_b = take(sizeof(uint32_t) * N);
     L->vals_b = take(sizeof(uint32_t) * N);
-    L->rhist = take(sizeof(uint32_t) * 256 * (size_t)nblk_r);
+    L->rhist = take(sizeof(uint32_t) * 2 * 256 * (size_t)nblk_r);
     L->cell_start = take(sizeof(uint32_t) * ((size_t)L->ncells + 1));
     L->tacc = take(bwd * sizeof(float) * (13 + 12 * (size_t)grid->R) * L->tchunks * N);
     L->order = take(sizeof(uint32_t) * N);

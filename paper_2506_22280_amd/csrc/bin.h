@@ -3,9 +3,10 @@
 // Each item (a Gaussian of one projection, or one key of a radix pass) contributes nkeys()
 // keys: key(k) is its k-th, and count(h) adds one to h[key] for each of them (in any order);
 // before its keys are placed, prepare() may load what emit() needs beyond the keys. k_bin_count builds per-wave key histograms in LDS (integer LDS atomics: exact counts)
-// and writes one count per (slice, key, item block). After an exclusive scan of those counts
-// in (slice, key, block) order, k_bin_fill recomputes the per-wave histograms, turns them into
-// per-wave running offsets, and places every (item, key) pair: the rank among equal keys in
+// and writes one count per (slice, key, item block), and beside it the offsets of the block's
+// waves 1-3 within it (10 bits each, packed). After an exclusive scan of the counts in (slice,
+// key, block) order, k_bin_fill forms per-wave running offsets from both and places every
+// (item, key) pair: the rank among equal keys in
 // one wave step comes from ballots over the key bits (a wave-level match), so the order
 // inside every list is a fixed function of the input and the whole binning is bitwise
 // reproducible.
@@ -40,10 +41,14 @@ __device__ __forceinline__ unsigned long long wave_match(unsigned key, bool acti
     return ((unsigned long long)mhi << 32) | mlo;
 }
 
+// (a wave takes ITEMS / BIN_WAVES items, each with at most one instance of a key, so the offsets
+// of waves 1-3 within a block, at most 3 ITEMS / BIN_WAVES, fit 10 bits each)
 template <class Src, int ITEMS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_count(Src src, uint32_t *__restrict__ cnt,
-                                                           int nbins, int nblk)
+                                                           uint32_t *__restrict__ pre, int nbins,
+                                                           int nblk)
 {
+    static_assert(3 * (ITEMS / BIN_WAVES) < 1024 && BIN_WAVES == 4, "wave offsets: 3 x 10 bits");
     extern __shared__ uint32_t hist[];   // [BIN_WAVES][nbins]
     const int slice = blockIdx.y, blk = blockIdx.x;
     const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
@@ -58,39 +63,35 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_count(Src src, uint32_t *__
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbins; b += BIN_THREADS) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int w = 0; w < BIN_WAVES; ++w) c += hist[w * nbins + b];
-        cnt[((size_t)slice * nbins + b) * nblk + blk] = c;
+        const uint32_t c0 = hist[b], c1 = hist[nbins + b], c2 = hist[2 * nbins + b];
+        const uint32_t c3 = hist[3 * nbins + b];
+        cnt[((size_t)slice * nbins + b) * nblk + blk] = c0 + c1 + c2 + c3;
+        // (the offsets in workgroup-major order: each workgroup writes, and reads, one run)
+        pre[((size_t)slice * nblk + blk) * nbins + b] =
+            c0 | ((c0 + c1) << 10) | ((c0 + c1 + c2) << 20);
     }
 }
 
 template <class Src, int ITEMS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
                                                           const uint32_t *__restrict__ cnt_scan,
+                                                          const uint32_t *__restrict__ pre,
                                                           int nbins, int nblk, int nbits)
 {
-    extern __shared__ uint32_t hist[];   // per-wave counts, then per-wave running offsets
+    extern __shared__ uint32_t hist[];   // per-wave running offsets
     const int slice = blockIdx.y, blk = blockIdx.x;
     const int wave = threadIdx.x / DIGS_WAVE, lane = lane_id();
-    for (int k = threadIdx.x; k < BIN_WAVES * nbins; k += BIN_THREADS) hist[k] = 0;
-    __syncthreads();
     uint32_t *h = hist + wave * nbins;
     constexpr int PER_WAVE = ITEMS / BIN_WAVES;
     const int base = blk * ITEMS + wave * PER_WAVE;
-    for (int step = 0; step < PER_WAVE / DIGS_WAVE; ++step) {
-        const int item = base + step * DIGS_WAVE + lane;
-        if (item < src.items) src.load(slice, item).count(h);
-    }
-    __syncthreads();
+    // each wave's first position per key: the block's (scanned) plus the wave's offset within it
     for (int b = threadIdx.x; b < nbins; b += BIN_THREADS) {
-        uint32_t run = cnt_scan[((size_t)slice * nbins + b) * nblk + blk];
-#pragma unroll
-        for (int w = 0; w < BIN_WAVES; ++w) {
-            const uint32_t c = hist[w * nbins + b];
-            hist[w * nbins + b] = run;
-            run += c;
-        }
+        const uint32_t run = cnt_scan[((size_t)slice * nbins + b) * nblk + blk];
+        const uint32_t p = pre[((size_t)slice * nblk + blk) * nbins + b];
+        hist[b] = run;
+        hist[nbins + b] = run + (p & 1023u);
+        hist[2 * nbins + b] = run + ((p >> 10) & 1023u);
+        hist[3 * nbins + b] = run + (p >> 20);
     }
     __syncthreads();
     // Emit: the step's (item, key) pairs are flattened in (lane, key) order and placed 64 at a time,
@@ -167,7 +168,8 @@ struct RadixSrc {
     }
 };
 
-// Count, scan and place (see above); the scan runs over (slice, key, block) counts.
+// Count, scan and place (see above); the scan runs over (slice, key, block) counts, which cnt
+// holds followed by the waves' offsets (2 cnt_elems words).
 // items: items per workgroup, DIGS_BIN_ITEMS or DIGS_BIN_ITEMS_SMALL (nblk = ceil(items of a
 // slice / items)). stages: time the three launches as their own stages (false when the caller
 // times the whole binning as one stage)
@@ -177,16 +179,18 @@ static inline hipError_t launch_binning(const Src &src, int slices, int nbins, i
                                         hipStream_t s, int items = DIGS_BIN_ITEMS,
                                         bool stages = true)
 {
+    // cnt holds 2 cnt_elems words: the counts (scanned in place), then the waves' offsets
+    uint32_t *pre = cnt + cnt_elems;
     const size_t lds = (size_t)BIN_WAVES * nbins * sizeof(uint32_t);
     const bool small = items == DIGS_BIN_ITEMS_SMALL;
     {
         ProfScope ps(stages ? PS_BIN_COUNT : -1, s);
         if (small)
             hipLaunchKernelGGL((k_bin_count<Src, DIGS_BIN_ITEMS_SMALL>), dim3(nblk, slices),
-                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk);
+                               dim3(BIN_THREADS), lds, s, src, cnt, pre, nbins, nblk);
         else
             hipLaunchKernelGGL((k_bin_count<Src, DIGS_BIN_ITEMS>), dim3(nblk, slices),
-                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk);
+                               dim3(BIN_THREADS), lds, s, src, cnt, pre, nbins, nblk);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -199,10 +203,10 @@ static inline hipError_t launch_binning(const Src &src, int slices, int nbins, i
         ProfScope ps(stages ? PS_BIN_FILL : -1, s);
         if (small)
             hipLaunchKernelGGL((k_bin_fill<Src, DIGS_BIN_ITEMS_SMALL>), dim3(nblk, slices),
-                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk, nbits);
+                               dim3(BIN_THREADS), lds, s, src, cnt, pre, nbins, nblk, nbits);
         else
             hipLaunchKernelGGL((k_bin_fill<Src, DIGS_BIN_ITEMS>), dim3(nblk, slices),
-                               dim3(BIN_THREADS), lds, s, src, cnt, nbins, nblk, nbits);
+                               dim3(BIN_THREADS), lds, s, src, cnt, pre, nbins, nblk, nbits);
     }
     return hipGetLastError();
 }
@@ -217,7 +221,7 @@ static inline int bits_for(int nbins)
 
 // Stable sort of (key, value) pairs by the low `kbits` bits of the key, 8 bits per pass. The
 // pairs start in (ka, va); the sorted pairs end in (ka, va) if *swapped is false, else in
-// (kb, vb). rhist needs 256 * ceil(n / DIGS_BIN_ITEMS) words, scratch the scan's scratch.
+// (kb, vb). rhist needs 2 * 256 * ceil(n / DIGS_BIN_ITEMS) words, scratch the scan's scratch.
 static inline hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                                           int n, int kbits, uint32_t *rhist, uint32_t *scratch,
                                           bool *swapped, hipStream_t s)

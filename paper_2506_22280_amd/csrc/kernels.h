@@ -14,13 +14,14 @@ struct WsLayout {
     size_t rect;       // [T][N] int4 tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16) and instance mask
     size_t gcount;     // [T][N] u32 instances per (t,n) (the forward's set-up)
     size_t goff;       // [T][N] u32 instance offsets: exclusive scan of gcount (the backward's)
-    size_t cnt;        // [T][ntiles][nblk] u32 per-block tile counts, scanned in place
+    size_t cnt;        // [T][ntiles][nblk] u32 per-block tile counts, scanned in place; then as
+                       //     many words of the blocks' per-wave offsets (binning)
     size_t scratch;    // scan block sums
     size_t list;       // [cap] u32 Gaussian index of each instance, grouped by (t, tile)
     size_t part;       // [cap][12] f32 backward partial sums, instance (t,n,k) at goff[t][n]+k
     size_t gwpart;     // [T][R][4*ceil(N/256)] f32 per-wave partial sums of dL/dw
     size_t keys_a, vals_a, keys_b, vals_b;  // [N] u32 cell sort ping-pong
-    size_t rhist;      // [256][ceil(N/1024)] u32 radix digit histograms
+    size_t rhist;      // 2 x [256][ceil(N/1024)] u32 radix digit histograms, per-wave offsets
     size_t cell_start;                      // [ncells + 1] u32 first position of each cell
     size_t tacc;       // [13 + 12R][tchunks][N] f32 per-Gaussian adjoint sums over chunks of views
     size_t order;      // [N] u32 the Gaussian at each position of cell order (per-Gaussian arrays

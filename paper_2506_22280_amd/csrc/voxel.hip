@@ -355,7 +355,7 @@ static bool phi_layout(const digs_vgrid *vg, int n, int64_t capacity, PhiLayout 
     L->va = take(sizeof(uint32_t) * L->cap);
     L->kb = take(sizeof(uint32_t) * L->cap);
     L->vb = take(sizeof(uint32_t) * L->cap);
-    L->rhist = take(sizeof(uint32_t) * 256 * nblk);
+    L->rhist = take(sizeof(uint32_t) * 2 * 256 * nblk);   // counts, then the waves' offsets
     L->bstart = take(sizeof(uint32_t) * ((size_t)L->nbricks + 1));
     L->total = off;
     return true;
