@@ -130,7 +130,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_fill(Src src,
             const unsigned key = active ? (unsigned)o.key(k) : 0u;
             const unsigned long long peers = wave_match(key, active, nbits);
             uint32_t pos = 0;
-            const int rank = __popcll(peers & lanemask_lt());
+            const int rank = lane_rank(peers);
             if (active) pos = h[key] + (uint32_t)rank;
             if (active && rank == 0) h[key] = pos + (uint32_t)__popcll(peers);
             if (active) src.emit(slice, item0 + j, o, k, key, pos);

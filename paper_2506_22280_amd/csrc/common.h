@@ -81,10 +81,11 @@ __device__ __forceinline__ int lane_id()
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
-__device__ __forceinline__ unsigned long long lanemask_lt()
+// the set bits of a wave mask below this lane (its rank among the mask's lanes)
+__device__ __forceinline__ int lane_rank(unsigned long long m)
 {
-    int l = lane_id();
-    return (l == 0) ? 0ull : (~0ull >> (64 - l));
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
 template <typename T>

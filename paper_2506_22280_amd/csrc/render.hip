@@ -799,10 +799,14 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
                 h = g < (uint32_t)n ? (e >> (LIST_BLOCK_SHIFT + 2 * blkid)) & 3u : 0u;
             }
             const unsigned long long m0 = __ballot(h == 3u), m1 = __ballot(h == 1u),
-                                     m2 = __ballot(h == 2u), lt = lanemask_lt();
-            if (h == 3u) qs[0][pend0 + __popcll(m0 & lt)] = g;
-            else if (h == 1u) qs[1][pend1 + __popcll(m1 & lt)] = g;
-            else if (h == 2u) qs[2][pend2 + __popcll(m2 & lt)] = g;
+                                     m2 = __ballot(h == 2u);
+            // a masked store per queue (the empty asm keeps the compiler from merging them into
+            // one store whose queue, count and mask each lane selects)
+            if (h == 3u) qs[0][pend0 + lane_rank(m0)] = g;
+            asm volatile("" ::: "memory");
+            if (h == 1u) qs[1][pend1 + lane_rank(m1)] = g;
+            asm volatile("" ::: "memory");
+            if (h == 2u) qs[2][pend2 + lane_rank(m2)] = g;
             const int ns0 = pend0 + __popcll(m0), ns1 = pend1 + __popcll(m1),
                       ns2 = pend2 + __popcll(m2);
             const int f0 = ns0 & ~7, f1 = ns1 & ~7, f2 = ns2 & ~7;
@@ -1289,15 +1293,16 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
 #pragma unroll
         for (int c = 0; c < 12; ++c) accS[ring + lane][c] = 0.0f;
         int np0 = pend0, np1 = pend1;
-        const unsigned long long lt = lanemask_lt();
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) {
             const uint32_t h = valid ? (ent >> (LIST_BLOCK_SHIFT + 2 * blk)) & 3u : 0u;
             const bool whole = h == 3u, half = h == 1u || h == 2u;
             const unsigned long long mw = __ballot(whole), mh = __ballot(half);
             const uint32_t pe = ((uint32_t)(ring + lane) << 3) | (uint32_t)blk;
-            if (whole) pq0[np0 + __popcll(mw & lt)] = pe;
-            if (half) pq1[np1 + __popcll(mh & lt)] = pe | ((h >> 1) << 2);
+            // a masked store per queue (the empty asm keeps them from being merged into one)
+            if (whole) pq0[np0 + lane_rank(mw)] = pe;
+            asm volatile("" ::: "memory");
+            if (half) pq1[np1 + lane_rank(mh)] = pe | ((h >> 1) << 2);
             np0 += __popcll(mw);
             np1 += __popcll(mh);
         }
