@@ -712,21 +712,23 @@ __device__ __forceinline__ void splat_fwd_rows(float q, float dq, float ddq, flo
     }
 }
 
-// Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8, or the queue's last group)
-// over rows [R0, R0 + NR) of the block: positive amplitudes into the lane's row sums acc,
+// Evaluates the wave's queued Gaussians [0, ns) (a multiple of 8 unless TAIL: the queue's last
+// group) over rows [R0, R0 + NR) of the block: positive amplitudes into the lane's row sums acc,
 // negative ones (by magnitude, in a second pass taken only when the group has any) into accn.
-template <bool EWA, int R0, int NR>
+// The queue holds the byte offsets of the Gaussians' records from rt.
+template <bool EWA, int R0, int NR, bool TAIL>
 __device__ __forceinline__ void splat_fwd_group(const float4 *__restrict__ rt,
                                                 const uint32_t *__restrict__ qid, int ns,
                                                 int gslot, float fi, float fby, float *acc,
                                                 float *accn)
 {
     for (int j = 0; j < ns; j += 8) {
-        // a slot past the queue's end repeats its last Gaussian with amplitude 0
+        // (TAIL) a slot past the queue's end repeats its last Gaussian with amplitude 0
         const int sn = j + gslot;
-        const bool live = sn < ns;
-        const size_t gg = qid[live ? sn : ns - 1];
-        const float4 r0 = rt[gg * 4 + 0], r1 = rt[gg * 4 + 1], r2 = rt[gg * 4 + 2];
+        const bool live = !TAIL || sn < ns;
+        const float4 *rg =
+            (const float4 *)((const char *)rt + qid[TAIL ? min(sn, ns - 1) : sn]);
+        const float4 r0 = rg[0], r1 = rg[1], r2 = rg[2];
         // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
         // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
         const float du = fi - r0.x, dv0 = (fby + (float)R0) - r0.y;
@@ -802,18 +804,23 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
                                      m2 = __ballot(h == 2u);
             // a masked store per queue (the empty asm keeps the compiler from merging them into
             // one store whose queue, count and mask each lane selects)
-            if (h == 3u) qs[0][pend0 + lane_rank(m0)] = g;
+            // (the queues hold the records' byte offsets, g * 64 < 2^30)
+            const uint32_t go = g << 6;
+            if (h == 3u) qs[0][pend0 + lane_rank(m0)] = go;
             asm volatile("" ::: "memory");
-            if (h == 1u) qs[1][pend1 + lane_rank(m1)] = g;
+            if (h == 1u) qs[1][pend1 + lane_rank(m1)] = go;
             asm volatile("" ::: "memory");
-            if (h == 2u) qs[2][pend2 + lane_rank(m2)] = g;
+            if (h == 2u) qs[2][pend2 + lane_rank(m2)] = go;
             const int ns0 = pend0 + __popcll(m0), ns1 = pend1 + __popcll(m1),
                       ns2 = pend2 + __popcll(m2);
             const int f0 = ns0 & ~7, f1 = ns1 & ~7, f2 = ns2 & ~7;
             wave_sync_lds();
-            if (f0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], f0, gslot, fi, fby, acc, accn);
-            if (f1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], f1, gslot, fi, fby, acc, accn);
-            if (f2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], f2, gslot, fi, fby, acc, accn);
+            if (f0 > 0)
+                splat_fwd_group<EWA, 0, 8, false>(rt, qs[0], f0, gslot, fi, fby, acc, accn);
+            if (f1 > 0)
+                splat_fwd_group<EWA, 0, 4, false>(rt, qs[1], f1, gslot, fi, fby, acc, accn);
+            if (f2 > 0)
+                splat_fwd_group<EWA, 4, 4, false>(rt, qs[2], f2, gslot, fi, fby, acc, accn);
             if ((f0 | f1 | f2) > 0) {
                 // move each queue's remainder to its front: lane 8c + i moves entry i of queue c
                 const int qc = lane >> 3, qi = lane & 7;
@@ -829,9 +836,12 @@ __device__ __forceinline__ void splat_fwd_tile(const DevGeom &G, int n, int t, i
             pend1 = ns1 - f1;
             pend2 = ns2 - f2;
         }
-        if (pend0 > 0) splat_fwd_group<EWA, 0, 8>(rt, qs[0], pend0, gslot, fi, fby, acc, accn);
-        if (pend1 > 0) splat_fwd_group<EWA, 0, 4>(rt, qs[1], pend1, gslot, fi, fby, acc, accn);
-        if (pend2 > 0) splat_fwd_group<EWA, 4, 4>(rt, qs[2], pend2, gslot, fi, fby, acc, accn);
+        if (pend0 > 0)
+            splat_fwd_group<EWA, 0, 8, true>(rt, qs[0], pend0, gslot, fi, fby, acc, accn);
+        if (pend1 > 0)
+            splat_fwd_group<EWA, 0, 4, true>(rt, qs[1], pend1, gslot, fi, fby, acc, accn);
+        if (pend2 > 0)
+            splat_fwd_group<EWA, 4, 4, true>(rt, qs[2], pend2, gslot, fi, fby, acc, accn);
         wave_sync_lds();
         // sum over the 8 Gaussian slots (lane bits 3..5) in a fixed order
 #pragma unroll
@@ -1095,16 +1105,19 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     const float vve = 2.0f * r1.x;
     float der = fmaf(CE, s1, r0.w * dv0);
     const float Rm = (float)(NROWS - 1);
+    // (the sums start at -0, which adding the first term leaves exactly that term)
     float S[12];
     if constexpr (EWA) {
         // per pixel a = g 2^x (dL/dE up to the factor -amp/2); dL/damp = sum a
-        float e0 = 0.f, e1 = 0.f, e2 = 0.f, Q0 = 0.f, Q1 = 0.f, W0 = 0.f, tw = -1.0f;
+        float e0 = -0.f, e1 = -0.f, e2 = -0.f, Q0 = -0.f, Q1 = -0.f, W0 = -0.f;
         const float *gp = gpx + lby * GPX_STRIDE + lbx;
+#pragma unroll
         for (int row = 0; row < NROWS; ++row) {
-            Q0 += e0;
-            Q1 += e1;
-            W0 = fmaf(tw, e0, W0);
-            tw += 2.0f;
+            if (row > 0) {   // (row 0 adds P_{-1} = 0)
+                Q0 += e0;
+                Q1 += e1;
+                W0 = fmaf((float)(2 * row - 1), e0, W0);
+            }
             float ee = er, de = der;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
@@ -1128,7 +1141,7 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         S[1] = fmaf(du0, fmaf(du0, e0, 2.0f * e1), e2);
         S[2] = fmaf(du0, EV0, EV1);
         S[3] = EW0;
-        S[4] = S[5] = S[6] = S[7] = S[8] = S[9] = 0.0f;
+        S[4] = S[5] = S[6] = S[7] = S[8] = S[9] = 0.0f;   // (not accumulated below)
         S[10] = fmaf(du0, e0, e1);
         S[11] = EV0;
     } else {
@@ -1137,18 +1150,19 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         float vq = fmaf(Gvv, t1, fmaf(r2.x, du0, r1.z));
         const float vvq = 2.0f * Gvv;
         float dqr = fmaf(Cq, s1, Bq0);
-        float S0 = 0.f, e0 = 0.f, e1 = 0.f, e2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
-        float Qe0 = 0.f, Qe1 = 0.f, We0 = 0.f, Qx0 = 0.f, Qx1 = 0.f, Wx0 = 0.f, tw = -1.0f;
+        float S0 = -0.f, e0 = -0.f, e1 = -0.f, e2 = -0.f, x0 = -0.f, x1 = -0.f, x2 = -0.f;
+        float Qe0 = -0.f, Qe1 = -0.f, We0 = -0.f, Qx0 = -0.f, Qx1 = -0.f, Wx0 = -0.f;
         const float *gp = gpx + lby * GPX_STRIDE + lbx;
 #pragma unroll
         for (int row = 0; row < NROWS; ++row) {
-            Qe0 += e0;
-            Qe1 += e1;
-            We0 = fmaf(tw, e0, We0);
-            Qx0 += x0;
-            Qx1 += x1;
-            Wx0 = fmaf(tw, x0, Wx0);
-            tw += 2.0f;
+            if (row > 0) {   // (row 0 adds P_{-1} = 0)
+                Qe0 += e0;
+                Qe1 += e1;
+                We0 = fmaf((float)(2 * row - 1), e0, We0);
+                Qx0 += x0;
+                Qx1 += x1;
+                Wx0 = fmaf((float)(2 * row - 1), x0, Wx0);
+            }
             // along the row: q(du) and E(du) by forward differences from the row's first pixel
             float q = qr, dq = dqr, ee = er, de = der;
 #pragma unroll
@@ -1210,7 +1224,8 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
         if (active && blk == b) {
             float *dst = accS[slot];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) dst[c] += S[c];
+            for (int c = 0; c < 12; ++c)
+                if (!EWA || c < 4 || c > 9) dst[c] += S[c];
         }
         wave_sync_lds();
     }
