@@ -1051,7 +1051,7 @@ hipError_t render_count_pairs(const RenderArgs &a, hipStream_t s)
 struct BwdShared {
     float gpx[GPX_FLOATS];
     uint32_t pairs[4][2][BWD_QUEUE];       // (entry slot << 3) | (half << 2) | block
-    uint32_t gid[4][2 * DIGS_WAVE];        // Gaussian of each entry slot
+    uint32_t gid[4][2 * DIGS_WAVE];        // record byte offset (Gaussian x 64) of each entry slot
     float accS[4][2 * DIGS_WAVE][13];      // moment sums of each entry slot
     int pend[2][4];                        // each wave's pairs left at the end of the tile
 };
@@ -1071,18 +1071,13 @@ __device__ __forceinline__ void splat_bwd_group(const float4 *__restrict__ rt,
     // contraction would compute it twice
 #pragma clang fp contract(off)
     constexpr int GPX_STRIDE = TW + 2, BXL = TW == 8 ? 0 : (TW == 16 ? 1 : 2);
-    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int lane = lane_id();
+    // a lane past the group's end evaluates its last pair again and adds nothing
     const bool active = lane < cnt;
-    const uint32_t pr = active ? pq[j0 + lane] : 0u;
+    const uint32_t pr = pq[j0 + min(lane, cnt - 1)];
     const int slot = (int)(pr >> 3), blk = (int)(pr & 3u);
-    float4 r0 = zero4, r1 = zero4, r2 = zero4;
-    if (active) {
-        const size_t ge = gid[slot];
-        r0 = rt[ge * 4 + 0];
-        r1 = rt[ge * 4 + 1];
-        r2 = rt[ge * 4 + 2];
-    }
+    const float4 *rg = (const float4 *)((const char *)rt + gid[slot]);
+    const float4 r0 = rg[0], r1 = rg[1], r2 = rg[2];
     // r0 = (us, vs, Huu', Huv'), r1 = (Hvv', gu2, gv2, Guu),
     // r2 = (Guv2, Gvv carrying the sign of amp, log2|amp|, -)
     const int lbx = (blk & ((1 << BXL) - 1)) * 8;
@@ -1304,7 +1299,7 @@ __device__ __forceinline__ void splat_bwd_tile(const DevGeom &G, int n, int t, i
         const uint32_t ent = valid ? list[k] : 0u;
         const uint32_t g = ent & LIST_INDEX_MASK;
         valid = valid && g < (uint32_t)n;
-        gid[ring + lane] = g;
+        gid[ring + lane] = g << 6;   // the record's byte offset (g * 64 < 2^30)
 #pragma unroll
         for (int c = 0; c < 12; ++c) accS[ring + lane][c] = 0.0f;
         int np0 = pend0, np1 = pend1;
