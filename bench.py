@@ -11,7 +11,7 @@ backward to mu, scale, quaternion, density, FFD coefficients and the temporal we
 
 The timed steps run the batched path: a plan (digs_plan_*) over fixed device buffers, its launch
 shape and instance capacity chosen by the library's autotuner on the first batch, replayed as HIP
-graphs. Per-kernel durations come from a second pass over the same steps launched eagerly with the
+graphs or as direct launches (the plan times both once and keeps the faster). Per-kernel durations come from a second pass over the same steps launched eagerly with the
 same tuning, each kernel stage bracketed by HIP events on its launch stream.
 
 Inputs (Gaussians, lattice, per-batch angles and weights, measured projections) are resident in
@@ -152,7 +152,7 @@ def _time_ms(fn, reps: int):
 
 def single_view_leg(dev):
     """The single-projection forward path: 50k Gaussians, 256x256 at 1.6 mm, one view per call,
-    eagerly and as a plan replay (HIP graph)."""
+    eagerly and as a plan replay (HIP graph or direct launches, whichever the plan timed faster)."""
     import torch
     from paper_2506_22280_amd import _lib, synth
     p = synth.single_view(seed=0)
@@ -180,7 +180,7 @@ def single_view_leg(dev):
                  g_quat=torch.empty((4, p.n), device=dev), g_rho=torch.empty((p.n,), device=dev),
                  g_coef=torch.empty_like(t["coef"]), g_w=torch.empty((1, 3), device=dev))
     plan = _lib.Plan(p.geom, p.grid, p.n, 1, dict(t, angles=ang, w=w, proj=proj, **grads))
-    graph = _time_ms(plan.fwd, 200)
+    replayed = _time_ms(plan.fwd, 200)
     # the scan's 680 views of the same model, one per launch: each writes its angle and weights
     # into the plan's buffers and replays the per-view stages (the per-Gaussian stage, shared by
     # every view, ran once in the plan's first fwd above)
@@ -195,9 +195,11 @@ def single_view_leg(dev):
         plan.fwd_views()
     views = _time_ms(view, ang_all.shape[0])
     tuning, _ = plan.tuning()
+    replay = plan.replay_modes()
     plan.close()
-    return {"ms_per_view_eager": round(eager, 4), "ms_per_view_graph": round(graph, 4),
-            "views_per_s_graph": round(1e3 / graph, 1),
+    return {"ms_per_view_eager": round(eager, 4), "ms_per_view_plan": round(replayed, 4),
+            "views_per_s_plan": round(1e3 / replayed, 1),
+            "plan_replay": {k: replay[k] for k in ("fwd", "fwd_views")},
             "ms_per_view_scan_views_only": round(views, 4),
             "views_per_s_scan_views_only": round(1e3 / views, 1),
             "stage_ms_per_view_eager": stages,
@@ -480,7 +482,7 @@ def main():
         del src, dst
 
     # the batched path: a plan over fixed buffers, autotuned on the first batch, replayed as HIP
-    # graphs; a step writes the batch's angles and weights into the plan's buffers, replays the
+    # graphs or direct launches (whichever it timed faster); a step writes the batch's angles and weights into the plan's buffers, replays the
     # forward, forms dL/dI = I - P of the L2 loss, and replays the backward
     torch.sub(meas[0], meas[0], out=gradp)
     plan = _lib.Plan(G, Gd, n, B, dict(est, angles=ang_buf, w=w_buf, proj=proj, grad_proj=gradp,
@@ -515,6 +517,7 @@ def main():
     diag, resized = plan.check()
     if resized or diag["overflow"] or diag["nonfinite"]:
         raise SystemExit("diagnostics report a problem in the timed steps: %s" % diag)
+    replay = plan.replay_modes()
     plan.close()
 
     # per-kernel timing: the same steps, launched eagerly with the plan's tuning, every kernel
@@ -577,7 +580,8 @@ def main():
     out["sources_sha256"] = sources_digest()
     out["tuning"] = {"chosen": {k: tuning[k] for k in ("tile_w", "tile_h", "splat_waves",
                                                        "persistent", "capacity", "slices")},
-                     "candidates_fwd_bwd_ms": tuning_candidates(tune_ms)}
+                     "candidates_fwd_bwd_ms": tuning_candidates(tune_ms),
+                     "replay": {k: replay[k] for k in ("fwd", "bwd")}}
     out["hbm_roofline_end_to_end"] = {
         "algorithmic_bytes_per_projection": int(ALGO_BYTES_PER_PROJ),
         "achieved_GBs": round(value * ALGO_BYTES_PER_PROJ / 1e9, 3),

@@ -236,7 +236,7 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
 /* ---------------------------------------------------------------------------------------------
  * Plans: the batched path. A plan fixes the shapes (geometry, lattice, N, T) and the device
  * buffers below; it owns its workspace and replays the forward and the backward as HIP graphs
- * (captured on first use). Inputs are read at replay time, so the caller updates a batch by
+ * (captured on first use) or as direct launches (digs_plan_set_replay). Inputs are read at replay time, so the caller updates a batch by
  * writing new contents (views' angles and weights, parameters) into the same buffers.
  *
  * digs_plan_create: tuning != NULL fixes the launch tuning; tuning == NULL runs the autotuner,
@@ -259,12 +259,25 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
  * happened in any call since the last check it grows the workspace to hold the largest need of
  * those calls (max_instances; the capacity never shrinks), sets *resized = 1, and the caller must
  * repeat the calls made since the last check.
+ * digs_plan_set_replay: how the plan re-issues each of its three launch sequences (forward,
+ * per-view forward, backward). DIGS_REPLAY_TIMED (the default): when a sequence is first called,
+ * its HIP-graph replay and direct launches of the same kernels on the stream are each timed three
+ * times (median, after one untimed run, on the plan's own stream, ordered after the work queued on
+ * `stream` and before what follows on it; the timing runs compute what the call computes) and
+ * the faster is kept. DIGS_REPLAY_GRAPH and DIGS_REPLAY_DIRECT fix the choice. Both give the
+ * same bits. Synchronises the plan's stream and drops the recorded graphs (each sequence is
+ * recorded, and timed, again at its next call); the workspace keeps its contents.
+ * digs_plan_get_replay: modes[0..2] = the choice for the forward, the per-view forward and the
+ * backward (DIGS_REPLAY_GRAPH or DIGS_REPLAY_DIRECT; 0 while the sequence has not been called).
  * digs_plan_get_tuning: the tuning in use and, if tune_ms != NULL, the autotuner's timings
  * tune_ms[c][0] (forward) and tune_ms[c][1] (backward) in ms per candidate c: tile shape c / 4
  * (16x16, 32x8, 8x8; zeros for a shape not tried), launch shape c % 4 (waves 4, 4, 1, 1 x
  * persistent 0, 1, 0, 1).
  * Errors: DIGS_EINVAL, DIGS_ENOMEM, DIGS_EHIP. */
 #define DIGS_TUNE_CANDIDATES 12
+#define DIGS_REPLAY_TIMED 0
+#define DIGS_REPLAY_GRAPH 1
+#define DIGS_REPLAY_DIRECT 2
 
 typedef struct digs_plan digs_plan;
 
@@ -282,6 +295,8 @@ int digs_plan_fwd(digs_plan *plan, void *stream);
 int digs_plan_fwd_views(digs_plan *plan, void *stream);
 int digs_plan_bwd(digs_plan *plan, void *stream);
 int digs_plan_check(digs_plan *plan, digs_diag *out, int *resized, void *stream);
+int digs_plan_set_replay(digs_plan *plan, int mode);
+int digs_plan_get_replay(const digs_plan *plan, int *modes);
 int digs_plan_get_tuning(const digs_plan *plan, digs_tuning *out, float *tune_ms);
 int digs_plan_destroy(digs_plan *plan);
 

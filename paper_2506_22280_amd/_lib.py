@@ -81,6 +81,7 @@ class PlanBuffers(ctypes.Structure):
 
 
 TUNE_CANDIDATES = 12   # 3 tile shapes x 4 launch shapes
+REPLAY_MODES = {"timed": 0, "graph": 1, "direct": 2}   # digs_plan_set_replay
 _VP = ctypes.c_void_p
 _lib = None
 
@@ -134,6 +135,8 @@ _SIGS = {
     "digs_plan_check": (ctypes.c_int, [_VP, ctypes.POINTER(Diag), ctypes.POINTER(ctypes.c_int),
                                        _VP]),
     "digs_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning), _VP]),
+    "digs_plan_set_replay": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "digs_plan_get_replay": (ctypes.c_int, [_VP, _VP]),
     "digs_plan_destroy": (ctypes.c_int, [_VP]),
     "digs_dvf_grid": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.POINTER(VGrid), _VP,
                                      _VP]),
@@ -562,12 +565,13 @@ def count_pairs(geom: dict, grid: dict, n: int, T: int, ws: Workspace,
 
 class Plan:
     """The batched path (digs_plan_*): fixed shapes and buffers, its own workspace, the forward
-    and backward replayed as HIP graphs. ``buffers`` maps the digs_plan_buffers names to device
-    tensors; the plan keeps references to them, and a new batch is given by writing into them.
-    tuning=None runs the library's autotuner on the buffers' current contents."""
+    and backward replayed as HIP graphs or direct launches (``replay``: "timed", the faster of the
+    two per sequence, or "graph" or "direct"). ``buffers`` maps the digs_plan_buffers names to
+    device tensors; the plan keeps references to them, and a new batch is given by writing into
+    them. tuning=None runs the library's autotuner on the buffers' current contents."""
 
     def __init__(self, geom: dict, grid: dict, n: int, T: int, buffers: dict,
-                 tuning: dict | None = None):
+                 tuning: dict | None = None, replay: str = "timed"):
         self.buffers = dict(buffers)
         R, nv, nu = grid["R"], geom["nv"], geom["nu"]
         expect = dict(coef=_lattice(grid), mu=(3, n), scale=(3, n), quat=(4, n), rho=(n,),
@@ -586,6 +590,8 @@ class Plan:
         _check("digs_plan_create", load().digs_plan_create(
             ctypes.byref(G), ctypes.byref(R), n, T, _byref(Tu), ctypes.byref(B), ctypes.byref(h)))
         self._h = h
+        if replay != "timed":
+            self.set_replay(replay)
 
     def fwd(self, stream=None):
         _check("digs_plan_fwd", load().digs_plan_fwd(self._h, _stream(stream)))
@@ -605,6 +611,20 @@ class Plan:
         _check("digs_plan_check", load().digs_plan_check(self._h, ctypes.byref(d),
                                                          ctypes.byref(r), _stream(stream)))
         return d.as_dict(), bool(r.value)
+
+    def set_replay(self, mode: str):
+        """"timed", "graph" or "direct" (digs_plan_set_replay)."""
+        if mode not in REPLAY_MODES:
+            raise ValueError("replay mode %r: one of %s" % (mode, sorted(REPLAY_MODES)))
+        _check("digs_plan_set_replay", load().digs_plan_set_replay(self._h, REPLAY_MODES[mode]))
+
+    def replay_modes(self):
+        """{"fwd", "fwd_views", "bwd"} -> "graph", "direct" or None (not called yet)."""
+        m = (ctypes.c_int * 3)()
+        _check("digs_plan_get_replay", load().digs_plan_get_replay(
+            self._h, ctypes.cast(m, ctypes.c_void_p)))
+        names = {0: None, 1: "graph", 2: "direct"}
+        return {k: names[m[i]] for i, k in enumerate(("fwd", "fwd_views", "bwd"))}
 
     def tuning(self):
         """(tuning dict, autotuner timings [candidate][fwd ms, bwd ms])."""

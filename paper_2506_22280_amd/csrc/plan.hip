@@ -1,7 +1,10 @@
 // plan.hip -- a prepared renderer for fixed shapes and fixed device buffers (the batched path):
 // it owns its workspace, holds the launch tuning (given by the caller, or chosen by timing the
 // candidate launch shapes on the caller's data), and captures the forward and the backward launch
-// sequences once each as HIP graphs that later calls replay.
+// sequences once each as HIP graphs that later calls replay. When a sequence is first called the
+// plan times its graph replay against launching the same kernels directly on the stream and keeps
+// the faster (a graph replay costs a few microseconds more than direct launches for short
+// sequences such as one view's forward); both give the same bits.
 //
 // The graphs hold kernel nodes only (every clear in the sequence is a fill kernel), so replays
 // are self-contained. An instance-capacity overflow is detected by digs_plan_check, which then
@@ -25,6 +28,9 @@ struct digs_plan {
     hipGraph_t gf = nullptr, gb = nullptr, gv = nullptr;
     hipGraphExec_t ef = nullptr, eb = nullptr, ev = nullptr;
     bool canonical = false;   // the workspace holds the per-Gaussian stage of the buffers' Gaussians
+    int replay = DIGS_REPLAY_TIMED;
+    int chosen[3] = {0, 0, 0};   // per sequence (0 forward, 1 backward, 2 per-view forward):
+                                 // DIGS_REPLAY_GRAPH or _DIRECT, 0 before its first call
     float tune_ms[DIGS_TUNE_CANDIDATES][2];
 };
 
@@ -40,6 +46,7 @@ static void drop_graphs(digs_plan *p)
     if (p->gv) (void)hipGraphDestroy(p->gv);
     p->ef = p->eb = p->ev = nullptr;
     p->gf = p->gb = p->gv = nullptr;
+    p->chosen[0] = p->chosen[1] = p->chosen[2] = 0;
     p->canonical = false;
 }
 
@@ -105,16 +112,12 @@ static int capture(digs_plan *p, int which)
         (void)hipGraphDestroy(g);
         return digs_set_hip_error(e);
     }
-    if (which == 0) {
-        p->gf = g;
-        p->ef = x;
-    } else if (which == 2) {
-        p->gv = g;
-        p->ev = x;
-    } else {
-        p->gb = g;
-        p->eb = x;
-    }
+    hipGraph_t &gs = which == 0 ? p->gf : which == 2 ? p->gv : p->gb;
+    hipGraphExec_t &xs = which == 0 ? p->ef : which == 2 ? p->ev : p->eb;
+    if (xs) (void)hipGraphExecDestroy(xs);   // (one recorded earlier whose timing failed)
+    if (gs) (void)hipGraphDestroy(gs);
+    gs = g;
+    xs = x;
     return DIGS_OK;
 }
 
@@ -279,29 +282,97 @@ extern "C" int digs_plan_create(const digs_geom *geom, const digs_grid *grid, in
     return DIGS_OK;
 }
 
-// The caller's stream waits for everything the plan's own stream has queued before a replay.
-static int order_after_plan_stream(digs_plan *p, hipStream_t s)
+// One stream waits for everything another has queued so far.
+static int order_after(hipStream_t waiter, hipStream_t s)
 {
     hipEvent_t ev;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
         return digs_set_hip_error(hipGetLastError());
-    hipError_t e = hipEventRecord(ev, p->cap);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    hipError_t e = hipEventRecord(ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(waiter, ev, 0);
     (void)hipEventDestroy(ev);
     return hip_rc(e);
+}
+
+static int run_direct(digs_plan *p, int which, hipStream_t s)
+{
+    return which == 0 ? run_fwd(p, s) : which == 2 ? run_fwd(p, s, true) : run_bwd(p, s);
+}
+
+static hipGraphExec_t graph_of(const digs_plan *p, int which)
+{
+    return which == 0 ? p->ef : which == 2 ? p->ev : p->eb;
+}
+
+// Median of three timed runs of sequence `which` on the plan's stream, after one untimed run;
+// graph: as a replay, else as direct launches.
+static int time_sequence(digs_plan *p, int which, bool graph, float *ms)
+{
+    hipEvent_t e[4];
+    for (int k = 0; k < 4; ++k)
+        if (hipEventCreate(&e[k]) != hipSuccess) {
+            for (int j = 0; j < k; ++j) (void)hipEventDestroy(e[j]);
+            return digs_set_hip_error(hipGetLastError());
+        }
+    int rc = DIGS_OK;
+    for (int k = 0; k < 4 && rc == DIGS_OK; ++k) {
+        rc = graph ? hip_rc(hipGraphLaunch(graph_of(p, which), p->cap))
+                   : run_direct(p, which, p->cap);
+        if (rc == DIGS_OK) rc = hip_rc(hipEventRecord(e[k], p->cap));
+    }
+    if (rc == DIGS_OK) rc = hip_rc(hipEventSynchronize(e[3]));
+    float t[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < 3 && rc == DIGS_OK; ++k)
+        rc = hip_rc(hipEventElapsedTime(&t[k], e[k], e[k + 1]));
+    for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return rc;
+}
+
+// Before the first call of sequence `which` (or the first after the graphs were dropped): record
+// its graph unless the replay is fixed to direct launches, and under DIGS_REPLAY_TIMED time the
+// replay against direct launches on the plan's stream (after the work queued on `s`; `s` then
+// waits for the timing runs, which compute what the call itself computes) and keep the faster.
+static int prepare_sequence(digs_plan *p, int which, hipStream_t s)
+{
+    if (p->chosen[which] != 0) return DIGS_OK;
+    if (p->replay == DIGS_REPLAY_DIRECT) {
+        p->chosen[which] = DIGS_REPLAY_DIRECT;
+        return DIGS_OK;
+    }
+    int rc = capture(p, which);
+    if (rc != DIGS_OK) return rc;
+    if (p->replay == DIGS_REPLAY_GRAPH) {
+        p->chosen[which] = DIGS_REPLAY_GRAPH;
+        return order_after(s, p->cap);
+    }
+    const int prof = digs_profile_enable(-1);
+    digs_profile_enable(0);
+    float tg = 0.0f, td = 0.0f;
+    rc = order_after(p->cap, s);
+    if (rc == DIGS_OK) rc = time_sequence(p, which, true, &tg);
+    if (rc == DIGS_OK) rc = time_sequence(p, which, false, &td);
+    digs_profile_enable(prof);
+    if (rc == DIGS_OK) rc = order_after(s, p->cap);
+    if (rc != DIGS_OK) return rc;
+    p->chosen[which] = tg <= td ? DIGS_REPLAY_GRAPH : DIGS_REPLAY_DIRECT;
+    return DIGS_OK;
+}
+
+static int launch_sequence(digs_plan *p, int which, hipStream_t s)
+{
+    const int rc = prepare_sequence(p, which, s);
+    if (rc != DIGS_OK) return rc;
+    return p->chosen[which] == DIGS_REPLAY_DIRECT ? run_direct(p, which, s)
+                                                  : hip_rc(hipGraphLaunch(graph_of(p, which), s));
 }
 
 extern "C" int digs_plan_fwd(digs_plan *p, void *stream)
 {
     if (!p) return DIGS_EINVAL;
     if (p->T == 0) return DIGS_OK;
-    hipStream_t s = (hipStream_t)stream;
-    if (!p->ef) {
-        int rc = capture(p, 0);
-        if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
-        if (rc != DIGS_OK) return rc;
-    }
-    const int rc = hip_rc(hipGraphLaunch(p->ef, s));
+    const int rc = launch_sequence(p, 0, (hipStream_t)stream);
     if (rc == DIGS_OK) p->canonical = true;
     return rc;
 }
@@ -311,13 +382,7 @@ extern "C" int digs_plan_fwd_views(digs_plan *p, void *stream)
     if (!p) return DIGS_EINVAL;
     if (p->T == 0) return DIGS_OK;
     if (!p->canonical) return DIGS_EINVAL;   // no digs_plan_fwd on this workspace yet
-    hipStream_t s = (hipStream_t)stream;
-    if (!p->ev) {
-        int rc = capture(p, 2);
-        if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
-        if (rc != DIGS_OK) return rc;
-    }
-    return hip_rc(hipGraphLaunch(p->ev, s));
+    return launch_sequence(p, 2, (hipStream_t)stream);
 }
 
 extern "C" int digs_plan_bwd(digs_plan *p, void *stream)
@@ -325,13 +390,28 @@ extern "C" int digs_plan_bwd(digs_plan *p, void *stream)
     if (!p) return DIGS_EINVAL;
     if (p->T == 0 && p->n == 0) return DIGS_OK;
     if (!p->b.grad_proj && p->n > 0 && p->T > 0) return DIGS_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    if (!p->eb) {
-        int rc = capture(p, 1);
-        if (rc == DIGS_OK) rc = order_after_plan_stream(p, s);
-        if (rc != DIGS_OK) return rc;
-    }
-    return hip_rc(hipGraphLaunch(p->eb, s));
+    return launch_sequence(p, 1, (hipStream_t)stream);
+}
+
+extern "C" int digs_plan_set_replay(digs_plan *p, int mode)
+{
+    if (!p || mode < DIGS_REPLAY_TIMED || mode > DIGS_REPLAY_DIRECT) return DIGS_EINVAL;
+    const int rc = hip_rc(hipStreamSynchronize(p->cap));
+    if (rc != DIGS_OK) return rc;
+    const bool canonical = p->canonical;   // the workspace keeps its contents
+    drop_graphs(p);
+    p->canonical = canonical;
+    p->replay = mode;
+    return DIGS_OK;
+}
+
+extern "C" int digs_plan_get_replay(const digs_plan *p, int *modes)
+{
+    if (!p || !modes) return DIGS_EINVAL;
+    modes[0] = p->chosen[0];
+    modes[1] = p->chosen[2];
+    modes[2] = p->chosen[1];
+    return DIGS_OK;
 }
 
 extern "C" int digs_plan_check(digs_plan *p, digs_diag *out, int *resized, void *stream)

@@ -1,6 +1,6 @@
-"""The batched path (digs_plan_*): graph replays equal the eager calls bit for bit, also after
-eager work and synchronisations between replays and after new inputs are written into the plan's
-buffers; every autotuner candidate gives the same bits; an instance-capacity overflow is
+"""The batched path (digs_plan_*): replays (HIP graphs, direct launches, or the faster of the
+two) equal the eager calls bit for bit, also after eager work and synchronisations between
+replays and after new inputs are written into the plan's buffers; every autotuner candidate gives the same bits; an instance-capacity overflow is
 detected, the plan grows and the repeated call is complete."""
 import numpy as np
 import pytest
@@ -44,13 +44,15 @@ def _eager(p, b, tuning=None):
 _GRADS = ("g_mu", "g_scale", "g_quat", "g_rho", "g_coef", "g_w")
 
 
-@pytest.mark.parametrize("nviews", [8, 6])
-def test_plan_replays_equal_eager(nviews):
-    _print("case: plan (autotuned) replays vs eager, small phantom, %d views" % nviews)
+@pytest.mark.parametrize("nviews,replay", [(8, "timed"), (6, "timed"), (8, "graph"),
+                                           (8, "direct")])
+def test_plan_replays_equal_eager(nviews, replay):
+    _print("case: plan (autotuned) replays (%s) vs eager, small phantom, %d views"
+           % (replay, nviews))
     p = synth.small_phantom(n=2048, nviews=nviews, seed=4)
     idx = np.arange(nviews)
     b = _buffers(p, idx)
-    with _lib.Plan(p.geom, p.grid, p.n, nviews, b) as plan:
+    with _lib.Plan(p.geom, p.grid, p.n, nviews, b, replay=replay) as plan:
         tuning, ms = plan.tuning()
         _print("chosen", tuning, "timings", ms)
         assert tuning["capacity"] > 0
@@ -84,6 +86,13 @@ def test_plan_replays_equal_eager(nviews):
         assert torch.equal(got, ref2_proj)
         for k in _GRADS:
             assert torch.equal(gg[k], ref2_g[k]), k
+        modes = plan.replay_modes()
+        _print("replay", modes)
+        assert modes["fwd_views"] is None
+        if replay == "timed":
+            assert modes["fwd"] in ("graph", "direct") and modes["bwd"] in ("graph", "direct")
+        else:
+            assert modes["fwd"] == replay and modes["bwd"] == replay
 
 
 def test_every_tuning_candidate_gives_the_same_bits():
@@ -183,12 +192,13 @@ def test_new_workspace_diagnostics_start_clear():
     assert d["behind_source"] == 0 and d["wide"] == 0 and d["max_instances"] == d["instances"]
 
 
-def test_plan_views_only_forward_equals_full_forward():
-    _print("case: plan forward of the per-view stages only, after new views are written; the "
-           "backward after it; equal to eager calls with the plan's tuning")
+@pytest.mark.parametrize("replay", ["timed", "graph", "direct"])
+def test_plan_views_only_forward_equals_full_forward(replay):
+    _print("case: plan forward of the per-view stages only (%s), after new views are written; "
+           "the backward after it; equal to eager calls with the plan's tuning" % replay)
     p = synth.small_phantom(n=2048, nviews=8, seed=10)
     b = _buffers(p, np.arange(4))
-    with _lib.Plan(p.geom, p.grid, p.n, 4, b) as plan:
+    with _lib.Plan(p.geom, p.grid, p.n, 4, b, replay=replay) as plan:
         with pytest.raises(_lib.DigsError):
             plan.fwd_views()          # no per-Gaussian stage yet
         plan.fwd()
@@ -207,3 +217,15 @@ def test_plan_views_only_forward_equals_full_forward():
             assert torch.equal(got, ref_proj), first
             for k in _GRADS:
                 assert torch.equal(gg[k], ref_g[k]), (first, k)
+        modes = plan.replay_modes()
+        _print("replay", modes)
+        if replay != "timed":
+            assert modes["fwd_views"] == replay
+        # another replay mode keeps the per-Gaussian stage: the per-view forward stays valid
+        other = "direct" if modes["fwd_views"] == "graph" else "graph"
+        plan.set_replay(other)
+        b["proj"].fill_(-1.0)
+        plan.fwd_views()
+        torch.cuda.synchronize()
+        assert torch.equal(b["proj"], ref_proj)
+        assert plan.replay_modes()["fwd_views"] == other
