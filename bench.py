@@ -61,9 +61,9 @@ ALGO_BYTES_PER_STEP = ALGO_BYTES_PER_PROJ * 64   # 129.7 MB per 64-view fwd+bwd 
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while their code (comments aside) is unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2218529.3 * (524288.0 / 262166.875) * 1024,
-           "write_bytes": 6628097.8 * 1.000 * 1024,
-           "sources_sha256": "cda986888cd8ff6f42e82eef48cf2ee939ee25021176173171dbbd56e6baa2dd"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2225268.7 * (524288.0 / 262167.625) * 1024,
+           "write_bytes": 6623091.2 * 1.000 * 1024,
+           "sources_sha256": "82c75eedf4471a2a486f487f259ef050b998010e9c9084803a1ff50513c78f0e"}
 
 
 def sources_digest() -> str:
