@@ -265,8 +265,8 @@ int digs_project_basis_bwd(const digs_geom *geom, const digs_grid *grid, const f
  * times (median, after one untimed run, on the plan's own stream, ordered after the work queued on
  * `stream` and before what follows on it; the timing runs compute what the call computes) and
  * the faster is kept. DIGS_REPLAY_GRAPH and DIGS_REPLAY_DIRECT fix the choice. Both give the
- * same bits. Synchronises the plan's stream and drops the recorded graphs (each sequence is
- * recorded, and timed, again at its next call); the workspace keeps its contents.
+ * same bits. Synchronises the device and drops the recorded graphs (each sequence is recorded,
+ * and timed, again at its next call); the workspace keeps its contents.
  * digs_plan_get_replay: modes[0..2] = the choice for the forward, the per-view forward and the
  * backward (DIGS_REPLAY_GRAPH or DIGS_REPLAY_DIRECT; 0 while the sequence has not been called).
  * digs_plan_get_tuning: the tuning in use and, if tune_ms != NULL, the autotuner's timings

@@ -396,7 +396,9 @@ extern "C" int digs_plan_bwd(digs_plan *p, void *stream)
 extern "C" int digs_plan_set_replay(digs_plan *p, int mode)
 {
     if (!p || mode < DIGS_REPLAY_TIMED || mode > DIGS_REPLAY_DIRECT) return DIGS_EINVAL;
-    const int rc = hip_rc(hipStreamSynchronize(p->cap));
+    // (replays may still be running on the callers' streams: the device is synchronised before
+    // their graphs are destroyed)
+    const int rc = hip_rc(hipDeviceSynchronize());
     if (rc != DIGS_OK) return rc;
     const bool canonical = p->canonical;   // the workspace keeps its contents
     drop_graphs(p);
