@@ -63,6 +63,12 @@ def test_host_side_validation_and_sizes():
                               1, None, None, None, None, 0, None, None)
     assert rc == -1
     assert lib.digs_strerror(-2) == b"workspace missing, misaligned or too small"
+    # plan calls without a plan, or with a replay mode that does not exist
+    assert lib.digs_plan_set_replay(None, 0) == -1
+    assert lib.digs_plan_get_replay(None, None) == -1
+    assert lib.digs_plan_fwd(None, None) == -1 and lib.digs_plan_bwd(None, None) == -1
+    with pytest.raises(ValueError):
+        _lib.Plan.set_replay(object(), "sometimes")
     # a too-small workspace is rejected
     t = _lib.Tuning()
     t.capacity = 1000
