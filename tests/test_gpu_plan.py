@@ -229,3 +229,30 @@ def test_plan_views_only_forward_equals_full_forward(replay):
         torch.cuda.synchronize()
         assert torch.equal(b["proj"], ref_proj)
         assert plan.replay_modes()["fwd_views"] == other
+
+
+def test_plan_first_calls_on_a_side_stream_are_ordered():
+    _print("case: first (timed) plan calls on a side stream, inputs written on that stream just "
+           "before; equal to the eager calls")
+    p = synth.small_phantom(n=2048, nviews=8, seed=12)
+    b = _buffers(p, np.arange(4))
+    with _lib.Plan(p.geom, p.grid, p.n, 4, b) as plan:
+        shape = {k: v for k, v in plan.tuning()[0].items() if k != "cull_radius"}
+        a2, w2 = p.views(np.arange(4, 8))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            # the new views reach the buffers on the side stream only; the plan's first calls
+            # (which time both replay modes on the plan's own stream) must see them
+            b["angles"].copy_(dev(a2), non_blocking=True)
+            b["w"].copy_(dev(w2), non_blocking=True)
+            b["proj"].fill_(-1.0)
+            plan.fwd(stream=side)
+            plan.bwd(stream=side)
+            got = b["proj"].clone()
+            gg = {k: b[k].clone() for k in _GRADS}
+        side.synchronize()
+        ref_proj, ref_g = _eager(p, b, tuning=shape)
+        assert torch.equal(got, ref_proj)
+        for k in _GRADS:
+            assert torch.equal(gg[k], ref_g[k]), k
