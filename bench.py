@@ -61,9 +61,9 @@ ALGO_BYTES_PER_STEP = ALGO_BYTES_PER_PROJ * 64   # 129.7 MB per 64-view fwd+bwd 
 # bench (FETCH_SIZE, then WRITE_SIZE, mean KiB per dispatch, scaled by what the same counters read
 # for a 512 MiB device copy: x2.0 and x1.0; profiles/batched_200k_hbm_counters.md), taken on the
 # library sources whose digest is given; reported only while their code (comments aside) is unchanged
-TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2218992.5 * (524288.0 / 262166.5625) * 1024,
-           "write_bytes": 6624920.7 * 1.000 * 1024,
-           "sources_sha256": "fdc8175348b9569f40c10afa22031d28019f35f0f9368c6373d9757cb94122e7"}
+TRAFFIC = {"kernel": "k_splat_bwd", "read_bytes": 2219897.6 * (524288.0 / 262166.5625) * 1024,
+           "write_bytes": 6624472.5 * 1.000 * 1024,
+           "sources_sha256": "cae9094998698b08728fd85aeb2bfaded4df50dc64d9a9cf70e53e5c95fb4d58"}
 
 
 def sources_digest() -> str:

@@ -342,7 +342,9 @@ struct FootEll {
     {
         const float lo = fmaxf(ya - cy, -ry), hi = fminf(yb - cy, ry);
         if (!(lo <= hi)) return false;
-        const float dl = fminf(fmaxf(ryl, lo), hi), dr = fminf(fmaxf(-ryl, lo), hi);
+        // (ryl clamped to [lo, hi]: the median of the three, one instruction)
+        const float dl = __builtin_amdgcn_fmed3f(ryl, lo, hi);
+        const float dr = __builtin_amdgcn_fmed3f(-ryl, lo, hi);
         L = cx - s * dl - __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dl, dl, 1.00001f)) * ia);
         R = cx - s * dr + __builtin_amdgcn_sqrtf(fmaxf(0.0f, fmaf(-D * dr, dr, 1.00001f)) * ia);
         return true;
